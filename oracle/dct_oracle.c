@@ -1,0 +1,500 @@
+/*
+ * Plain FP64 CPU oracle for the discrete-ordinates CT dose method of
+ * Norris & Liu, "Photon Fluence and Dose Estimation in Computed Tomography
+ * using a Discrete Ordinates Boltzmann Solver" (arXiv:1811.12391).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the HIP library is checked against.  Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg may load it; the product
+ * path never does.  It shares no code, header or table with the HIP library.
+ *
+ * What it computes (paper section in brackets):
+ *   - uncollided fluence by ray tracing from a collimated isotropic point
+ *     source, phi_u = w_g exp(-tau_g) / (4 pi r^2) [Sec. II-A, first-collision
+ *     source paragraph; Sec. II-B source types];
+ *   - the first-collision source built from phi_u, in Legendre/real spherical
+ *     harmonic moments [Sec. II-A, eq. 2 and the first-collision paragraph];
+ *   - per-group source iteration with downscatter on the discrete-ordinates
+ *     equation, eq. (2), vacuum boundaries [Sec. II-A];
+ *   - diamond-difference sweeps over voxels with a set-to-zero fixup;
+ *   - scalar fluence by quadrature, eq. (3), and the collision-kerma dose
+ *     tally dose = sum_g kappa_g (phi_u,g + phi_c,g) [Sec. II-A].
+ *
+ * Readings taken where the paper is silent (spatial scheme, iteration scheme,
+ * weight placement in eq. 2, beam window, stopping rule) follow the method
+ * description: diamond difference; group Gauss-Seidel from the highest group
+ * with source iteration started from zero; the quadrature weight belongs to
+ * the incoming direction; a rectangular window in azimuth and elevation with
+ * full angles fan x cone, edges inclusive; stop when the relative max-norm
+ * change of the scalar flux is <= tol.
+ *
+ * Index conventions: voxel v = i + nx*(j + ny*k); group g = 0 highest energy;
+ * moment index lm = l*l + l + m for m = -l..l; arrays are C-order with the
+ * voxel index innermost.
+ *
+ * Parity: every function below is pinned by the CPU test suite against closed
+ * forms, hand values, brute force or invariants, except the phantom
+ * generator, the fixup pattern and the stopping point, which have no external
+ * values ("parity unpinned" beyond oracle <-> GPU self-consistency).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics, Schmidt semi-normalised, no Condon-Shortley      */
+/* phase, polar axis z: Y_00 = 1 and sum_m Y_lm(a) Y_lm(b) = P_l(a.b).       */
+/* Used for the Legendre scattering expansion of eq. (2).                     */
+/* ------------------------------------------------------------------------ */
+int orc_real_sh(int L, double ox, double oy, double oz, double *Y)
+{
+    if (L < 0 || L > 16) return -1;
+    double P[17][17];
+    double mu = oz;
+    double s = hypot(ox, oy);
+    double phi = atan2(oy, ox);
+    for (int m = 0; m <= L; ++m) {
+        double pmm = 1.0;
+        for (int t = 1; t <= m; ++t) pmm *= (2.0 * t - 1.0) * s;   /* (2m-1)!! s^m */
+        P[m][m] = pmm;
+        if (m + 1 <= L) P[m + 1][m] = (2.0 * m + 1.0) * mu * pmm;
+        for (int l = m + 2; l <= L; ++l)
+            P[l][m] = ((2.0 * l - 1.0) * mu * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (l - m);
+    }
+    for (int l = 0; l <= L; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double ratio = 1.0;                         /* (l-am)! / (l+am)! */
+            for (int t = l - am + 1; t <= l + am; ++t) ratio /= (double)t;
+            double nrm = sqrt((am == 0 ? 1.0 : 2.0) * ratio);
+            double ang = (m >= 0) ? cos(am * phi) : sin(am * phi);
+            Y[l * l + l + m] = nrm * P[l][am] * ang;
+        }
+    }
+    return 0;
+}
+
+/* Moment <-> direction maps of the P_N expansion:
+ *   M[n][lm] = (2l+1)/(4 pi) Y_lm(Omega_n)  (moments -> angular source)
+ *   D[lm][n] = w_n Y_lm(Omega_n)            (angular flux -> moments; row 0 is eq. 3) */
+int orc_moment_maps(int L, int N, const double *dirs, const double *w, double *Mmap, double *Dmap)
+{
+    int Nm = (L + 1) * (L + 1);
+    double Y[289];
+    for (int n = 0; n < N; ++n) {
+        if (orc_real_sh(L, dirs[3 * n], dirs[3 * n + 1], dirs[3 * n + 2], Y)) return -1;
+        for (int l = 0; l <= L; ++l)
+            for (int m = -l; m <= l; ++m) {
+                int lm = l * l + l + m;
+                if (Mmap) Mmap[(size_t)n * Nm + lm] = (2.0 * l + 1.0) / (4.0 * ORC_PI) * Y[lm];
+                if (Dmap) Dmap[(size_t)lm * N + n] = w[n] * Y[lm];
+            }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Siddon ray trace: the segment p -> x (x a voxel centre) is cut at every    */
+/* x, y and z grid plane strictly between the box entry and x.  Each segment  */
+/* gets length (a_m - a_{m-1}) r and the voxel holding its midpoint.          */
+/* ------------------------------------------------------------------------ */
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_siddon(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+               const double *p, const double *x, int maxseg, int *vox, double *len)
+{
+    int n[3] = {nx, ny, nz};
+    double del[3] = {dx, dy, dz};
+    double d[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double a_in = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) continue;
+        double lo = org[a], hi = org[a] + n[a] * del[a];
+        double t0 = (lo - p[a]) / d[a], t1 = (hi - p[a]) / d[a];
+        double tmin = t0 < t1 ? t0 : t1;
+        if (tmin > a_in) a_in = tmin;
+    }
+    int cap = nx + ny + nz + 3;
+    double *al = (double *)malloc(sizeof(double) * (cap + 2));
+    int na = 0;
+    al[na++] = a_in;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) continue;
+        for (int m = 0; m <= n[a]; ++m) {
+            double t = (org[a] + m * del[a] - p[a]) / d[a];
+            if (t > a_in && t < 1.0) al[na++] = t;
+        }
+    }
+    al[na++] = 1.0;
+    qsort(al + 1, na - 2, sizeof(double), cmp_double);
+    int ns = 0;
+    for (int s = 1; s < na; ++s) {
+        if (ns >= maxseg) { free(al); return -1; }
+        double a0 = al[s - 1], a1 = al[s];
+        double mid = 0.5 * (a0 + a1);
+        int idx[3];
+        for (int a = 0; a < 3; ++a) {
+            int t = (int)floor((p[a] + mid * d[a] - org[a]) / del[a]);
+            if (t < 0) t = 0;
+            if (t > n[a] - 1) t = n[a] - 1;
+            idx[a] = t;
+        }
+        vox[ns] = idx[0] + nx * (idx[1] + ny * idx[2]);
+        len[ns] = (a1 - a0) * r;
+        ++ns;
+    }
+    free(al);
+    return ns;
+}
+
+/* Beam window of a collimated point source: azimuth in the plane normal to z,
+ * measured from the beam axis projected on that plane, and elevation from
+ * that plane; full angles fan x cone, edges inclusive. */
+static int in_beam(const double *d, const double *axis, double fan_deg, double cone_deg)
+{
+    double ax = axis[0], ay = axis[1];
+    double an = hypot(ax, ay);
+    ax /= an;
+    ay /= an;
+    double ex = -ay, ey = ax;                         /* z x a */
+    double along = d[0] * ax + d[1] * ay;
+    double across = d[0] * ex + d[1] * ey;
+    double az = atan2(across, along);
+    double el = atan2(d[2], hypot(d[0], d[1]));
+    double hf = fan_deg * ORC_PI / 360.0, hc = cone_deg * ORC_PI / 360.0;
+    return fabs(az) <= hf && fabs(el) <= hc;
+}
+
+/* Uncollided fluence phi_u[B][G][C]: no scatter term, so it follows from the
+ * optical depth along the straight ray from the source to each voxel centre
+ * (first-collision paragraph of Sec. II-A; "calculated analytically" in
+ * Sec. IV).  tau_g is summed in ray order, source to target. */
+int orc_uncollided(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+                   const uint8_t *mat, const double *rho, int G, int M, const double *st,
+                   int B, const double *pos, const double *axis, double fan_deg, double cone_deg,
+                   const double *gw, int nthreads, double *phi_u)
+{
+    size_t C = (size_t)nx * ny * nz;
+    int cap = nx + ny + nz + 4;
+    (void)M;
+    for (int b = 0; b < B; ++b) {
+        const double *p = pos + 3 * b;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+        for (long v = 0; v < (long)C; ++v) {
+            int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((size_t)nx * ny));
+            double x[3] = {org[0] + (i + 0.5) * dx, org[1] + (j + 0.5) * dy, org[2] + (k + 0.5) * dz};
+            double d[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!in_beam(d, axis + 3 * b, fan_deg, cone_deg)) {
+                for (int g = 0; g < G; ++g) phi_u[((size_t)b * G + g) * C + v] = 0.0;
+                continue;
+            }
+            int *vox = (int *)malloc(sizeof(int) * cap);
+            double *len = (double *)malloc(sizeof(double) * cap);
+            int ns = orc_siddon(nx, ny, nz, dx, dy, dz, org, p, x, cap, vox, len);
+            for (int g = 0; g < G; ++g) {
+                double tau = 0.0;
+                for (int s = 0; s < ns; ++s) {
+                    int u = vox[s];
+                    tau += len[s] * rho[u] * st[(size_t)mat[u] * G + g];
+                }
+                phi_u[((size_t)b * G + g) * C + v] = gw[g] * exp(-tau) / (4.0 * ORC_PI * r2);
+            }
+            free(vox);
+            free(len);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diamond difference for one voxel and one direction.                         */
+/* Cell balance of eq. (2) over a box with c_a = |Omega_a| / Delta_a:          */
+/*   sum_a c_a (out_a - in_a) + sigma psi_c = q,  out_a = 2 psi_c - in_a.       */
+/* Fixup: a negative outgoing face is set to zero and psi_c is recomputed from */
+/* the balance with that face removed, until no new negative face appears.     */
+/* Returns the number of fixed faces.                                          */
+/* ------------------------------------------------------------------------ */
+int orc_dd_cell(double q, double sig, const double *c, const double *pin, int fixup,
+                double *pc, double *pout)
+{
+    double num = q + 2.0 * (c[0] * pin[0] + c[1] * pin[1] + c[2] * pin[2]);
+    double den = sig + 2.0 * (c[0] + c[1] + c[2]);
+    double psi = num / den;
+    int fixed[3] = {0, 0, 0}, nf = 0;
+    for (int a = 0; a < 3; ++a) pout[a] = 2.0 * psi - pin[a];
+    if (fixup) {
+        for (int pass = 0; pass < 3; ++pass) {
+            int fresh = 0;
+            for (int a = 0; a < 3; ++a)
+                if (!fixed[a] && pout[a] < 0.0) { fixed[a] = 1; fresh = 1; ++nf; }
+            if (!fresh) break;
+            num = q;
+            den = sig;
+            for (int a = 0; a < 3; ++a) {
+                if (fixed[a]) num += c[a] * pin[a];
+                else { num += 2.0 * c[a] * pin[a]; den += 2.0 * c[a]; }
+            }
+            psi = num / den;
+            for (int a = 0; a < 3; ++a) pout[a] = fixed[a] ? 0.0 : 2.0 * psi - pin[a];
+        }
+    }
+    *pc = psi;
+    return nf;
+}
+
+/* One transport sweep for every direction: cells visited in upwind order
+ * (lexicographic in the octant's reflected coordinates), incoming boundary
+ * angular flux = inflow[n] (0 for vacuum).  psi[N][C] receives the cell-centre
+ * angular flux; leak[N][3] (optional) the sum of outgoing boundary face fluxes
+ * per axis.  Returns the total number of fixed faces. */
+long orc_sweep(int nx, int ny, int nz, double dx, double dy, double dz, const double *sigt,
+               int N, const double *dirs, const double *q, const double *inflow, int fixup,
+               int nthreads, double *psi, double *leak)
+{
+    size_t C = (size_t)nx * ny * nz;
+    long nfix = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(+ : nfix)
+    for (int n = 0; n < N; ++n) {
+        const double *om = dirs + 3 * n;
+        double c[3] = {fabs(om[0]) / dx, fabs(om[1]) / dy, fabs(om[2]) / dz};
+        double bc = inflow ? inflow[n] : 0.0;
+        double *fx = (double *)malloc(sizeof(double) * (size_t)ny * nz);
+        double *fy = (double *)malloc(sizeof(double) * (size_t)nx * nz);
+        double *fz = (double *)malloc(sizeof(double) * (size_t)nx * ny);
+        for (size_t t = 0; t < (size_t)ny * nz; ++t) fx[t] = bc;
+        for (size_t t = 0; t < (size_t)nx * nz; ++t) fy[t] = bc;
+        for (size_t t = 0; t < (size_t)nx * ny; ++t) fz[t] = bc;
+        double lx = 0.0, ly = 0.0, lz = 0.0;
+        const double *qn = q + (size_t)n * C;
+        double *pn = psi + (size_t)n * C;
+        for (int kk = 0; kk < nz; ++kk) {
+            int k = om[2] > 0 ? kk : nz - 1 - kk;
+            for (int jj = 0; jj < ny; ++jj) {
+                int j = om[1] > 0 ? jj : ny - 1 - jj;
+                for (int ii = 0; ii < nx; ++ii) {
+                    int i = om[0] > 0 ? ii : nx - 1 - ii;
+                    size_t v = (size_t)i + (size_t)nx * (j + (size_t)ny * k);
+                    double pin[3] = {fx[j + (size_t)ny * k], fy[i + (size_t)nx * k], fz[i + (size_t)nx * j]};
+                    double pc, pout[3];
+                    nfix += orc_dd_cell(qn[v], sigt[v], c, pin, fixup, &pc, pout);
+                    pn[v] = pc;
+                    fx[j + (size_t)ny * k] = pout[0];
+                    fy[i + (size_t)nx * k] = pout[1];
+                    fz[i + (size_t)nx * j] = pout[2];
+                    if (ii == nx - 1) lx += pout[0];
+                    if (jj == ny - 1) ly += pout[1];
+                    if (kk == nz - 1) lz += pout[2];
+                }
+            }
+        }
+        if (leak) {
+            leak[3 * n + 0] = lx;
+            leak[3 * n + 1] = ly;
+            leak[3 * n + 2] = lz;
+        }
+        free(fx);
+        free(fy);
+        free(fz);
+    }
+    return nfix;
+}
+
+/* First-collision source of one right-hand side: the uncollided flux at voxel
+ * v is a delta in angle along d/r (d = x_v - p), so its moments are
+ * phi_u Y_lm(d/r) and the once-scattered source has moments
+ *   ext[g][lm][v] = sum_{g' <= g} rho_v s_l^{g'->g}[m_v] phi_u,g'(v) Y_lm(d/r)
+ * (first-collision paragraph of Sec. II-A), summed in increasing g'.  An
+ * optional isotropic volumetric source S[g][v] (the S term of eq. 1) is added
+ * to the l = 0 moment afterwards. */
+int orc_first_collision(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+                        const uint8_t *mat, const double *rho, int G, int L, const double *ss,
+                        const double *p, const double *pu, const double *ext_iso, int nthreads,
+                        double *ext)
+{
+    size_t C = (size_t)nx * ny * nz;
+    int Nm = (L + 1) * (L + 1);
+    int lof[289];
+    for (int l = 0; l <= L; ++l)
+        for (int m = -l; m <= l; ++m) lof[l * l + l + m] = l;
+    memset(ext, 0, sizeof(double) * (size_t)G * Nm * C);
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (long v = 0; v < (long)C; ++v) {
+        int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((size_t)nx * ny));
+        double d[3] = {org[0] + (i + 0.5) * dx - p[0], org[1] + (j + 0.5) * dy - p[1],
+                       org[2] + (k + 0.5) * dz - p[2]};
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double Y[289];
+        orc_real_sh(L, d[0] / r, d[1] / r, d[2] / r, Y);
+        int m = mat[v];
+        for (int g = 0; g < G; ++g)
+            for (int gp = 0; gp <= g; ++gp) {
+                double fu = pu[(size_t)gp * C + v];
+                for (int lm = 0; lm < Nm; ++lm) {
+                    double s = ss[(((size_t)m * (L + 1) + lof[lm]) * G + gp) * G + g];
+                    ext[((size_t)g * Nm + lm) * C + v] += rho[v] * s * fu * Y[lm];
+                }
+            }
+        if (ext_iso)
+            for (int g = 0; g < G; ++g) ext[(size_t)g * Nm * C + v] += ext_iso[(size_t)g * C + v];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full solve: uncollided -> first-collision source -> per-group source        */
+/* iteration with downscatter -> dose.  Each right-hand side (source) b is      */
+/* solved on its own with its own stopping point.                               */
+/* ------------------------------------------------------------------------ */
+int orc_solve(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+              const uint8_t *mat, const double *rho,
+              int G, int M, int L, const double *st, const double *ss, const double *kap,
+              int N, const double *dirs, const double *w,
+              int B, const double *pos, const double *axis, double fan_deg, double cone_deg,
+              const double *gw, const double *ext_iso,
+              double tol, int max_iter, const int *fixed_iters, int fixup,
+              const double *test_inflow, int nthreads,
+              double *phi_u, double *phi, double *dose, int *iters, double *eps, double *bal,
+              long *nfix_out)
+{
+    size_t C = (size_t)nx * ny * nz;
+    int Nm = (L + 1) * (L + 1);
+    int lof[289];
+    for (int l = 0; l <= L; ++l)
+        for (int m = -l; m <= l; ++m) lof[l * l + l + m] = l;
+    double *Mmap = (double *)malloc(sizeof(double) * N * Nm);
+    double *Dmap = (double *)malloc(sizeof(double) * N * Nm);
+    orc_moment_maps(L, N, dirs, w, Mmap, Dmap);
+    double V = dx * dy * dz;
+    double Ax = dy * dz, Ay = dx * dz, Az = dx * dy;
+
+    orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg,
+                   cone_deg, gw, nthreads, phi_u);
+
+    double *ext = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
+    double *Q = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *q = (double *)malloc(sizeof(double) * (size_t)N * C);
+    double *ps = (double *)malloc(sizeof(double) * (size_t)N * C);
+    double *cur = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *nxt = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *sigt = (double *)malloc(sizeof(double) * C);
+    double *leak = (double *)malloc(sizeof(double) * 3 * N);
+    double *inflow = (double *)malloc(sizeof(double) * N);
+    if (!ext || !Q || !q || !ps || !cur || !nxt || !sigt || !leak || !inflow) return -4;
+    long nfix_total = 0;
+
+    for (int b = 0; b < B; ++b) {
+        const double *p = pos + 3 * b;
+        const double *pu = phi_u + (size_t)b * G * C;
+        orc_first_collision(nx, ny, nz, dx, dy, dz, org, mat, rho, G, L, ss, p, pu, ext_iso,
+                            nthreads, ext);
+
+        for (int g = 0; g < G; ++g) {
+            double bc = test_inflow ? test_inflow[g] : 0.0;
+            for (int n = 0; n < N; ++n) inflow[n] = bc;
+            for (size_t v = 0; v < C; ++v) sigt[v] = rho[v] * st[(size_t)mat[v] * G + g];
+            double *eg = ext + (size_t)g * Nm * C;
+            /* production: volumetric source plus boundary inflow */
+            double P = 0.0;
+            for (size_t v = 0; v < C; ++v) P += eg[v];
+            P *= V;
+            if (bc != 0.0)
+                for (int n = 0; n < N; ++n)
+                    P += bc * w[n] * (fabs(dirs[3 * n]) * Ax * ny * nz + fabs(dirs[3 * n + 1]) * Ay * nx * nz +
+                                      fabs(dirs[3 * n + 2]) * Az * nx * ny);
+            memset(cur, 0, sizeof(double) * (size_t)Nm * C);
+            int it = 0;
+            double e = 0.0;
+            for (;;) {
+                /* scattering source within the group plus the fixed source */
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+                for (long v = 0; v < (long)C; ++v) {
+                    int m = mat[v];
+                    for (int lm = 0; lm < Nm; ++lm) {
+                        double s = ss[(((size_t)m * (L + 1) + lof[lm]) * G + g) * G + g];
+                        Q[(size_t)lm * C + v] = eg[(size_t)lm * C + v] + rho[v] * s * cur[(size_t)lm * C + v];
+                    }
+                }
+                /* moments -> directions */
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+                for (long v = 0; v < (long)C; ++v)
+                    for (int n = 0; n < N; ++n) {
+                        double acc = 0.0;
+                        for (int lm = 0; lm < Nm; ++lm) acc += Mmap[(size_t)n * Nm + lm] * Q[(size_t)lm * C + v];
+                        q[(size_t)n * C + v] = acc;
+                    }
+                nfix_total += orc_sweep(nx, ny, nz, dx, dy, dz, sigt, N, dirs, q, inflow, fixup, nthreads, ps, leak);
+                /* directions -> moments (row 0 is the scalar flux, eq. 3) */
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+                for (long v = 0; v < (long)C; ++v)
+                    for (int lm = 0; lm < Nm; ++lm) {
+                        double acc = 0.0;
+                        for (int n = 0; n < N; ++n) acc += Dmap[(size_t)lm * N + n] * ps[(size_t)n * C + v];
+                        nxt[(size_t)lm * C + v] = acc;
+                    }
+                double dmax = 0.0, fmax = 0.0;
+                for (size_t v = 0; v < C; ++v) {
+                    double df = fabs(nxt[v] - cur[v]);
+                    double f = fabs(nxt[v]);
+                    if (df > dmax) dmax = df;
+                    if (f > fmax) fmax = f;
+                }
+                e = fmax > 0.0 ? dmax / fmax : 0.0;
+                double *t = cur; cur = nxt; nxt = t;
+                ++it;
+                if (fixed_iters) { if (it >= fixed_iters[g]) break; }
+                else if (e <= tol || it >= max_iter) break;
+            }
+            iters[b * G + g] = it;
+            eps[b * G + g] = e;
+            /* balance of the final sweep's group: production, removal, leakage */
+            double R = 0.0;
+            for (size_t v = 0; v < C; ++v) {
+                double s0 = rho[v] * ss[(((size_t)mat[v] * (L + 1) + 0) * G + g) * G + g];
+                R += (sigt[v] - s0) * cur[v];
+            }
+            R *= V;
+            double Lk = 0.0;
+            for (int n = 0; n < N; ++n)
+                Lk += w[n] * (fabs(dirs[3 * n]) * Ax * leak[3 * n] + fabs(dirs[3 * n + 1]) * Ay * leak[3 * n + 1] +
+                              fabs(dirs[3 * n + 2]) * Az * leak[3 * n + 2]);
+            bal[(b * G + g) * 3 + 0] = P;
+            bal[(b * G + g) * 3 + 1] = R;
+            bal[(b * G + g) * 3 + 2] = Lk;
+            /* downscatter into every lower-energy group */
+            for (int g2 = g + 1; g2 < G; ++g2) {
+                double *e2 = ext + (size_t)g2 * Nm * C;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+                for (long v = 0; v < (long)C; ++v) {
+                    int m = mat[v];
+                    for (int lm = 0; lm < Nm; ++lm) {
+                        double s = ss[(((size_t)m * (L + 1) + lof[lm]) * G + g) * G + g2];
+                        e2[(size_t)lm * C + v] += rho[v] * s * cur[(size_t)lm * C + v];
+                    }
+                }
+            }
+            memcpy(phi + ((size_t)b * G + g) * Nm * C, cur, sizeof(double) * (size_t)Nm * C);
+            /* dose: collision kerma of uncollided + collided scalar fluence */
+            for (size_t v = 0; v < C; ++v) {
+                double k0 = kap[(size_t)mat[v] * G + g];
+                if (g == 0) dose[(size_t)b * C + v] = 0.0;
+                dose[(size_t)b * C + v] += k0 * (pu[(size_t)g * C + v] + cur[v]);
+            }
+        }
+    }
+    if (nfix_out) *nfix_out = nfix_total;
+    free(Mmap); free(Dmap); free(ext); free(Q); free(q); free(ps); free(cur); free(nxt);
+    free(sigt); free(leak); free(inflow);
+    return 0;
+}

@@ -1,0 +1,452 @@
+"""Pins of the FP64 CPU oracle against things other than itself: closed forms,
+hand values, textbook/library routines, brute force on tiny inputs and
+invariants of the discretised equations.  Each test says what fixes it."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1811_12391_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_dirs(rng, n):
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+# ---------------------------------------------------------------- harmonics
+def test_sh_addition_theorem(oracle_mod):
+    """sum_m Y_lm(a) Y_lm(b) = P_l(a.b), P_l from numpy's Legendre series."""
+    rng = np.random.default_rng(1)
+    L = 6
+    for _ in range(50):
+        a, b = _rand_dirs(rng, 2)
+        Ya, Yb = oracle_mod.real_sh(L, a), oracle_mod.real_sh(L, b)
+        for l in range(L + 1):
+            s = sum(Ya[l * l + l + m] * Yb[l * l + l + m] for m in range(-l, l + 1))
+            ref = np.polynomial.legendre.legval(a @ b, [0] * l + [1])
+            assert abs(s - ref) < 1e-13
+
+
+def test_sh_low_order_closed_forms(oracle_mod):
+    """Y_00 = 1, (Y_1,-1, Y_10, Y_11) = (Oy, Oz, Ox), Y_20 = (3 mu^2 - 1)/2,
+    Y_22 = sqrt(3)/2 (Ox^2 - Oy^2), Y_2,-2 = sqrt(3) Ox Oy."""
+    rng = np.random.default_rng(2)
+    for o in _rand_dirs(rng, 20):
+        Y = oracle_mod.real_sh(2, o)
+        x, y, z = o
+        ref = [1, y, z, x, math.sqrt(3) * x * y, math.sqrt(3) * y * z, (3 * z * z - 1) / 2,
+               math.sqrt(3) * x * z, math.sqrt(3) / 2 * (x * x - y * y)]
+        assert np.allclose(Y, ref, atol=1e-14, rtol=0)
+
+
+def test_sh_orthogonality(oracle_mod):
+    """int Y_lm Y_l'm' dOmega = 4 pi/(2l+1) delta, by a product Gauss-Legendre x
+    trapezoid rule exact for these degrees."""
+    L = 4
+    mu, wmu = np.polynomial.legendre.leggauss(12)
+    nphi = 24
+    phis = 2 * math.pi * np.arange(nphi) / nphi
+    Nm = (L + 1) ** 2
+    G = np.zeros((Nm, Nm))
+    for m_, wm in zip(mu, wmu):
+        s = math.sqrt(1 - m_ * m_)
+        for ph in phis:
+            Y = oracle_mod.real_sh(L, (s * math.cos(ph), s * math.sin(ph), m_))
+            G += np.outer(Y, Y) * wm * (2 * math.pi / nphi)
+    ref = np.diag([4 * math.pi / (2 * l + 1) for l in range(L + 1) for _ in range(2 * l + 1)])
+    assert np.allclose(G, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("N,Lmax", [(2, 1), (4, 2), (6, 3), (8, 4)])
+def test_maps_inverse_on_lqn(oracle_mod, N, Lmax):
+    """D M = I for L <= N/2 on the level-symmetric sets (the quadrature
+    integrates the products of the retained harmonics exactly), and row 0 of D
+    is eq. 3's weights."""
+    d, w = I.lq_quadrature(N)
+    for L in range(0, Lmax + 1):
+        M, D = oracle_mod.moment_maps(L, d, w)
+        assert np.allclose(D @ M, np.eye((L + 1) ** 2), atol=2e-14, rtol=0), (N, L)
+        assert np.array_equal(D[0], w)
+
+
+# ---------------------------------------------------------------- Siddon
+def _box_entry(p, x, org, hi):
+    d = x - p
+    ok = d != 0
+    t0 = (org[ok] - p[ok]) / d[ok]
+    t1 = (hi[ok] - p[ok]) / d[ok]
+    return max(0.0, np.max(np.minimum(t0, t1)))
+
+
+def test_siddon_length_partition(oracle_mod):
+    """Segment lengths sum to |x - entry| and every voxel index is valid."""
+    rng = np.random.default_rng(3)
+    grid = (7, 5, 4, 1.3, 0.9, 2.1, np.array([-4.55, -2.25, -4.2]))
+    nx, ny, nz, dx, dy, dz, org = grid
+    hi = org + np.array([nx * dx, ny * dy, nz * dz])
+    for _ in range(200):
+        i, j, k = rng.integers(nx), rng.integers(ny), rng.integers(nz)
+        x = org + (np.array([i, j, k]) + 0.5) * np.array([dx, dy, dz])
+        p = rng.uniform(-30, 30, size=3)
+        p[rng.integers(3)] = 30.0 * rng.choice([-1, 1])
+        vox, ln = oracle_mod.siddon(grid, p, x)
+        a_in = _box_entry(p, x, org, hi)
+        assert abs(ln.sum() - (1 - a_in) * np.linalg.norm(x - p)) < 1e-12
+        assert np.all(ln >= 0) and np.all((vox >= 0) & (vox < nx * ny * nz))
+        assert vox[-1] == i + nx * (j + ny * k)
+
+
+def test_siddon_brute_force(oracle_mod):
+    """Per-voxel path lengths match dense midpoint sampling of the segment on a
+    3x3x3 grid."""
+    rng = np.random.default_rng(4)
+    grid = (3, 3, 3, 1.0, 1.5, 0.8, np.array([-1.5, -2.25, -1.2]))
+    nx, ny, nz, dx, dy, dz, org = grid
+    hi = org + np.array([nx * dx, ny * dy, nz * dz])
+    ns = 400000
+    for _ in range(12):
+        i, j, k = rng.integers(3, size=3)
+        x = org + (np.array([i, j, k]) + 0.5) * np.array([dx, dy, dz])
+        p = rng.uniform(-6, 6, size=3)
+        p[rng.integers(3)] = 8.0 * rng.choice([-1, 1])
+        vox, ln = oracle_mod.siddon(grid, p, x)
+        got = np.bincount(vox, weights=ln, minlength=27)
+        a_in = _box_entry(p, x, org, hi)
+        t = a_in + (1 - a_in) * (np.arange(ns) + 0.5) / ns
+        pts = p[None] + t[:, None] * (x - p)[None]
+        idx = np.floor((pts - org) / np.array([dx, dy, dz])).astype(int)
+        idx = np.clip(idx, 0, 2)
+        v = idx[:, 0] + 3 * (idx[:, 1] + 3 * idx[:, 2])
+        ref = np.bincount(v, minlength=27) * (1 - a_in) * np.linalg.norm(x - p) / ns
+        assert np.allclose(got, ref, atol=1e-4)
+
+
+def test_siddon_axis_aligned(oracle_mod):
+    """A ray along +x through voxel centres crosses full voxels of length dx."""
+    grid = (5, 2, 2, 0.7, 1.0, 1.0, np.array([0.0, 0.0, 0.0]))
+    p = np.array([-3.0, 0.5, 0.5])
+    x = np.array([4 * 0.7 + 0.35, 0.5, 0.5])
+    vox, ln = oracle_mod.siddon(grid, p, x)
+    keep = ln > 0
+    assert list(vox[keep]) == [0, 1, 2, 3, 4]
+    assert np.allclose(ln[keep], [0.7, 0.7, 0.7, 0.7, 0.35], atol=1e-14)
+
+
+# ---------------------------------------------------------------- uncollided
+def _small_cyl():
+    ph = I.cylinder_phantom(12, 10, 6, 2.0)
+    return ph
+
+
+def _beam_ref(ph, p, axis, fan, cone):
+    x, y, z = ph.centres()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    d = np.stack([X - p[0], Y - p[1], Z - p[2]], -1).reshape(-1, 3)
+    a = np.array([axis[0], axis[1]]) / np.hypot(axis[0], axis[1])
+    along = d[:, 0] * a[0] + d[:, 1] * a[1]
+    across = -d[:, 0] * a[1] + d[:, 1] * a[0]
+    az = np.degrees(np.arctan2(across, along))
+    el = np.degrees(np.arctan2(d[:, 2], np.hypot(d[:, 0], d[:, 1])))
+    return (np.abs(az) <= fan / 2) & (np.abs(el) <= cone / 2), d
+
+
+def test_uncollided_vacuum(oracle_mod):
+    """Zero density: phi_u = w / (4 pi r^2) inside the fan x cone window, 0 outside."""
+    ph = _small_cyl()
+    ph.density[:] = 0.0
+    xs = I.xs_tables(ph.material_names, 3, 0)
+    p, ax = np.array([0.0, 40.0, 0.0]), np.array([0.0, -1.0, 0.0])
+    gw = np.array([0.5, 0.3, 0.2])
+    out = oracle_mod.uncollided(ph, xs.sigma_t, p, ax, 30.0, 12.0, gw)[0]
+    inb, d = _beam_ref(ph, p, ax, 30.0, 12.0)
+    r2 = (d ** 2).sum(1)
+    assert 0 < inb.sum() < ph.C
+    for g in range(3):
+        assert np.allclose(out[g], np.where(inb, gw[g] / (4 * math.pi * r2), 0.0), rtol=1e-14, atol=0)
+
+
+def test_uncollided_pure_absorber(oracle_mod):
+    """Homogeneous grid: phi_u = w exp(-mu s) / (4 pi r^2), s = chord from the box
+    entry to the voxel centre (closed form)."""
+    ph = _small_cyl()
+    ph.material[:] = 1
+    ph.density[:] = 1.0
+    xs = I.xs_tables(ph.material_names, 2, 0)
+    p, ax = np.array([3.0, 35.0, -4.0]), np.array([-0.1, -1.0, 0.0])
+    gw = np.array([0.6, 0.4])
+    out = oracle_mod.uncollided(ph, xs.sigma_t, p, ax, 40.0, 20.0, gw)[0]
+    inb, d = _beam_ref(ph, p, ax, 40.0, 20.0)
+    hi = ph.origin + np.array([ph.nx * ph.dx, ph.ny * ph.dy, ph.nz * ph.dz])
+    r = np.linalg.norm(d, axis=1)
+    assert inb.sum() > 50
+    for v in np.nonzero(inb)[0]:
+        x = p + d[v]
+        a_in = _box_entry(p, x, ph.origin, hi)
+        s = (1 - a_in) * r[v]
+        for g in range(2):
+            ref = gw[g] * math.exp(-xs.sigma_t[1, g] * s) / (4 * math.pi * r[v] ** 2)
+            assert abs(out[g, v] / ref - 1) < 1e-12
+
+
+def test_uncollided_heterogeneous_brute_force(oracle_mod):
+    """Optical depth through the abdomen phantom matches dense sampling of
+    sigma_t along the ray."""
+    ph = I.abdomen_phantom(16, 14, 4, 2.4)
+    xs = I.xs_tables(ph.material_names, 2, 0)
+    p, ax = np.array([0.0, 54.0, 0.0]), np.array([0.0, -1.0, 0.0])
+    out = oracle_mod.uncollided(ph, xs.sigma_t, p, ax, 60.0, 30.0, np.array([1.0, 1.0]))[0]
+    inb, d = _beam_ref(ph, p, ax, 60.0, 30.0)
+    hi = ph.origin + np.array([ph.nx * ph.dx, ph.ny * ph.dy, ph.nz * ph.dz])
+    rng = np.random.default_rng(5)
+    sel = rng.choice(np.nonzero(inb)[0], 25, replace=False)
+    ns = 200000
+    dl = np.array([ph.dx, ph.dy, ph.dz])
+    for v in sel:
+        x = p + d[v]
+        a_in = _box_entry(p, x, ph.origin, hi)
+        t = a_in + (1 - a_in) * (np.arange(ns) + 0.5) / ns
+        pts = p[None] + t[:, None] * d[v][None]
+        idx = np.clip(np.floor((pts - ph.origin) / dl).astype(int), 0, [ph.nx - 1, ph.ny - 1, ph.nz - 1])
+        u = idx[:, 0] + ph.nx * (idx[:, 1] + ph.ny * idx[:, 2])
+        seg = (1 - a_in) * np.linalg.norm(d[v]) / ns
+        for g in range(2):
+            tau = np.sum(ph.density[u] * xs.sigma_t[ph.material[u], g]) * seg
+            # compare optical depths: sampling error is a fraction of one
+            # sample length per material boundary (|dtau| << one voxel's tau)
+            tau_o = -math.log(out[g, v] * 4 * math.pi * np.sum(d[v] ** 2))
+            assert abs(tau_o - tau) < 1e-3 * max(1.0, tau / 10)
+
+
+def test_uncollided_independent_of_quadrature(oracle_mod):
+    """phi_u does not depend on the S_N / P_N choice (Sec. III-A: one
+    uncollided set serves every quadrature)."""
+    prob = I.make_problem("tiny")
+    r1 = oracle_mod.solve_problem(prob, fixed_iters=[2] * prob.G)
+    d2, w2 = I.lq_quadrature(2)
+    r2 = oracle_mod.solve(prob.phantom, prob.xs, d2, w2, 0, prob.src_pos, prob.src_axis, prob.fan_deg,
+                          prob.cone_deg, prob.group_w, fixed_iters=[2] * prob.G)
+    assert np.array_equal(r1.phi_u, r2.phi_u)
+
+
+# ---------------------------------------------------------------- first collision
+def test_first_collision_addition_theorem(oracle_mod):
+    """The angular first-collision source M ext at direction Omega_n equals
+    sum_{g'<=g} rho sum_l (2l+1)/(4pi) s_l^{g'g} P_l(Omega_n . Omega_hat) phi_u,g'
+    (scattering of a beam along Omega_hat; Legendre expansion of sigma_s in eq. 2)."""
+    prob = I.make_problem("tiny_abd")
+    ph, L, G = prob.phantom, prob.L, prob.G
+    pu = oracle_mod.uncollided(ph, prob.xs.sigma_t, prob.src_pos, prob.src_axis, prob.fan_deg,
+                               prob.cone_deg, prob.group_w)[0]
+    ext = oracle_mod.first_collision(ph, prob.xs.sigma_s, L, prob.src_pos[0], pu)
+    M, _ = oracle_mod.moment_maps(L, prob.dirs, prob.weights)
+    x, y, z = ph.centres()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    d = np.stack([X, Y, Z], -1).reshape(-1, 3) - prob.src_pos[0]
+    oh = d / np.linalg.norm(d, axis=1, keepdims=True)
+    rng = np.random.default_rng(6)
+    sel = rng.choice(np.nonzero(pu[0] > 0)[0], 20, replace=False)
+    for v in sel:
+        m = ph.material[v]
+        cosang = prob.dirs @ oh[v]
+        for g in range(G):
+            ang = M @ ext[g, :, v]
+            ref = np.zeros(prob.N)
+            for gp in range(g + 1):
+                for l in range(L + 1):
+                    Pl = np.polynomial.legendre.legval(cosang, [0] * l + [1])
+                    ref += ph.density[v] * (2 * l + 1) / (4 * math.pi) * prob.xs.sigma_s[m, l, gp, g] * Pl * pu[gp, v]
+            assert np.allclose(ang, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- DD cell and sweep
+def test_dd_cell_hand_values(oracle_mod):
+    with open(os.path.join(GOLD, "dd_cell_hand.json")) as f:
+        hv = json.load(f)
+    c = np.full(3, 1 / math.sqrt(3))
+    pc, pout, nf = oracle_mod.dd_cell(1.0, 1.0, c, [0, 0, 0])
+    h = hv["case_i"]
+    assert abs(pc - h["psi_c"]) < 1e-12 and np.allclose(pout, h["psi_out"], atol=1e-12) and nf == 0
+    assert abs(np.sum(c * pout) - h["leakage"]) < 1e-12 and abs(pc * 1.0 - h["absorption"]) < 1e-12
+    mu1 = math.sqrt((4 - math.sqrt(6.4)) / 12)
+    om = np.array([mu1, mu1, math.sqrt(1 - 2 * mu1 * mu1)])
+    cc = om / np.array([1.0, 2.0, 0.5])
+    h = hv["case_ii"]
+    pc, pout, nf = oracle_mod.dd_cell(0.7, 2.0, cc, [0.5, 0.25, 0.0], fixup=False)
+    assert abs(pc - h["psi_c_dd"]) < 1e-12 and abs(pout[0] - h["psi_out_x_dd"]) < 1e-12
+    pc, pout, nf = oracle_mod.dd_cell(0.7, 2.0, cc, [0.5, 0.25, 0.0], fixup=True)
+    assert abs(pc - h["psi_c_fixup"]) < 1e-12 and np.allclose(pout, h["psi_out_fixup"], atol=1e-12) and nf == 1
+    # the fixed-up cell still balances
+    bal = np.sum(cc * (pout - [0.5, 0.25, 0.0])) + 2.0 * pc - 0.7
+    assert abs(bal) < 1e-15
+
+
+def test_dd_cell_fixup_cascade(oracle_mod):
+    """Fixing one face can make another negative; every outgoing face ends >= 0
+    and the cell still balances."""
+    rng = np.random.default_rng(7)
+    for _ in range(2000):
+        c = rng.uniform(0.01, 3, 3)
+        pin = rng.uniform(0, 2, 3) * (rng.uniform(size=3) < 0.7)
+        q, sig = rng.uniform(0, 0.3), rng.uniform(0.1, 30)
+        pc, pout, nf = oracle_mod.dd_cell(q, sig, c, pin, fixup=True)
+        assert np.all(pout >= 0)
+        assert abs(np.sum(c * (pout - pin)) + sig * pc - q) < 1e-12 * max(1, q + np.sum(c * pin))
+
+
+def test_sweep_balance_every_sweep(oracle_mod):
+    """One sweep conserves particles per direction: V (sum q - sigma psi) equals
+    the outgoing minus incoming boundary current (DD and the fixup are
+    conservative)."""
+    rng = np.random.default_rng(8)
+    nx, ny, nz, dx, dy, dz = 7, 6, 5, 0.8, 1.1, 0.6
+    C = nx * ny * nz
+    sig = rng.uniform(0.05, 8.0, C)
+    d, w = I.lq_quadrature(4)
+    q = rng.uniform(0, 1, (len(w), C)) * (rng.uniform(size=(len(w), C)) < 0.3)
+    inflow = 0.05
+    psi, leak, nf = oracle_mod.sweep((nx, ny, nz), (dx, dy, dz), sig, d, q, inflow=inflow)
+    assert nf > 0
+    V = dx * dy * dz
+    A = np.array([dy * dz, dx * dz, dx * dy])
+    nin = np.array([ny * nz, nx * nz, nx * ny])
+    for n in range(len(w)):
+        prod = V * np.sum(q[n]) + np.sum(np.abs(d[n]) * A * nin * inflow)
+        rem = V * np.sum(sig * psi[n])
+        lk = np.sum(np.abs(d[n]) * A * leak[n])
+        assert abs(prod - rem - lk) < 1e-12 * prod
+
+
+def test_sweep_uniform_exact(oracle_mod):
+    """With inflow psi0 on every face and source q = sigma psi0 the DD equations
+    are solved exactly by psi = psi0 everywhere (infinite-medium check of the
+    sweep, any cell size)."""
+    nx, ny, nz = 5, 4, 3
+    C = nx * ny * nz
+    sig = np.full(C, 1.7)
+    d, w = I.lq_quadrature(6)
+    psi0 = 0.37
+    q = np.full((len(w), C), 1.7 * psi0)
+    psi, _, nf = oracle_mod.sweep((nx, ny, nz), (0.5, 2.0, 1.0), sig, d, q, inflow=psi0)
+    assert np.allclose(psi, psi0, rtol=1e-14, atol=0) and nf == 0
+
+
+def test_sweep_mirror_symmetry(oracle_mod):
+    """Reflecting the problem in x maps the flux of each direction onto its
+    mirror direction."""
+    rng = np.random.default_rng(9)
+    nx, ny, nz = 6, 5, 4
+    sig = rng.uniform(0.1, 3, (nz, ny, nx))
+    qc = rng.uniform(0, 1, (nz, ny, nx))
+    d, w = I.lq_quadrature(4)
+    q = np.broadcast_to(qc.reshape(-1), (len(w), nx * ny * nz))
+    psi, _, _ = oracle_mod.sweep((nx, ny, nz), (1, 1, 1), sig.reshape(-1), d, q)
+    sig_m, q_m = sig[:, :, ::-1].reshape(-1), np.broadcast_to(qc[:, :, ::-1].reshape(-1), q.shape)
+    psi_m, _, _ = oracle_mod.sweep((nx, ny, nz), (1, 1, 1), sig_m, d, q_m)
+    n8 = len(w) // 8
+    for n in range(len(w)):
+        o, p = divmod(n, n8)
+        nm = (o ^ 1) * n8 + p
+        a = psi[n].reshape(nz, ny, nx)
+        b = psi_m[nm].reshape(nz, ny, nx)[:, :, ::-1]
+        assert np.allclose(a, b, rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------- full solve
+def _infinite_problem(G=4, L=1):
+    ph = I.cylinder_phantom(6, 5, 4, 1.0)
+    ph.material[:] = 1
+    ph.density[:] = 1.0
+    xs = I.xs_tables(ph.material_names, G, L)
+    return ph, xs
+
+
+def test_infinite_medium_multigroup(oracle_mod):
+    """Uniform isotropic source S_g and isotropic inflow phi_g/(4 pi) on every
+    face reproduce the infinite homogeneous medium:
+    phi_g = (S_g + sum_{g'<g} s_0^{g'g} phi_g') / (sigma_t,g - s_0^{gg})."""
+    ph, xs = _infinite_problem()
+    G = xs.G
+    S = np.array([1.0, 0.5, 0.25, 2.0])
+    st, s0 = xs.sigma_t[1], xs.sigma_s[1, 0]
+    phi = np.zeros(G)
+    for g in range(G):
+        phi[g] = (S[g] + sum(s0[gp, g] * phi[gp] for gp in range(g))) / (st[g] - s0[g, g])
+    d, w = I.lq_quadrature(4)
+    ext = np.repeat(S[:, None], ph.C, axis=1)
+    r = oracle_mod.solve(ph, xs, d, w, 1, np.array([0, 40.0, 0]), np.array([0, -1.0, 0]), 20, 10,
+                         np.zeros(G), ext_iso=ext, tol=1e-13, test_inflow=phi / (4 * math.pi))
+    assert np.allclose(r.phi[0, :, 0], phi[:, None], rtol=1e-11, atol=0)
+    assert np.abs(r.phi[0, :, 1:]).max() < 1e-11 * phi.max()
+
+
+def test_source_iteration_rate(oracle_mod):
+    """Single group in an infinite medium: converges to S / sigma_a, and the
+    relative change shrinks like c = s_0/sigma_t per iteration (spectral radius
+    of source iteration), so the count is bounded by log(tol (1-c)) / log c."""
+    ph, xs = _infinite_problem(G=1, L=0)
+    st, ss = xs.sigma_t[1, 0], xs.sigma_s[1, 0, 0, 0]
+    c = ss / st
+    S = 1.3
+    sa = st - ss
+    d, w = I.lq_quadrature(2)
+    ext = np.full((1, ph.C), S)
+    r = oracle_mod.solve(ph, xs, d, w, 0, np.array([0, 40.0, 0]), np.array([0, -1.0, 0]), 20, 10,
+                         np.zeros(1), ext_iso=ext, tol=1e-10, test_inflow=np.array([S / sa / (4 * math.pi)]))
+    assert np.allclose(r.phi[0, 0, 0], S / sa, rtol=1e-9)
+    assert r.iters[0, 0] <= math.ceil(math.log(1e-10 * (1 - c)) / math.log(c)) + 3
+
+
+def test_balance_at_convergence(oracle_mod):
+    """Per group, production = removal + leakage at tight tolerance (P = R + L)."""
+    prob = I.make_problem("tiny_abd")
+    r = oracle_mod.solve_problem(prob, tol=1e-13)
+    P, R, Lk = r.balance[0].T
+    assert np.all(np.abs(P - R - Lk) <= 1e-10 * P)
+
+
+def test_cylinder_mirror_symmetry(oracle_mod):
+    """Water cylinder with the source on the y axis: dose is mirror symmetric in
+    x and in z (LQ_N and DD are mirror-exact)."""
+    prob = I.make_problem("c1")
+    r = oracle_mod.solve_problem(prob, tol=1e-8)
+    dose = r.dose[0].reshape(8, 24, 24)
+    sc = np.abs(dose).max()
+    assert np.abs(dose - dose[:, :, ::-1]).max() < 1e-12 * sc
+    assert np.abs(dose - dose[::-1, :, :]).max() < 1e-12 * sc
+
+
+def test_linearity_in_weights(oracle_mod):
+    """The solve is linear in the source group weights (fixed iteration counts)."""
+    prob = I.make_problem("tiny")
+    G = prob.G
+    fi = [6] * G
+    rng = np.random.default_rng(10)
+    w1, w2 = rng.uniform(0, 1, G), rng.uniform(0, 1, G)
+    args = (prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos, prob.src_axis,
+            prob.fan_deg, prob.cone_deg)
+    r1 = oracle_mod.solve(*args, w1, fixed_iters=fi, fixup=False)
+    r2 = oracle_mod.solve(*args, w2, fixed_iters=fi, fixup=False)
+    r3 = oracle_mod.solve(*args, 2 * w1 + 3 * w2, fixed_iters=fi, fixup=False)
+    assert np.allclose(r3.dose, 2 * r1.dose + 3 * r2.dose, rtol=1e-12, atol=1e-15 * np.abs(r3.dose).max())
+
+
+def test_dose_definition(oracle_mod):
+    """dose = sum_g kappa_g[m] (phi_u,g + phi_00,g) (collision kerma, Sec. II-A)."""
+    prob = I.make_problem("tiny")
+    r = oracle_mod.solve_problem(prob)
+    k = prob.xs.kerma[prob.phantom.material].T          # [G][C]
+    ref = np.sum(k * (r.phi_u[0] + r.phi[0, :, 0]), axis=0)
+    assert np.allclose(r.dose[0], ref, rtol=1e-14, atol=0)
+
+
+def test_threads_bitwise(oracle_mod):
+    """Thread count does not change any result bit."""
+    prob = I.make_problem("tiny_abd")
+    a = oracle_mod.solve_problem(prob, threads=1)
+    b = oracle_mod.solve_problem(prob, threads=4)
+    assert np.array_equal(a.dose, b.dose) and np.array_equal(a.phi, b.phi)
