@@ -1,0 +1,172 @@
+/*
+ * dctsn — multigroup discrete-ordinates (S_N) photon fluence and dose solver
+ * for CT, gfx950 (MI355X) native.  C ABI.
+ *
+ * The calls follow the statement of the problem in Norris & Liu,
+ * "Photon Fluence and Dose Estimation in Computed Tomography using a Discrete
+ * Ordinates Boltzmann Solver" (arXiv:1811.12391):
+ *   geometry and materials      Sec. II-B (CT volume -> dosimetric materials), Sec. II-D (meshes)
+ *   cross sections              Sec. II-B (cross-section set), Sec. II-D (multigroup library)
+ *   quadrature / anisotropy     Sec. II-B, Sec. II-A eq. (3), Sec. II-D (S_N sets, P_N order)
+ *   source                      Sec. II-B (point / fan / cone source, position, spectrum,
+ *                               azimuthal and polar subtended angles), Sec. II-C
+ *   solve                       Sec. II-A eq. (2) with vacuum boundaries, first-collision
+ *                               source method, eq. (3) for the scalar fluence; Sec. II-B
+ *                               ("Launch Solver" only with complete, consistent input)
+ *   dose                        Sec. II-A (collision kerma taken as absorbed dose),
+ *                               Sec. III-A (fluence split into uncollided and collided)
+ *
+ * Conventions shared by every call:
+ *   - voxel index v = i + nx*(j + ny*k), x fastest; C = nx*ny*nz;
+ *   - group g = 0 is the highest energy;
+ *   - real spherical-harmonic moment index lm = l*l + l + m, Nm = (L+1)^2;
+ *   - every input pointer is read during the call and never retained
+ *     (the library copies what it needs); outputs are caller-allocated;
+ *   - a context owns its device memory (hipMalloc on the context's device)
+ *     and runs every kernel on the stream given to dct_create;
+ *   - any set_* call invalidates earlier results;
+ *   - status codes below; on failure dct_last_error() describes the cause.
+ * A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef DCTSN_H
+#define DCTSN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DCT_OK 0
+#define DCT_EINVAL (-1)    /* bad argument, size or value */
+#define DCT_ESTATE (-2)    /* an input is missing or inputs conflict (Sec. II-B) */
+#define DCT_EDEVICE (-3)   /* HIP error or no GPU; message holds the HIP error string */
+#define DCT_ENOMEM (-4)    /* device or host allocation failed */
+#define DCT_ENOTCONV (-5)  /* max_iter reached before tol in some group; outputs valid */
+#define DCT_ENUMERIC (-6)  /* NaN or Inf met in a convergence reduction */
+
+/* Arithmetic of the collided solve.  The ray-traced optical depth, the
+ * convergence and balance reductions and the dose tally are FP64 in every
+ * mode. */
+#define DCT_FP64 0          /* everything FP64 */
+#define DCT_FP32 1          /* sweeps, moment maps and moment storage FP32 */
+#define DCT_FP32_BF16MAP 2  /* as DCT_FP32, with bf16 inputs to both moment maps
+                               (fp32 accumulation) */
+
+typedef struct dct_ctx dct_ctx;
+
+typedef struct dct_opts {
+    int precision;            /* DCT_FP64 / DCT_FP32 / DCT_FP32_BF16MAP */
+    double tol;               /* per-group stop: max|dphi_00| / max|phi_00| <= tol */
+    int max_iter;             /* per-group iteration cap (>= 1) */
+    const int *fixed_iters;   /* [G] or NULL: run exactly this many iterations per group
+                                 (ignores tol; used to lock the stopping point) */
+    int fixup;                /* 1: set-to-zero negative-flux fixup in the sweep */
+    const double *test_inflow;/* [G] or NULL: isotropic angular flux entering through every
+                                 boundary face (NULL = vacuum, Sec. II-A) */
+    int chunk;                /* iterations enqueued between host convergence polls (0 = auto) */
+    int use_graph;            /* 1: capture one iteration in a HIP graph and replay it */
+    int profile;              /* 1: time every sweep launch with HIP events (dct_stats) */
+} dct_opts;
+
+typedef struct dct_stats {
+    /* caller-owned arrays, each may be NULL */
+    int *iters;               /* [B][G] iterations taken */
+    double *eps;              /* [B][G] final relative change */
+    double *balance;          /* [B][G][3] production, removal, leakage of the final sweep */
+    /* filled by the library */
+    long long sweep_updates;  /* sum over sweeps of C * N (cell-angle updates, all groups, RHS) */
+    int sweep_launches;       /* sweep kernel launches whose time is in sweep_ms */
+    double sweep_ms;          /* summed device time of sweep launches (profile = 1) */
+    double solve_ms;          /* device time of the whole dct_solve (HIP events) */
+    int iteration_sets;       /* iteration launch sets enqueued (>= max over RHS of iterations) */
+} dct_stats;
+
+/* Create a context on HIP device `device` using `stream` (a hipStream_t; NULL
+ * means the device's default stream).  device = -1 creates a host-only
+ * context that validates inputs but cannot solve (DCT_EDEVICE from solve). */
+int dct_create(dct_ctx **out, int device, void *stream);
+
+/* Release the context and all its device memory.  NULL is accepted. */
+int dct_destroy(dct_ctx *ctx);
+
+/* Message of the last failing call on ctx (valid until the next call); ""
+ * after success.  A NULL ctx gives the message of the last failed
+ * dct_create. */
+const char *dct_last_error(const dct_ctx *ctx);
+
+/* Voxel phantom (Sec. II-B: CT volume converted to dosimetric materials;
+ * Sec. II-D: rectangular mesh of cubic or box voxels).
+ *   nx, ny, nz > 0; dx, dy, dz > 0 (cm); origin[3] = grid corner (cm);
+ *   material[C] (uint8, < M of dct_set_xs); density[C] (g/cm^3, finite, >= 0).
+ * EINVAL on bad sizes or values. */
+int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy, double dz,
+                     const double *origin, const uint8_t *material, const double *density);
+
+/* Multigroup cross sections per unit density (Sec. II-B / II-D: multigroup
+ * library; eq. (2) with a Legendre expansion of the scattering kernel).
+ *   G >= 1 groups, edges_keV[G+1] strictly descending (may be NULL);
+ *   M in [1, 8] materials; L in [0, 7] Legendre order;
+ *   sigma_t[M][G] cm^2/g total;
+ *   sigma_s[M][L+1][G][G] cm^2/g Legendre moments s_l^{g->g'} (from, to),
+ *     zero for g' < g (no upscatter);
+ *   kerma[M][G] keV cm^2/g, dose = sum_g kerma_g * fluence_g.
+ * EINVAL on upscatter entries, negative or non-finite sigma_t / kerma. */
+int dct_set_xs(dct_ctx *ctx, int G, const double *edges_keV, int M, int L, const double *sigma_t,
+               const double *sigma_s, const double *kerma);
+
+/* Discrete-ordinates quadrature (Sec. II-A eq. (3), Sec. II-D: S_N sets with
+ * N(N+2) directions).  dirs[n][3] unit vectors with no zero component,
+ * w[n] > 0; n a multiple of 8 when the set is octant-symmetric (not required).
+ * ESTATE at solve time if the P_N order L exceeds what the set integrates
+ * (checked as D M = I to 1e-10 on the moment maps). */
+int dct_set_quadrature(dct_ctx *ctx, int n, const double *dirs, const double *w);
+
+/* Collimated isotropic point sources (Sec. II-B: position, energy
+ * distribution, azimuthal and polar subtended angles), one right-hand side
+ * each, all solved together.
+ *   B >= 1; pos[B][3] cm, each outside the voxel grid box;
+ *   axis[B][3] beam axis (NULL: toward the z axis, -pos projected on z = 0);
+ *     its projection on z = 0 must be non-zero;
+ *   fan_deg in (0, 360]: full azimuthal opening about z (360 = no fan limit);
+ *   cone_deg in (0, 180]: full polar opening from the z = 0 plane (180 = none);
+ *   group_w[G] photons per source photon in each group (one source photon
+ *     is emitted isotropically into 4 pi before collimation).
+ * Window edges are inclusive. */
+int dct_set_source(dct_ctx *ctx, int B, const double *pos, const double *axis, double fan_deg,
+                   double cone_deg, const double *group_w);
+
+/* Optional isotropic volumetric source S[G][C] (photons / cm^3 per source
+ * photon, the S term of eq. (1)), added to every right-hand side.  NULL
+ * removes it. */
+int dct_set_volume_source(dct_ctx *ctx, const double *S);
+
+/* Run the whole solve on the device (Sec. II-A): ray-traced uncollided
+ * fluence, first-collision source, per-group source iteration with
+ * downscatter (g = 0 .. G-1) on diamond-difference sweeps, scalar fluence by
+ * quadrature, dose tally.  opts may be NULL (defaults: FP64, tol 1e-6,
+ * max_iter 1000, fixup on, vacuum, graph off, profile off); stats may be NULL.
+ * Returns ENOTCONV (outputs valid) if some group stopped at max_iter,
+ * ENUMERIC on NaN/Inf, ESTATE if an input is missing or inputs conflict. */
+int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats);
+
+/* Results of the last solve into caller-allocated HOST buffers.
+ *   dose[B][C] (summed = 0) or dose[C] (summed = 1: sum over sources), keV/g
+ *     per source photon;
+ *   phi_u[B][G][C] uncollided scalar fluence (may be NULL);
+ *   phi_c[B][G][C] collided scalar fluence phi_00 (may be NULL).
+ * ESTATE before a successful solve. */
+int dct_dose(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c);
+
+/* As dct_dose, into DEVICE buffers of the context's device, written on the
+ * context's stream (asynchronous). */
+int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c);
+
+/* All collided flux moments of the last solve into a host buffer
+ * phi[B][G][Nm][C] (FP64 whatever the precision). */
+int dct_moments(dct_ctx *ctx, double *phi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCTSN_H */

@@ -1,0 +1,219 @@
+// Internal declarations of the dctsn HIP library (gfx950).
+//
+// Data layout in HBM
+// ------------------
+// Moment-space arrays (ext, phi, phi_u, dose, material, density) use the
+// natural voxel order v = i + nx*(j + ny*k).
+//
+// Direction-space arrays (the angular source q and angular flux psi of every
+// direction, and the per-class total cross section used by the sweep) use a
+// "diagonal-rotated" layout chosen so that one wavefront step of the sweep
+// touches consecutive addresses.  A sweep wave maps its 64 lanes to 64
+// consecutive y indices of one z layer and walks x; at step t lane j handles
+// the cell with i' + j' = const (primed = reflected into the octant's sweep
+// direction).  Two layouts cover the eight octants:
+//   class A (Ox*Oy > 0): pos = (k*nx + (i + j) mod nx) * ny + j
+//   class B (Ox*Oy < 0): pos = (k*nx + (i - j) mod nx) * ny + j
+// In both, the cells of one wave step share the row (k, r) and differ only in
+// j, so the 64 lanes read 64 consecutive elements (descending for Oy < 0).
+// The moment maps read/write these layouts directly; the combine kernel moves
+// between them and the natural layout through LDS, one (k, 16-row) slab at a
+// time (a slab is closed under both rotations).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DCT_MAXMAT 8
+#define DCT_MAXL 5
+#define DCT_MAXNM ((DCT_MAXL + 1) * (DCT_MAXL + 1))
+#define DCT_PI 3.14159265358979323846
+
+namespace dct {
+
+// ---------------------------------------------------------------- layouts
+__host__ __device__ inline int rot_row(int cls, int i, int jm, int nx)
+{
+    int r = cls == 0 ? i + jm : i - jm;
+    if (r >= nx) r -= nx;
+    if (r < 0) r += nx;
+    return r;
+}
+
+__host__ __device__ inline long cls_pos(int cls, int i, int j, int k, int nx, int ny)
+{
+    int r = rot_row(cls, i, j % nx, nx);
+    return ((long)k * nx + r) * ny + j;
+}
+
+// class of a direction: 0 when Ox and Oy have the same sign
+__host__ __device__ inline int dir_class(double ox, double oy) { return ((ox > 0) == (oy > 0)) ? 0 : 1; }
+
+// ---------------------------------------------------------------- harmonics
+// Real spherical harmonics with Y_00 = 1 and sum_m Y_lm(a) Y_lm(b) = P_l(a.b),
+// evaluated in Cartesian form: Y_lm = N_lm * T_l^|m|(z) * {Re, Im}(x + i y)^|m|
+// where T_l^m = d^m P_l / dz^m (so no angle functions are needed) and
+// N_lm = sqrt((2 - delta_m0) (l-m)! / (l+m)!).
+template <typename R>
+__host__ __device__ inline void real_sh_cart(int L, R x, R y, R z, R *Y)
+{
+    // (x + i y)^m
+    R cr[DCT_MAXL + 1], ci[DCT_MAXL + 1];
+    cr[0] = 1;
+    ci[0] = 0;
+    for (int m = 1; m <= L; ++m) {
+        cr[m] = cr[m - 1] * x - ci[m - 1] * y;
+        ci[m] = cr[m - 1] * y + ci[m - 1] * x;
+    }
+    for (int m = 0; m <= L; ++m) {
+        // T_m^m = (2m-1)!!, T_{m+1}^m = (2m+1) z T_m^m, then the three-term recurrence
+        R dfac = 1;
+        for (int t = 1; t <= m; ++t) dfac *= (R)(2 * t - 1);
+        R tm2 = 0, tm1 = dfac;
+        for (int l = m; l <= L; ++l) {
+            R tl;
+            if (l == m) tl = dfac;
+            else if (l == m + 1) tl = (R)(2 * m + 1) * z * dfac;
+            else tl = ((R)(2 * l - 1) * z * tm1 - (R)(l + m - 1) * tm2) / (R)(l - m);
+            if (l > m) { tm2 = tm1; tm1 = tl; }
+            R ratio = 1;
+            for (int t = l - m + 1; t <= l + m; ++t) ratio /= (R)t;
+            R nrm = sqrt((m == 0 ? (R)1 : (R)2) * ratio);
+            Y[l * l + l + m] = nrm * tl * cr[m];
+            if (m > 0) Y[l * l + l - m] = nrm * tl * ci[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- device state
+// Per right-hand-side state of the device-driven group / iteration machine.
+struct RhsState {
+    int g;          // group being iterated (== G when every group is done)
+    int it;         // iterations done in group g
+    int pending;    // 1: the transition kernel must set up group g
+    int finished;   // 1: all groups done
+    int nan;        // NaN/Inf seen in a convergence reduction
+    int notconv;    // some group stopped at max_iter above tol
+    unsigned long long eps_num, eps_den;   // bit patterns of non-negative doubles (max)
+    unsigned int cnt_combine, cnt_trans;   // last-block-done counters
+};
+
+struct Geo {
+    int nx, ny, nz;
+    long C;
+    double dx, dy, dz;
+    double org[3];
+};
+
+struct TraceArgs {
+    Geo geo;
+    const uint8_t *mat;
+    const double *rho;
+    const double *st;     // [M][G]
+    int G, M, B;
+    const double *pos;    // [B][3]
+    const double *axis;   // [B][3]
+    double half_fan, half_cone;   // radians
+    const double *gw;     // [G]
+    double *phi_u;        // [B][G][C]
+};
+
+struct TransArgs {
+    Geo geo;
+    int G, M, L, Nm, N, B;
+    double V;
+    const uint8_t *mat;
+    const double *rho;
+    const double *st, *ss;    // [M][G], [M][L+1][G][G]
+    const double *pos;        // [B][3]
+    const double *phi_u;      // [B][G][C]
+    const double *ext_iso;    // [G][C] or null
+    const double *inflow;     // [G] or null
+    const double *dirs, *w;   // [N][3], [N]
+    const double *leak_part;  // [B][N][nblk][3]
+    int nblk;
+    void *phi_all;            // T [B][G][Nm][C]
+    void *ext;                // T [B][Nm][C]
+    void *Qc;                 // T [2][B][Nm][C]
+    RhsState *state;
+    double *bal;              // [B][G][3]
+    int *n_unfinished;
+};
+
+struct CombArgs {
+    Geo geo;
+    int G, L, Nm, B;
+    const uint8_t *mat;
+    const double *rho;
+    const double *ss;
+    const void *part;         // T [2][B][Nm][C] (class layouts)
+    const void *ext;          // T [B][Nm][C]
+    void *phi_all;            // T [B][G][Nm][C]
+    void *Qc;                 // T [2][B][Nm][C]
+    RhsState *state;
+    int *iters;               // [B][G]
+    double *eps;              // [B][G]
+    const int *fixed_iters;   // [G] or null
+    double tol;
+    int max_iter;
+    int nblocks_per_b;
+};
+
+struct MapArgs {
+    long C;
+    int B, N, Nm;
+    int Nc[2];
+    const int *cdir;          // [2][N] global direction index of class-local index
+    const void *Mtab;         // [2][NcP][NmP] (T or bf16)
+    const void *Dtab;         // [2][NmP][NcP]
+    int NcP, NmP;
+    const void *Qc;           // T [2][B][Nm][C]
+    void *q;                  // T [B][N][C]
+    const void *psi;          // T [B][N][C]
+    void *part;               // T [2][B][Nm][C]
+    const RhsState *state;
+};
+
+struct SweepArgs {
+    int nx, ny, nz;
+    long C;
+    int N, B, G;
+    int BK, NBJ, NBK, diag, nblk;
+    const double *dirs;
+    double dx, dy, dz;
+    const void *q;            // T [B][N][C]
+    void *psi;                // T [B][N][C]
+    const void *sigc;         // T [2][G][C]
+    void *yface;              // T [B*N][nx*nz]
+    void *zface;              // T [B*N][nx*ny]
+    double *leak_part;        // [B][N][nblk][3]
+    const RhsState *state;
+    const double *inflow;     // [G] or null
+    int fixup;
+};
+
+struct DoseArgs {
+    long C;
+    int G, B, Nm;
+    const uint8_t *mat;
+    const double *kap;        // [M][G]
+    const double *phi_u;      // [B][G][C]
+    const void *phi_all;      // T [B][G][Nm][C]
+    double *dose;             // [B][C]
+    double *phi_c;            // [B][G][C] or null
+    double *phi_u_out;        // [B][G][C] or null
+    int summed;               // 1: dose[C] = sum_b
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_trace(const TraceArgs &a, hipStream_t s);
+hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, const double *st, int G, int M,
+                       void *sigc, int is_f64, hipStream_t s);
+hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f64, 1 f32, 2 bf16
+hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_dose(const DoseArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_moments_out(const void *phi_all, long n, double *out, int is_f64, hipStream_t s);
+
+}  // namespace dct

@@ -1,0 +1,218 @@
+// Moment <-> direction maps of the P_N scattering expansion (eq. 2 with the
+// Legendre expansion of sigma_s; eq. 3 is row 0 of the D map), as dense
+// contractions over voxels on the matrix cores:
+//   M map: q[n][p]    = sum_lm M[n][lm] Q[lm][p],  M[n][lm] = (2l+1)/(4pi) Y_lm(Omega_n)
+//   D map: part[lm][p] = sum_n D[lm][n] psi[n][p], D[lm][n] = w_n Y_lm(Omega_n)
+// Each class of octants (same rotated layout) is one GEMM: rows = the class's
+// directions (M map) or the moments (D map), columns = voxel positions in that
+// class's layout, K = moments (M map) or the class's directions (D map).
+//
+// One wave computes 16 x 16 output tiles with v_mfma_*_16x16x4 (f64, f32) or
+// v_mfma_f32_16x16x16_bf16 (bf16 inputs, f32 accumulation).  Operand
+// placement (64 lanes, lane = col + 16 * krow):
+//   A[i][k]: lane i + 16 k        (16x16x16 bf16: k in [4 krow, 4 krow + 4) packed)
+//   B[k][j]: lane j + 16 k
+//   D[i][j]: lane j + 16 (i / 4), element i % 4
+// The 16 lanes of one k-row load 16 consecutive positions, so every load and
+// store of q / psi / Q / part is a 16-element contiguous run.
+#include "dct_internal.h"
+
+namespace dct {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline d4_t mfma_k4(double a, double b, d4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f4_t mfma_k4(float a, float b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+template <typename T> struct acc4;
+template <> struct acc4<double> { typedef d4_t type; };
+template <> struct acc4<float> { typedef f4_t type; };
+
+// round-to-nearest-even fp32 -> bf16 bits
+__device__ inline short to_bf16(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+// ---------------------------------------------------------------- M map
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_mmap(MapArgs a)
+{
+    typedef typename acc4<T>::type A4;
+    const int b = blockIdx.z, c = blockIdx.y;
+    if (a.state[b].finished) return;
+    const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
+    const long C = a.C;
+    const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
+    const bool inb = p < C;
+    const int Nm = a.Nm;
+    const T *Q = (const T *)a.Qc + ((long)c * a.B + b) * Nm * C;
+    T bq[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int lm = 4 * s + kr;
+        bq[s] = (inb && lm < Nm) ? Q[(long)lm * C + p] : (T)0;
+    }
+    const T *Mt = (const T *)a.Mtab + (long)c * a.NcP * a.NmP;
+    const int Nc = a.Nc[c];
+    const int *cd = a.cdir + c * a.N;
+    T *q = (T *)a.q + (long)b * a.N * C;
+    for (int rb = 0; rb * 16 < Nc; ++rb) {
+        A4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc = mfma_k4(Mt[(rb * 16 + col) * a.NmP + 4 * s + kr], bq[s], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int nl = rb * 16 + 4 * kr + r;
+            if (nl < Nc && inb) q[(long)cd[nl] * C + p] = acc[r];
+        }
+    }
+}
+
+template <int NS16>
+__global__ __launch_bounds__(256) void k_mmap_bf16(MapArgs a)
+{
+    const int b = blockIdx.z, c = blockIdx.y;
+    if (a.state[b].finished) return;
+    const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
+    const long C = a.C;
+    const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
+    const bool inb = p < C;
+    const int Nm = a.Nm;
+    const float *Q = (const float *)a.Qc + ((long)c * a.B + b) * Nm * C;
+    s4_t bq[NS16];
+#pragma unroll
+    for (int s = 0; s < NS16; ++s)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int lm = 16 * s + 4 * kr + e;
+            bq[s][e] = to_bf16((inb && lm < Nm) ? Q[(long)lm * C + p] : 0.0f);
+        }
+    const short *Mt = (const short *)a.Mtab + (long)c * a.NcP * a.NmP;
+    const int Nc = a.Nc[c];
+    const int *cd = a.cdir + c * a.N;
+    float *q = (float *)a.q + (long)b * a.N * C;
+    for (int rb = 0; rb * 16 < Nc; ++rb) {
+        f4_t acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NS16; ++s) {
+            s4_t av = *(const s4_t *)(Mt + (rb * 16 + col) * a.NmP + 16 * s + 4 * kr);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bq[s], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int nl = rb * 16 + 4 * kr + r;
+            if (nl < Nc && inb) q[(long)cd[nl] * C + p] = acc[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- D map
+template <typename T>
+__global__ __launch_bounds__(256) void k_dmap(MapArgs a)
+{
+    typedef typename acc4<T>::type A4;
+    const int b = blockIdx.z, c = blockIdx.y;
+    if (a.state[b].finished) return;
+    const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
+    const long C = a.C;
+    const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
+    const bool inb = p < C;
+    const int Nm = a.Nm, Nc = a.Nc[c];
+    const int *cd = a.cdir + c * a.N;
+    const T *psi = (const T *)a.psi + (long)b * a.N * C;
+    const T *Dt = (const T *)a.Dtab + (long)c * a.NmP * a.NcP;
+    T *part = (T *)a.part + ((long)c * a.B + b) * Nm * C;
+    for (int rb = 0; rb * 16 < Nm; ++rb) {
+        A4 acc = {0, 0, 0, 0};
+        for (int s = 0; 4 * s < Nc; ++s) {
+            int nl = 4 * s + kr;
+            T bv = (inb && nl < Nc) ? psi[(long)cd[nl] * C + p] : (T)0;
+            acc = mfma_k4(Dt[(rb * 16 + col) * a.NcP + 4 * s + kr], bv, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int lm = rb * 16 + 4 * kr + r;
+            if (lm < Nm && inb) part[(long)lm * C + p] = acc[r];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
+{
+    const int b = blockIdx.z, c = blockIdx.y;
+    if (a.state[b].finished) return;
+    const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
+    const long C = a.C;
+    const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
+    const bool inb = p < C;
+    const int Nm = a.Nm, Nc = a.Nc[c];
+    const int *cd = a.cdir + c * a.N;
+    const float *psi = (const float *)a.psi + (long)b * a.N * C;
+    const short *Dt = (const short *)a.Dtab + (long)c * a.NmP * a.NcP;
+    float *part = (float *)a.part + ((long)c * a.B + b) * Nm * C;
+    for (int rb = 0; rb * 16 < Nm; ++rb) {
+        f4_t acc = {0, 0, 0, 0};
+        for (int s = 0; 16 * s < Nc; ++s) {
+            s4_t bv;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int nl = 16 * s + 4 * kr + e;
+                bv[e] = to_bf16((inb && nl < Nc) ? psi[(long)cd[nl] * C + p] : 0.0f);
+            }
+            s4_t av = *(const s4_t *)(Dt + (rb * 16 + col) * a.NcP + 16 * s + 4 * kr);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int lm = rb * 16 + 4 * kr + r;
+            if (lm < Nm && inb) part[(long)lm * C + p] = acc[r];
+        }
+    }
+}
+
+template <typename T>
+static void dispatch_mmap(const MapArgs &a, dim3 grid, hipStream_t s)
+{
+    int NS = (a.Nm + 3) / 4;
+    switch (NS) {
+    case 1: hipLaunchKernelGGL((k_mmap<T, 1>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_mmap<T, 2>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_mmap<T, 3>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_mmap<T, 4>), grid, dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_mmap<T, 5>), grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_mmap<T, 6>), grid, dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_mmap<T, 7>), grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_mmap<T, 8>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_mmap<T, 9>), grid, dim3(256), 0, s, a); break;
+    }
+}
+
+hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.C + 63) / 64), 2, a.B);
+    if (mode == 0) dispatch_mmap<double>(a, grid, s);
+    else if (mode == 1) dispatch_mmap<float>(a, grid, s);
+    else {
+        int NS16 = (a.Nm + 15) / 16;
+        if (NS16 == 1) hipLaunchKernelGGL(k_mmap_bf16<1>, grid, dim3(256), 0, s, a);
+        else if (NS16 == 2) hipLaunchKernelGGL(k_mmap_bf16<2>, grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(k_mmap_bf16<3>, grid, dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.C + 63) / 64), 2, a.B);
+    if (mode == 0) hipLaunchKernelGGL(k_dmap<double>, grid, dim3(256), 0, s, a);
+    else if (mode == 1) hipLaunchKernelGGL(k_dmap<float>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_dmap_bf16, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace dct

@@ -1,0 +1,308 @@
+// Source assembly and the device-driven group / iteration machine.
+//
+// Each right-hand side b (one source position) carries its own state:
+// current group g, iterations done, and flags.  One "iteration set" is the
+// fixed launch sequence  transition -> M-map -> sweep -> D-map -> combine;
+// the host enqueues sets without knowing where each RHS stands, and every
+// kernel reads the RHS state to decide what to do.  This keeps the host out
+// of the inner loop (it only polls one counter now and then), gives each RHS
+// its own stopping point, and makes a set capturable in a HIP graph.
+//
+// transition: when the previous set finished group g-1 of b (pending = 1) it
+//   closes the balance of group g-1 and builds the fixed source of group g:
+//   first-collision source (Sec. II-A) + optional volumetric source + the
+//   downscatter from every converged higher group (eq. 2, g' < g), in that
+//   order, and starts the iteration from phi = 0.
+// combine: merges the two class-layout halves of the direction->moment map
+//   into phi (natural layout), measures the relative change of phi_00, builds
+//   the next within-group source Q = ext + sigma_s^{gg} phi in both class
+//   layouts, and (last block of b) applies the stopping rule.
+#include "dct_internal.h"
+
+namespace dct {
+
+__device__ inline int l_of(int lm)
+{
+    int l = 0;
+    while ((l + 1) * (l + 1) <= lm) ++l;
+    return l;
+}
+
+template <typename T>
+__device__ inline T *tptr(void *p) { return (T *)p; }
+template <typename T>
+__device__ inline const T *tptr(const void *p) { return (const T *)p; }
+
+__device__ inline double block_sum(double v, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    return t;   // valid on thread 0
+}
+
+__device__ inline double block_max(double v, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, red[i]);
+    return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_transition(TransArgs a)
+{
+    __shared__ double red[8];
+    const int b = blockIdx.y;
+    RhsState *st = a.state + b;
+    if (!st->pending) return;
+    const int g = st->g;
+    const Geo &geo = a.geo;
+    const long C = geo.C;
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    const bool inb = v < C;
+    const int G = a.G, L = a.L, Nm = a.Nm;
+    double Rp = 0.0, Pp = 0.0;
+    T *phi_all = (T *)a.phi_all;
+    if (inb) {
+        const int m = a.mat[v];
+        const double rho = a.rho[v];
+        if (g > 0) {
+            // removal of the finished group: (sigma_t - sigma_s0^{gg}) phi_00
+            const int gp = g - 1;
+            double s0 = rho * a.ss[(((long)m * (L + 1)) * G + gp) * G + gp];
+            double sig = rho * a.st[m * G + gp];
+            Rp = (sig - s0) * (double)phi_all[(((long)b * G + gp) * Nm) * C + v];
+        }
+        if (g < G) {
+            const int i = (int)(v % geo.nx);
+            const int j = (int)((v / geo.nx) % geo.ny);
+            const int k = (int)(v / ((long)geo.nx * geo.ny));
+            const double *p = a.pos + 3 * b;
+            double d0 = geo.org[0] + (i + 0.5) * geo.dx - p[0];
+            double d1 = geo.org[1] + (j + 0.5) * geo.dy - p[1];
+            double d2 = geo.org[2] + (k + 0.5) * geo.dz - p[2];
+            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            double Y[DCT_MAXNM];
+            real_sh_cart<double>(L, d0 / r, d1 / r, d2 / r, Y);
+            const long pA = cls_pos(0, i, j, k, geo.nx, geo.ny);
+            const long pB = cls_pos(1, i, j, k, geo.nx, geo.ny);
+            T *ext = (T *)a.ext + (long)b * Nm * C;
+            T *QA = (T *)a.Qc + (long)b * Nm * C;
+            T *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
+            for (int lm = 0; lm < Nm; ++lm) {
+                const int l = l_of(lm);
+                const double *sl = a.ss + ((long)m * (L + 1) + l) * G * G;
+                double e = 0.0;
+                // first-collision source, groups g' <= g in order
+                for (int gp = 0; gp <= g; ++gp) {
+                    double s = sl[gp * G + g];
+                    if (s != 0.0) e += rho * s * a.phi_u[((long)b * G + gp) * C + v] * Y[lm];
+                }
+                if (lm == 0 && a.ext_iso) e += a.ext_iso[(long)g * C + v];
+                // downscatter from converged higher-energy groups, in order
+                for (int gp = 0; gp < g; ++gp) {
+                    double s = sl[gp * G + g];
+                    if (s != 0.0) e += rho * s * (double)phi_all[(((long)b * G + gp) * Nm + lm) * C + v];
+                }
+                T et = (T)e;
+                ext[(long)lm * C + v] = et;
+                phi_all[(((long)b * G + g) * Nm + lm) * C + v] = (T)0;
+                QA[(long)lm * C + pA] = et;
+                QB[(long)lm * C + pB] = et;
+                if (lm == 0) Pp = e;
+            }
+        }
+    }
+    double Rs = block_sum(Rp, red);
+    double Ps = block_sum(Pp, red);
+    if (threadIdx.x == 0) {
+        if (g > 0) atomicAdd(&a.bal[((long)b * G + g - 1) * 3 + 1], Rs * a.V);
+        if (g < G) atomicAdd(&a.bal[((long)b * G + g) * 3 + 0], Ps * a.V);
+        if (blockIdx.x == 0) {
+            const double Ax = geo.dy * geo.dz, Ay = geo.dx * geo.dz, Az = geo.dx * geo.dy;
+            if (g > 0) {
+                double Lk = 0.0;
+                for (int n = 0; n < a.N; ++n) {
+                    double lx = 0, ly = 0, lz = 0;
+                    for (int q = 0; q < a.nblk; ++q) {
+                        const double *lp = a.leak_part + (((long)b * a.N + n) * a.nblk + q) * 3;
+                        lx += lp[0];
+                        ly += lp[1];
+                        lz += lp[2];
+                    }
+                    Lk += a.w[n] * (fabs(a.dirs[3 * n]) * Ax * lx + fabs(a.dirs[3 * n + 1]) * Ay * ly +
+                                    fabs(a.dirs[3 * n + 2]) * Az * lz);
+                }
+                a.bal[((long)b * G + g - 1) * 3 + 2] = Lk;
+            }
+            if (g < G && a.inflow && a.inflow[g] != 0.0) {
+                double Pin = 0.0;
+                for (int n = 0; n < a.N; ++n)
+                    Pin += a.w[n] * (fabs(a.dirs[3 * n]) * Ax * geo.ny * geo.nz +
+                                     fabs(a.dirs[3 * n + 1]) * Ay * geo.nx * geo.nz +
+                                     fabs(a.dirs[3 * n + 2]) * Az * geo.nx * geo.ny);
+                atomicAdd(&a.bal[((long)b * G + g) * 3 + 0], a.inflow[g] * Pin);
+            }
+        }
+        __threadfence();
+        unsigned prev = atomicAdd(&st->cnt_trans, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            st->cnt_trans = 0;
+            st->pending = 0;
+            if (g >= G) {
+                st->finished = 1;
+                atomicSub(a.n_unfinished, 1);
+            }
+        }
+    }
+}
+
+hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
+    if (is_f64) hipLaunchKernelGGL(k_transition<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_transition<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// LDS tile of one slab (z layer k, 16 consecutive y rows, all x) with an odd
+// row pitch so that the 16 lanes of a row segment hit distinct banks.
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine(CombArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T *tile = (T *)smem_raw;
+    __shared__ double red[8];
+    const int b = blockIdx.y;
+    RhsState *st = a.state + b;
+    if (st->finished) return;
+    const int g = st->g;
+    const int nx = a.geo.nx, ny = a.geo.ny;
+    const long C = a.geo.C;
+    const int G = a.G, Nm = a.Nm, L = a.L;
+    const int nslj = (ny + 15) >> 4;
+    const int k = blockIdx.x / nslj;
+    const int j0 = (blockIdx.x % nslj) * 16;
+    const int pitch = nx + 1;
+    const int tile_n = 16 * nx;
+    const T *partA = (const T *)a.part + (long)b * Nm * C;
+    const T *partB = (const T *)a.part + ((long)a.B + b) * Nm * C;
+    T *QA = (T *)a.Qc + (long)b * Nm * C;
+    T *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
+    const T *ext = (const T *)a.ext + (long)b * Nm * C;
+    T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
+    double dmax = 0.0, fmax_ = 0.0;
+    for (int lm = 0; lm < Nm; ++lm) {
+        const int l = l_of(lm);
+        // class A half, rotated rows -> natural tile
+        for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+            int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+            if (j < ny) {
+                int i = rot_row(1, r, j % nx, nx);          // inverse of (i + j) mod nx
+                long p = ((long)k * nx + r) * ny + j;
+                tile[jl * pitch + i] = partA[(long)lm * C + p];
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+            int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+            if (j < ny) {
+                int i = rot_row(0, r, j % nx, nx);          // inverse of (i - j) mod nx
+                long p = ((long)k * nx + r) * ny + j;
+                tile[jl * pitch + i] += partB[(long)lm * C + p];
+            }
+        }
+        __syncthreads();
+        // natural order: new moments, change of phi_00, next within-group source
+        for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+            int jl = idx / nx, i = idx - jl * nx, j = j0 + jl;
+            if (j < ny) {
+                long v = i + (long)nx * (j + (long)ny * k);
+                T pn = tile[jl * pitch + i];
+                if (lm == 0) {
+                    double old = (double)phib[v];
+                    double dn = fabs((double)pn - old);
+                    double an = fabs((double)pn);
+                    dmax = (dn > dmax || dn != dn) ? dn : dmax;
+                    fmax_ = (an > fmax_ || an != an) ? an : fmax_;
+                }
+                phib[(long)lm * C + v] = pn;
+                int m = a.mat[v];
+                double s = a.rho[v] * a.ss[(((long)m * (L + 1) + l) * G + g) * G + g];
+                tile[jl * pitch + i] = (T)((double)ext[(long)lm * C + v] + s * (double)pn);
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+            int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+            if (j < ny) {
+                int jm = j % nx;
+                long p = ((long)k * nx + r) * ny + j;
+                QA[(long)lm * C + p] = tile[jl * pitch + rot_row(1, r, jm, nx)];
+                QB[(long)lm * C + p] = tile[jl * pitch + rot_row(0, r, jm, nx)];
+            }
+        }
+        __syncthreads();
+    }
+    double dm = block_max(dmax, red);
+    double fm = block_max(fmax_, red);
+    if (threadIdx.x == 0) {
+        atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
+        atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
+        __threadfence();
+        unsigned prev = atomicAdd(&st->cnt_combine, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            double num = __longlong_as_double((long long)atomicAdd(&st->eps_num, 0ull));
+            double den = __longlong_as_double((long long)atomicAdd(&st->eps_den, 0ull));
+            int it = st->it + 1;
+            st->it = it;
+            bool bad = !isfinite(num) || !isfinite(den);
+            double e = den > 0.0 ? num / den : 0.0;
+            bool stop;
+            if (bad) {
+                st->nan = 1;
+                stop = true;
+            } else if (a.fixed_iters) {
+                stop = it >= a.fixed_iters[g];
+            } else {
+                stop = (e <= a.tol) || (it >= a.max_iter);
+                if (stop && e > a.tol) st->notconv = 1;
+            }
+            if (stop) {
+                a.iters[(long)b * G + g] = it;
+                a.eps[(long)b * G + g] = e;
+                st->g = bad ? G : g + 1;
+                st->it = 0;
+                st->pending = 1;
+            }
+            st->eps_num = 0ull;
+            st->eps_den = 0ull;
+            st->cnt_combine = 0;
+        }
+    }
+}
+
+hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s)
+{
+    const int nslj = (a.geo.ny + 15) >> 4;
+    dim3 grid((unsigned)(a.geo.nz * nslj), a.B);
+    size_t shm = (size_t)16 * (a.geo.nx + 1) * (is_f64 ? 8 : 4);
+    if (is_f64) hipLaunchKernelGGL(k_combine<double>, grid, dim3(256), shm, s, a);
+    else hipLaunchKernelGGL(k_combine<float>, grid, dim3(256), shm, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace dct

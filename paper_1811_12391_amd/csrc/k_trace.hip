@@ -1,0 +1,215 @@
+// Uncollided fluence by Siddon ray tracing, per-class cross-section tables,
+// and the dose tally.
+//
+// Uncollided fluence (first-collision paragraph of Sec. II-A; "calculated
+// analytically" in Sec. IV): phi_u,g(v) = w_g exp(-tau_g(v)) / (4 pi r^2)
+// with tau_g the optical depth along the straight segment from the source to
+// the centre of voxel v, zero outside the fan x cone window.  One thread per
+// (source, target voxel); neighbouring threads trace neighbouring rays, so the
+// density/material gathers of a wavefront hit the same cache lines.  The
+// optical depth is accumulated in FP64 as path length x density per material
+// (at most DCT_MAXMAT materials, kept in registers) and contracted with the
+// mass attenuation table at the end.
+#include "dct_internal.h"
+
+namespace dct {
+
+__global__ __launch_bounds__(256) void k_trace(TraceArgs a)
+{
+    const Geo &g = a.geo;
+    long v = (long)blockIdx.x * 256 + threadIdx.x;
+    int b = blockIdx.y;
+    if (v >= g.C) return;
+    int i = (int)(v % g.nx);
+    int j = (int)((v / g.nx) % g.ny);
+    int k = (int)(v / ((long)g.nx * g.ny));
+    const double del[3] = {g.dx, g.dy, g.dz};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const double *p = a.pos + 3 * b;
+    double d[3];
+    d[0] = g.org[0] + (i + 0.5) * g.dx - p[0];
+    d[1] = g.org[1] + (j + 0.5) * g.dy - p[1];
+    d[2] = g.org[2] + (k + 0.5) * g.dz - p[2];
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double r = sqrt(r2);
+    double *out = a.phi_u + (long)b * a.G * g.C + v;
+
+    // beam window: azimuth about z from the projected axis, elevation from z = 0
+    double ax = a.axis[3 * b], ay = a.axis[3 * b + 1];
+    double an = hypot(ax, ay);
+    ax /= an;
+    ay /= an;
+    double along = d[0] * ax + d[1] * ay;
+    double across = -d[0] * ay + d[1] * ax;
+    double az = atan2(across, along);
+    double el = atan2(d[2], hypot(d[0], d[1]));
+    if (!(fabs(az) <= a.half_fan && fabs(el) <= a.half_cone)) {
+        for (int gg = 0; gg < a.G; ++gg) out[(long)gg * g.C] = 0.0;
+        return;
+    }
+
+    // entry into the grid box (slab method); the target is inside the box
+    double a_in = 0.0;
+    for (int t = 0; t < 3; ++t) {
+        if (d[t] == 0.0) continue;
+        double t0 = (g.org[t] - p[t]) / d[t];
+        double t1 = (g.org[t] + nn[t] * del[t] - p[t]) / d[t];
+        double tmin = t0 < t1 ? t0 : t1;
+        if (tmin > a_in) a_in = tmin;
+    }
+    // first plane crossing strictly after the entry, per axis
+    double anext[3];
+    int mpl[3], stp[3];
+    for (int t = 0; t < 3; ++t) {
+        if (d[t] == 0.0) {
+            anext[t] = 2.0;
+            mpl[t] = 0;
+            stp[t] = 0;
+            continue;
+        }
+        stp[t] = d[t] > 0 ? 1 : -1;
+        double u = (p[t] + a_in * d[t] - g.org[t]) / del[t];
+        int m = d[t] > 0 ? (int)floor(u) + 1 : (int)ceil(u) - 1;
+        double tt = (g.org[t] + m * del[t] - p[t]) / d[t];
+        for (int guard = 0; guard < 4 && tt <= a_in; ++guard) {
+            m += stp[t];
+            tt = (g.org[t] + m * del[t] - p[t]) / d[t];
+        }
+        for (int guard = 0; guard < 4; ++guard) {
+            double tb = (g.org[t] + (m - stp[t]) * del[t] - p[t]) / d[t];
+            if (tb > a_in) {
+                m -= stp[t];
+                tt = tb;
+            } else {
+                break;
+            }
+        }
+        mpl[t] = m;
+        anext[t] = tt;
+    }
+
+    double acc[DCT_MAXMAT];
+#pragma unroll
+    for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] = 0.0;
+    double a0 = a_in;
+    const int cap = g.nx + g.ny + g.nz + 4;
+    for (int it = 0; it < cap; ++it) {
+        double a1 = fmin(anext[0], fmin(anext[1], anext[2]));
+        bool last = a1 >= 1.0;
+        if (last) a1 = 1.0;
+        double len = (a1 - a0) * r;
+        double mid = 0.5 * (a0 + a1);
+        int idx[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            int c = (int)floor((p[t] + mid * d[t] - g.org[t]) / del[t]);
+            idx[t] = c < 0 ? 0 : (c > nn[t] - 1 ? nn[t] - 1 : c);
+        }
+        long u = idx[0] + (long)g.nx * (idx[1] + (long)g.ny * idx[2]);
+        int m = a.mat[u];
+        double lr = len * a.rho[u];
+#pragma unroll
+        for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] += (m == mm) ? lr : 0.0;
+        if (last) break;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (anext[t] == a1) {
+                mpl[t] += stp[t];
+                anext[t] = (g.org[t] + mpl[t] * del[t] - p[t]) / d[t];
+            }
+        }
+        a0 = a1;
+    }
+    double inv = 1.0 / (4.0 * DCT_PI * r2);
+    for (int gg = 0; gg < a.G; ++gg) {
+        double tau = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < DCT_MAXMAT; ++mm)
+            if (mm < a.M) tau += a.st[mm * a.G + gg] * acc[mm];
+        out[(long)gg * g.C] = a.gw[gg] * exp(-tau) * inv;
+    }
+}
+
+hipError_t launch_trace(const TraceArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
+    hipLaunchKernelGGL(k_trace, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Total macroscopic cross section of every group in both sweep layouts:
+// sigc[cls][g][pos_cls(v)] = rho_v * sigma_t[m_v][g].
+template <typename T>
+__global__ __launch_bounds__(256) void k_sigc(Geo g, const uint8_t *mat, const double *rho, const double *st,
+                                              int G, T *sigc)
+{
+    long v = (long)blockIdx.x * 256 + threadIdx.x;
+    int gg = blockIdx.y;
+    if (v >= g.C) return;
+    int i = (int)(v % g.nx);
+    int j = (int)((v / g.nx) % g.ny);
+    int k = (int)(v / ((long)g.nx * g.ny));
+    T val = (T)(rho[v] * st[mat[v] * G + gg]);
+    sigc[(long)gg * g.C + cls_pos(0, i, j, k, g.nx, g.ny)] = val;
+    sigc[((long)G + gg) * g.C + cls_pos(1, i, j, k, g.nx, g.ny)] = val;
+}
+
+hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, const double *st, int G, int M,
+                       void *sigc, int is_f64, hipStream_t s)
+{
+    (void)M;
+    dim3 grid((unsigned)((g.C + 255) / 256), G);
+    if (is_f64) hipLaunchKernelGGL(k_sigc<double>, grid, dim3(256), 0, s, g, mat, rho, st, G, (double *)sigc);
+    else hipLaunchKernelGGL(k_sigc<float>, grid, dim3(256), 0, s, g, mat, rho, st, G, (float *)sigc);
+    return hipGetLastError();
+}
+
+// Dose tally (Sec. II-A: collision kerma as absorbed dose):
+// dose_b(v) = sum_g kappa_g[m_v] (phi_u,g(v) + phi_00,g(v)), summed in group order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dose(DoseArgs a)
+{
+    long v = (long)blockIdx.x * 256 + threadIdx.x;
+    if (v >= a.C) return;
+    const T *pa = (const T *)a.phi_all;
+    int m = a.mat[v];
+    double tot = 0.0;
+    for (int b = 0; b < a.B; ++b) {
+        double dsum = 0.0;
+        for (int g = 0; g < a.G; ++g) {
+            double pu = a.phi_u[((long)b * a.G + g) * a.C + v];
+            double pc = (double)pa[(((long)b * a.G + g) * a.Nm) * a.C + v];
+            dsum += a.kap[m * a.G + g] * (pu + pc);
+            if (a.phi_c) a.phi_c[((long)b * a.G + g) * a.C + v] = pc;
+            if (a.phi_u_out) a.phi_u_out[((long)b * a.G + g) * a.C + v] = pu;
+        }
+        if (a.summed) tot += dsum;
+        else a.dose[(long)b * a.C + v] = dsum;
+    }
+    if (a.summed) a.dose[v] = tot;
+}
+
+hipError_t launch_dose(const DoseArgs &a, int is_f64, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.C + 255) / 256));
+    if (is_f64) hipLaunchKernelGGL(k_dose<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_dose<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_widen(const T *src, long n, double *dst)
+{
+    long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) dst[t] = (double)src[t];
+}
+
+hipError_t launch_moments_out(const void *phi_all, long n, double *out, int is_f64, hipStream_t s)
+{
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (is_f64) hipLaunchKernelGGL(k_widen<double>, grid, dim3(256), 0, s, (const double *)phi_all, n, out);
+    else hipLaunchKernelGGL(k_widen<float>, grid, dim3(256), 0, s, (const float *)phi_all, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace dct

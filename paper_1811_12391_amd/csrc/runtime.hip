@@ -1,0 +1,890 @@
+// Host runtime of the dctsn library: the C ABI declared in include/dctsn.h.
+//
+// Input validation mirrors the "Launch Solver only with complete, consistent
+// input" rule of Sec. II-B: each set_* call checks its own arguments (EINVAL);
+// consistency between calls (material ids vs M, G of the source vs the cross
+// sections, sources inside the grid, P_N order vs the quadrature) is checked
+// when the solve starts (ESTATE).
+//
+// dct_solve enqueues, on the context's stream:
+//   sigma tables -> ray trace -> [transition, M map, sweep(s), D map, combine]*
+//   -> dose
+// where the bracket is one iteration set of the device-driven machine (see
+// k_source.hip).  The host enqueues sets in chunks and polls a single device
+// counter of unfinished right-hand sides one chunk behind, so the GPU never
+// waits for the host inside a solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dctsn.h"
+#include "dct_internal.h"
+
+using namespace dct;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct dct_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    bool has_geo = false, has_xs = false, has_quad = false, has_src = false;
+    int nx = 0, ny = 0, nz = 0;
+    double dx = 0, dy = 0, dz = 0, org[3] = {0, 0, 0};
+    std::vector<uint8_t> mat;
+    std::vector<double> rho;
+    int G = 0, M = 0, L = 0;
+    std::vector<double> st, ss, kap;
+    int N = 0;
+    std::vector<double> dirs, w;
+    int B = 0;
+    std::vector<double> pos, axis, gw;
+    double fan = 0, cone = 0;
+    std::vector<double> iso;
+
+    std::map<std::string, DevBuf> bufs;
+    bool dev_dirty = true;      // inputs changed since the last upload
+    int tab_prec = -1;          // precision of the uploaded moment-map tables
+    bool solved = false;
+    int solved_prec = 0;
+    int solved_Nm = 0;
+
+    std::vector<hipEvent_t> evpool;
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    int *h_unf = nullptr;
+    void *h_stage = nullptr;
+    size_t h_stage_bytes = 0;
+};
+
+static int fail(dct_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HC(call)                                                                                  \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? DCT_ENOMEM : DCT_EDEVICE,                \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                      \
+    } while (0)
+
+static hipError_t dbuf(dct_ctx *ctx, const std::string &name, size_t bytes, void **out)
+{
+    DevBuf &b = ctx->bufs[name];
+    if (bytes == 0) bytes = 256;
+    if (b.bytes < bytes) {
+        if (b.p) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        hipError_t e = hipMalloc(&b.p, bytes);
+        if (e != hipSuccess) return e;
+        b.bytes = bytes;
+    }
+    *out = b.p;
+    return hipSuccess;
+}
+
+static bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+static void invalidate(dct_ctx *ctx)
+{
+    ctx->solved = false;
+    ctx->dev_dirty = true;
+    ctx->tab_prec = -1;
+}
+
+extern "C" {
+
+int dct_create(dct_ctx **out, int device, void *stream)
+{
+    if (!out) {
+        g_create_error = "dct_create: out is NULL";
+        return DCT_EINVAL;
+    }
+    *out = nullptr;
+    dct_ctx *ctx = nullptr;
+    try {
+        ctx = new dct_ctx();
+    } catch (const std::bad_alloc &) {
+        g_create_error = "dct_create: out of host memory";
+        return DCT_ENOMEM;
+    }
+    ctx->device = device;
+    if (device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || device >= n) {
+            g_create_error = std::string("dct_create: no HIP device ") + std::to_string(device) + " (" +
+                             (e != hipSuccess ? hipGetErrorString(e) : "device index out of range") + ")";
+            delete ctx;
+            return DCT_EDEVICE;
+        }
+        e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[0]);
+        if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[1]);
+        if (e == hipSuccess) e = hipEventCreate(&ctx->ev_t0);
+        if (e == hipSuccess) e = hipEventCreate(&ctx->ev_t1);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->h_unf, 4 * sizeof(int), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            g_create_error = std::string("dct_create: ") + hipGetErrorString(e);
+            delete ctx;
+            return DCT_EDEVICE;
+        }
+        ctx->stream = (hipStream_t)stream;
+    }
+    g_create_error.clear();
+    *out = ctx;
+    return DCT_OK;
+}
+
+int dct_destroy(dct_ctx *ctx)
+{
+    if (!ctx) return DCT_OK;
+    if (ctx->device >= 0) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto &kv : ctx->bufs)
+            if (kv.second.p) (void)hipFree(kv.second.p);
+        for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {ctx->ev_poll[0], ctx->ev_poll[1], ctx->ev_t0, ctx->ev_t1})
+            if (e) (void)hipEventDestroy(e);
+        if (ctx->h_unf) (void)hipHostFree(ctx->h_unf);
+        if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    }
+    delete ctx;
+    return DCT_OK;
+}
+
+const char *dct_last_error(const dct_ctx *ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy, double dz,
+                     const double *origin, const uint8_t *material, const double *density)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, DCT_EINVAL, "set_geometry: nx, ny, nz must be > 0");
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(dz))
+        return fail(ctx, DCT_EINVAL, "set_geometry: voxel sizes must be finite and > 0");
+    if (nx > 4096 || ny > 4096 || nz > 4096 || (double)nx * ny * nz > 2.0e9)
+        return fail(ctx, DCT_EINVAL, "set_geometry: grid too large");
+    if (!origin || !material || !density) return fail(ctx, DCT_EINVAL, "set_geometry: NULL array");
+    if (!finite_all(origin, 3)) return fail(ctx, DCT_EINVAL, "set_geometry: origin not finite");
+    size_t C = (size_t)nx * ny * nz;
+    for (size_t v = 0; v < C; ++v)
+        if (!std::isfinite(density[v]) || density[v] < 0)
+            return fail(ctx, DCT_EINVAL, "set_geometry: density must be finite and >= 0 (voxel " +
+                                             std::to_string(v) + ")");
+    try {
+        ctx->mat.assign(material, material + C);
+        ctx->rho.assign(density, density + C);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DCT_ENOMEM, "set_geometry: out of host memory");
+    }
+    ctx->nx = nx;
+    ctx->ny = ny;
+    ctx->nz = nz;
+    ctx->dx = dx;
+    ctx->dy = dy;
+    ctx->dz = dz;
+    std::memcpy(ctx->org, origin, sizeof(ctx->org));
+    ctx->has_geo = true;
+    ctx->iso.clear();
+    invalidate(ctx);
+    return DCT_OK;
+}
+
+int dct_set_xs(dct_ctx *ctx, int G, const double *edges_keV, int M, int L, const double *sigma_t,
+               const double *sigma_s, const double *kerma)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (G < 1 || G > 256) return fail(ctx, DCT_EINVAL, "set_xs: G must be in [1, 256]");
+    if (M < 1 || M > DCT_MAXMAT) return fail(ctx, DCT_EINVAL, "set_xs: M must be in [1, 8]");
+    if (L < 0 || L > DCT_MAXL) return fail(ctx, DCT_EINVAL, "set_xs: L must be in [0, 5]");
+    if (!sigma_t || !sigma_s || !kerma) return fail(ctx, DCT_EINVAL, "set_xs: NULL array");
+    if (edges_keV)
+        for (int g = 0; g < G; ++g)
+            if (!(edges_keV[g] > edges_keV[g + 1]))
+                return fail(ctx, DCT_EINVAL, "set_xs: edges must be strictly descending");
+    size_t nss = (size_t)M * (L + 1) * G * G;
+    if (!finite_all(sigma_t, (size_t)M * G) || !finite_all(sigma_s, nss) || !finite_all(kerma, (size_t)M * G))
+        return fail(ctx, DCT_EINVAL, "set_xs: non-finite value");
+    for (int i = 0; i < M * G; ++i)
+        if (sigma_t[i] < 0 || kerma[i] < 0) return fail(ctx, DCT_EINVAL, "set_xs: negative sigma_t or kerma");
+    for (int m = 0; m < M; ++m)
+        for (int l = 0; l <= L; ++l)
+            for (int gf = 0; gf < G; ++gf)
+                for (int gt = 0; gt < gf; ++gt)
+                    if (sigma_s[(((size_t)m * (L + 1) + l) * G + gf) * G + gt] != 0.0)
+                        return fail(ctx, DCT_EINVAL, "set_xs: upscatter entry sigma_s[" + std::to_string(m) +
+                                                         "][" + std::to_string(l) + "][" + std::to_string(gf) +
+                                                         "][" + std::to_string(gt) + "] != 0");
+    ctx->st.assign(sigma_t, sigma_t + (size_t)M * G);
+    ctx->ss.assign(sigma_s, sigma_s + nss);
+    ctx->kap.assign(kerma, kerma + (size_t)M * G);
+    ctx->G = G;
+    ctx->M = M;
+    ctx->L = L;
+    ctx->has_xs = true;
+    invalidate(ctx);
+    return DCT_OK;
+}
+
+int dct_set_quadrature(dct_ctx *ctx, int n, const double *dirs, const double *w)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (n < 1 || n > 4096) return fail(ctx, DCT_EINVAL, "set_quadrature: n must be in [1, 4096]");
+    if (!dirs || !w) return fail(ctx, DCT_EINVAL, "set_quadrature: explicit dirs and weights are required");
+    if (!finite_all(dirs, 3 * (size_t)n) || !finite_all(w, n))
+        return fail(ctx, DCT_EINVAL, "set_quadrature: non-finite value");
+    for (int i = 0; i < n; ++i) {
+        const double *o = dirs + 3 * i;
+        double nn = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+        if (std::fabs(nn - 1.0) > 1e-12) return fail(ctx, DCT_EINVAL, "set_quadrature: direction not unit length");
+        if (o[0] == 0.0 || o[1] == 0.0 || o[2] == 0.0)
+            return fail(ctx, DCT_EINVAL, "set_quadrature: direction with a zero component");
+        if (!(w[i] > 0)) return fail(ctx, DCT_EINVAL, "set_quadrature: weights must be > 0");
+    }
+    ctx->dirs.assign(dirs, dirs + 3 * (size_t)n);
+    ctx->w.assign(w, w + n);
+    ctx->N = n;
+    ctx->has_quad = true;
+    invalidate(ctx);
+    return DCT_OK;
+}
+
+int dct_set_source(dct_ctx *ctx, int B, const double *pos, const double *axis, double fan_deg, double cone_deg,
+                   const double *group_w)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!ctx->has_xs) return fail(ctx, DCT_ESTATE, "set_source: call set_xs first (group weights need G)");
+    if (B < 1 || B > 65535) return fail(ctx, DCT_EINVAL, "set_source: B must be in [1, 65535]");
+    if (!pos || !group_w) return fail(ctx, DCT_EINVAL, "set_source: NULL array");
+    if (!(fan_deg > 0 && fan_deg <= 360) || !(cone_deg > 0 && cone_deg <= 180))
+        return fail(ctx, DCT_EINVAL, "set_source: fan must be in (0, 360], cone in (0, 180] degrees");
+    if (!finite_all(pos, 3 * (size_t)B) || !finite_all(group_w, ctx->G) || (axis && !finite_all(axis, 3 * (size_t)B)))
+        return fail(ctx, DCT_EINVAL, "set_source: non-finite value");
+    for (int g = 0; g < ctx->G; ++g)
+        if (group_w[g] < 0) return fail(ctx, DCT_EINVAL, "set_source: negative group weight");
+    std::vector<double> ax(3 * (size_t)B);
+    for (int b = 0; b < B; ++b) {
+        double a0, a1, a2;
+        if (axis) {
+            a0 = axis[3 * b];
+            a1 = axis[3 * b + 1];
+            a2 = axis[3 * b + 2];
+        } else {
+            a0 = -pos[3 * b];
+            a1 = -pos[3 * b + 1];
+            a2 = 0.0;
+        }
+        if (std::hypot(a0, a1) == 0.0)
+            return fail(ctx, DCT_EINVAL, "set_source: beam axis has no component in the z = 0 plane");
+        ax[3 * b] = a0;
+        ax[3 * b + 1] = a1;
+        ax[3 * b + 2] = a2;
+    }
+    ctx->pos.assign(pos, pos + 3 * (size_t)B);
+    ctx->axis = ax;
+    ctx->gw.assign(group_w, group_w + ctx->G);
+    ctx->fan = fan_deg;
+    ctx->cone = cone_deg;
+    ctx->B = B;
+    ctx->has_src = true;
+    invalidate(ctx);
+    return DCT_OK;
+}
+
+int dct_set_volume_source(dct_ctx *ctx, const double *S)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!S) {
+        ctx->iso.clear();
+        invalidate(ctx);
+        return DCT_OK;
+    }
+    if (!ctx->has_geo || !ctx->has_xs) return fail(ctx, DCT_ESTATE, "set_volume_source: set geometry and xs first");
+    size_t n = (size_t)ctx->G * ctx->nx * ctx->ny * ctx->nz;
+    if (!finite_all(S, n)) return fail(ctx, DCT_EINVAL, "set_volume_source: non-finite value");
+    ctx->iso.assign(S, S + n);
+    invalidate(ctx);
+    return DCT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- solve
+namespace {
+
+struct Plan {
+    int prec = 0, Nm = 0, Nc[2] = {0, 0}, NcP = 0, NmP = 0;
+    int BK = 1, NBJ = 1, NBK = 1, nblk = 1, ndiag = 1;
+    size_t tsz = 8;
+    std::vector<int> cdir;   // [2][N]
+};
+
+static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
+{
+    if (!ctx->has_geo || !ctx->has_xs || !ctx->has_quad || !ctx->has_src)
+        return fail(ctx, DCT_ESTATE, std::string("solve: missing input:") + (ctx->has_geo ? "" : " geometry") +
+                                         (ctx->has_xs ? "" : " cross-sections") + (ctx->has_quad ? "" : " quadrature") +
+                                         (ctx->has_src ? "" : " source"));
+    if ((int)ctx->gw.size() != ctx->G)
+        return fail(ctx, DCT_ESTATE, "solve: source group weights were given for a different G; call set_source again");
+    if (!ctx->iso.empty() && ctx->iso.size() != (size_t)ctx->G * ctx->nx * ctx->ny * ctx->nz)
+        return fail(ctx, DCT_ESTATE, "solve: volume source shape does not match the current G and grid");
+    for (uint8_t m : ctx->mat)
+        if ((int)m >= ctx->M) return fail(ctx, DCT_ESTATE, "solve: material id >= M");
+    for (int b = 0; b < ctx->B; ++b) {
+        const double *p = &ctx->pos[3 * b];
+        double hi[3] = {ctx->org[0] + ctx->nx * ctx->dx, ctx->org[1] + ctx->ny * ctx->dy, ctx->org[2] + ctx->nz * ctx->dz};
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) inside = inside && p[a] >= ctx->org[a] && p[a] <= hi[a];
+        if (inside) return fail(ctx, DCT_ESTATE, "solve: source " + std::to_string(b) + " lies inside the voxel grid");
+    }
+    if (o.precision < DCT_FP64 || o.precision > DCT_FP32_BF16MAP) return fail(ctx, DCT_EINVAL, "solve: bad precision");
+    if (o.max_iter < 1) return fail(ctx, DCT_EINVAL, "solve: max_iter must be >= 1");
+    if (!(o.tol >= 0) || !std::isfinite(o.tol)) return fail(ctx, DCT_EINVAL, "solve: tol must be finite and >= 0");
+    if (o.fixed_iters)
+        for (int g = 0; g < ctx->G; ++g)
+            if (o.fixed_iters[g] < 1 || o.fixed_iters[g] > 1000000)
+                return fail(ctx, DCT_EINVAL, "solve: fixed_iters entries must be in [1, 1e6]");
+    if (o.test_inflow && !finite_all(o.test_inflow, ctx->G))
+        return fail(ctx, DCT_EINVAL, "solve: test_inflow not finite");
+
+    const int L = ctx->L, N = ctx->N;
+    const int Nm = (L + 1) * (L + 1);
+    pl.Nm = Nm;
+    pl.prec = o.precision;
+    pl.tsz = o.precision == DCT_FP64 ? 8 : 4;
+    if ((size_t)16 * (ctx->nx + 1) * pl.tsz > 65536)
+        return fail(ctx, DCT_EINVAL, "solve: nx too large for the 64 KiB combine tile (nx <= 511 in FP64, 1023 in FP32)");
+    // moment maps and the check that the quadrature integrates them: D M = I
+    std::vector<double> Y((size_t)N * Nm);
+    for (int n = 0; n < N; ++n)
+        real_sh_cart<double>(L, ctx->dirs[3 * n], ctx->dirs[3 * n + 1], ctx->dirs[3 * n + 2], &Y[(size_t)n * Nm]);
+    double worst = 0.0;
+    for (int a = 0; a < Nm; ++a) {
+        int la = 0;
+        while ((la + 1) * (la + 1) <= a) ++la;
+        for (int bb = 0; bb < Nm; ++bb) {
+            int lb = 0;
+            while ((lb + 1) * (lb + 1) <= bb) ++lb;
+            double s = 0.0;
+            for (int n = 0; n < N; ++n)
+                s += ctx->w[n] * Y[(size_t)n * Nm + a] * (2.0 * lb + 1.0) / (4.0 * DCT_PI) * Y[(size_t)n * Nm + bb];
+            worst = std::max(worst, std::fabs(s - (a == bb ? 1.0 : 0.0)));
+        }
+    }
+    if (worst > 1e-10)
+        return fail(ctx, DCT_ESTATE, "solve: the quadrature does not integrate the P_" + std::to_string(L) +
+                                         " moments (|D M - I| = " + std::to_string(worst) + "); lower L or refine S_N");
+    pl.cdir.assign(2 * (size_t)N, 0);
+    for (int n = 0; n < N; ++n) {
+        int c = dir_class(ctx->dirs[3 * n], ctx->dirs[3 * n + 1]);
+        pl.cdir[(size_t)c * N + pl.Nc[c]++] = n;
+    }
+    pl.NcP = 16 * ((std::max(pl.Nc[0], pl.Nc[1]) + 15) / 16);
+    if (pl.NcP == 0) pl.NcP = 16;
+    pl.NmP = 16 * ((Nm + 15) / 16);
+    pl.BK = std::min(16, ctx->nz);
+    pl.NBJ = (ctx->ny + 63) / 64;
+    pl.NBK = (ctx->nz + pl.BK - 1) / pl.BK;
+    pl.nblk = pl.NBJ * pl.NBK;
+    pl.ndiag = pl.NBJ + pl.NBK - 1;
+    return DCT_OK;
+}
+
+static uint16_t bf16_bits(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    dct_opts o;
+    if (opts) o = *opts;
+    else {
+        std::memset(&o, 0, sizeof(o));
+        o.precision = DCT_FP64;
+        o.tol = 1e-6;
+        o.max_iter = 1000;
+        o.fixup = 1;
+    }
+    if (ctx->device < 0) return fail(ctx, DCT_EDEVICE, "solve: host-only context (created with device = -1)");
+    Plan pl;
+    int rc = check_consistency(ctx, o, pl);
+    if (rc != DCT_OK) return rc;
+    ctx->solved = false;
+    HC(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz, G = ctx->G, M = ctx->M, L = ctx->L, N = ctx->N, B = ctx->B;
+    const long C = (long)nx * ny * nz;
+    const int Nm = pl.Nm;
+    const size_t ts = pl.tsz;
+    const int is64 = o.precision == DCT_FP64;
+    const int mode = o.precision == DCT_FP64 ? 0 : (o.precision == DCT_FP32 ? 1 : 2);
+
+    // ---------------- device buffers
+    void *d_mat, *d_rho, *d_st, *d_ss, *d_kap, *d_pos, *d_axis, *d_gw, *d_dirs, *d_w, *d_cdir, *d_Mt, *d_Dt;
+    void *d_iso = nullptr, *d_infl = nullptr, *d_fixed = nullptr;
+    void *d_phiu, *d_sigc, *d_ext, *d_Qc, *d_q, *d_psi, *d_part, *d_phi, *d_yf, *d_zf, *d_leak, *d_state, *d_bal,
+        *d_iters, *d_eps, *d_unf, *d_dose;
+    HC(dbuf(ctx, "mat", C, &d_mat));
+    HC(dbuf(ctx, "rho", C * 8, &d_rho));
+    HC(dbuf(ctx, "st", ctx->st.size() * 8, &d_st));
+    HC(dbuf(ctx, "ss", ctx->ss.size() * 8, &d_ss));
+    HC(dbuf(ctx, "kap", ctx->kap.size() * 8, &d_kap));
+    HC(dbuf(ctx, "pos", ctx->pos.size() * 8, &d_pos));
+    HC(dbuf(ctx, "axis", ctx->axis.size() * 8, &d_axis));
+    HC(dbuf(ctx, "gw", ctx->gw.size() * 8, &d_gw));
+    HC(dbuf(ctx, "dirs", ctx->dirs.size() * 8, &d_dirs));
+    HC(dbuf(ctx, "w", ctx->w.size() * 8, &d_w));
+    HC(dbuf(ctx, "cdir", pl.cdir.size() * 4, &d_cdir));
+    const size_t tabsz = (size_t)2 * pl.NcP * pl.NmP * (mode == 2 ? 2 : ts);
+    HC(dbuf(ctx, "Mt", tabsz, &d_Mt));
+    HC(dbuf(ctx, "Dt", tabsz, &d_Dt));
+    if (!ctx->iso.empty()) HC(dbuf(ctx, "iso", ctx->iso.size() * 8, &d_iso));
+    if (o.test_inflow) HC(dbuf(ctx, "infl", (size_t)G * 8, &d_infl));
+    if (o.fixed_iters) HC(dbuf(ctx, "fixed", (size_t)G * 4, &d_fixed));
+    HC(dbuf(ctx, "phiu", (size_t)B * G * C * 8, &d_phiu));
+    HC(dbuf(ctx, "sigc", (size_t)2 * G * C * ts, &d_sigc));
+    HC(dbuf(ctx, "ext", (size_t)B * Nm * C * ts, &d_ext));
+    HC(dbuf(ctx, "Qc", (size_t)2 * B * Nm * C * ts, &d_Qc));
+    HC(dbuf(ctx, "q", (size_t)B * N * C * ts, &d_q));
+    HC(dbuf(ctx, "psi", (size_t)B * N * C * ts, &d_psi));
+    HC(dbuf(ctx, "part", (size_t)2 * B * Nm * C * ts, &d_part));
+    HC(dbuf(ctx, "phi", (size_t)B * G * Nm * C * ts, &d_phi));
+    HC(dbuf(ctx, "yf", pl.NBJ > 1 ? (size_t)B * N * nx * nz * ts : 0, &d_yf));
+    HC(dbuf(ctx, "zf", pl.NBK > 1 ? (size_t)B * N * nx * ny * ts : 0, &d_zf));
+    HC(dbuf(ctx, "leak", (size_t)B * N * pl.nblk * 3 * 8, &d_leak));
+    HC(dbuf(ctx, "state", (size_t)B * sizeof(RhsState), &d_state));
+    HC(dbuf(ctx, "bal", (size_t)B * G * 3 * 8, &d_bal));
+    HC(dbuf(ctx, "iters", (size_t)B * G * 4, &d_iters));
+    HC(dbuf(ctx, "eps", (size_t)B * G * 8, &d_eps));
+    HC(dbuf(ctx, "unf", 256, &d_unf));
+    HC(dbuf(ctx, "dose", (size_t)B * C * 8, &d_dose));
+
+    // ---------------- inputs: uploaded once, kept on the device until a set_* call
+    if (ctx->dev_dirty || ctx->tab_prec != o.precision) {
+        std::vector<unsigned char> Mt(tabsz, 0), Dt(tabsz, 0);
+        std::vector<double> Y(Nm);
+        for (int c = 0; c < 2; ++c)
+            for (int nl = 0; nl < pl.Nc[c]; ++nl) {
+                int n = pl.cdir[(size_t)c * N + nl];
+                real_sh_cart<double>(L, ctx->dirs[3 * n], ctx->dirs[3 * n + 1], ctx->dirs[3 * n + 2], Y.data());
+                for (int lm = 0; lm < Nm; ++lm) {
+                    int l = 0;
+                    while ((l + 1) * (l + 1) <= lm) ++l;
+                    double mv = (2.0 * l + 1.0) / (4.0 * DCT_PI) * Y[lm];
+                    double dv = ctx->w[n] * Y[lm];
+                    size_t im = ((size_t)c * pl.NcP + nl) * pl.NmP + lm;
+                    size_t id = ((size_t)c * pl.NmP + lm) * pl.NcP + nl;
+                    if (mode == 0) {
+                        ((double *)Mt.data())[im] = mv;
+                        ((double *)Dt.data())[id] = dv;
+                    } else if (mode == 1) {
+                        ((float *)Mt.data())[im] = (float)mv;
+                        ((float *)Dt.data())[id] = (float)dv;
+                    } else {
+                        ((uint16_t *)Mt.data())[im] = bf16_bits(mv);
+                        ((uint16_t *)Dt.data())[id] = bf16_bits(dv);
+                    }
+                }
+            }
+        HC(hipMemcpyAsync(d_Mt, Mt.data(), tabsz, hipMemcpyHostToDevice, s));
+        HC(hipMemcpyAsync(d_Dt, Dt.data(), tabsz, hipMemcpyHostToDevice, s));
+        if (ctx->dev_dirty) {
+            HC(hipMemcpyAsync(d_mat, ctx->mat.data(), C, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_rho, ctx->rho.data(), C * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_st, ctx->st.data(), ctx->st.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_ss, ctx->ss.data(), ctx->ss.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_kap, ctx->kap.data(), ctx->kap.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_pos, ctx->pos.data(), ctx->pos.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_axis, ctx->axis.data(), ctx->axis.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_gw, ctx->gw.data(), ctx->gw.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_dirs, ctx->dirs.data(), ctx->dirs.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_w, ctx->w.data(), ctx->w.size() * 8, hipMemcpyHostToDevice, s));
+            HC(hipMemcpyAsync(d_cdir, pl.cdir.data(), pl.cdir.size() * 4, hipMemcpyHostToDevice, s));
+            if (d_iso) HC(hipMemcpyAsync(d_iso, ctx->iso.data(), ctx->iso.size() * 8, hipMemcpyHostToDevice, s));
+        }
+        HC(hipStreamSynchronize(s));   // host tables must outlive the copies
+        ctx->dev_dirty = false;
+        ctx->tab_prec = o.precision;
+    }
+    // per-solve options and the initial state of every right-hand side (small,
+    // from pinned host memory so the copies are truly asynchronous)
+    {
+        size_t need = (size_t)B * sizeof(RhsState) + (size_t)G * 12 + 64;
+        if (ctx->h_stage_bytes < need) {
+            if (ctx->h_stage) HC(hipHostFree(ctx->h_stage));
+            ctx->h_stage = nullptr;
+            ctx->h_stage_bytes = 0;
+            HC(hipHostMalloc(&ctx->h_stage, need, hipHostMallocDefault));
+            ctx->h_stage_bytes = need;
+        }
+        HC(hipEventSynchronize(ctx->ev_t1));   // the previous solve no longer reads the staging area
+        unsigned char *hs = (unsigned char *)ctx->h_stage;
+        RhsState *hst = (RhsState *)hs;
+        for (int b = 0; b < B; ++b) {
+            std::memset(&hst[b], 0, sizeof(RhsState));
+            hst[b].pending = 1;
+        }
+        size_t off = (size_t)B * sizeof(RhsState);
+        int *hunf = (int *)(hs + off);
+        *hunf = B;
+        off += 8;
+        HC(hipMemcpyAsync(d_state, hst, (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
+        HC(hipMemcpyAsync(d_unf, hunf, 4, hipMemcpyHostToDevice, s));
+        if (d_infl) {
+            std::memcpy(hs + off, o.test_inflow, (size_t)G * 8);
+            HC(hipMemcpyAsync(d_infl, hs + off, (size_t)G * 8, hipMemcpyHostToDevice, s));
+            off += (size_t)G * 8;
+        }
+        if (d_fixed) {
+            std::memcpy(hs + off, o.fixed_iters, (size_t)G * 4);
+            HC(hipMemcpyAsync(d_fixed, hs + off, (size_t)G * 4, hipMemcpyHostToDevice, s));
+        }
+    }
+    HC(hipMemsetAsync(d_bal, 0, (size_t)B * G * 3 * 8, s));
+    HC(hipMemsetAsync(d_iters, 0, (size_t)B * G * 4, s));
+    HC(hipMemsetAsync(d_eps, 0, (size_t)B * G * 8, s));
+    HC(hipMemsetAsync(d_leak, 0, (size_t)B * N * pl.nblk * 3 * 8, s));
+
+    Geo geo;
+    geo.nx = nx;
+    geo.ny = ny;
+    geo.nz = nz;
+    geo.C = C;
+    geo.dx = ctx->dx;
+    geo.dy = ctx->dy;
+    geo.dz = ctx->dz;
+    std::memcpy(geo.org, ctx->org, sizeof(geo.org));
+
+    HC(hipEventRecord(ctx->ev_t0, s));
+    HC(launch_sigc(geo, (const uint8_t *)d_mat, (const double *)d_rho, (const double *)d_st, G, M, d_sigc, is64, s));
+    {
+        TraceArgs ta;
+        ta.geo = geo;
+        ta.mat = (const uint8_t *)d_mat;
+        ta.rho = (const double *)d_rho;
+        ta.st = (const double *)d_st;
+        ta.G = G;
+        ta.M = M;
+        ta.B = B;
+        ta.pos = (const double *)d_pos;
+        ta.axis = (const double *)d_axis;
+        ta.half_fan = ctx->fan * DCT_PI / 360.0;
+        ta.half_cone = ctx->cone * DCT_PI / 360.0;
+        ta.gw = (const double *)d_gw;
+        ta.phi_u = (double *)d_phiu;
+        HC(launch_trace(ta, s));
+    }
+
+    TransArgs tr;
+    tr.geo = geo;
+    tr.G = G;
+    tr.M = M;
+    tr.L = L;
+    tr.Nm = Nm;
+    tr.N = N;
+    tr.B = B;
+    tr.V = ctx->dx * ctx->dy * ctx->dz;
+    tr.mat = (const uint8_t *)d_mat;
+    tr.rho = (const double *)d_rho;
+    tr.st = (const double *)d_st;
+    tr.ss = (const double *)d_ss;
+    tr.pos = (const double *)d_pos;
+    tr.phi_u = (const double *)d_phiu;
+    tr.ext_iso = (const double *)d_iso;
+    tr.inflow = (const double *)d_infl;
+    tr.dirs = (const double *)d_dirs;
+    tr.w = (const double *)d_w;
+    tr.leak_part = (const double *)d_leak;
+    tr.nblk = pl.nblk;
+    tr.phi_all = d_phi;
+    tr.ext = d_ext;
+    tr.Qc = d_Qc;
+    tr.state = (RhsState *)d_state;
+    tr.bal = (double *)d_bal;
+    tr.n_unfinished = (int *)d_unf;
+
+    MapArgs ma;
+    ma.C = C;
+    ma.B = B;
+    ma.N = N;
+    ma.Nm = Nm;
+    ma.Nc[0] = pl.Nc[0];
+    ma.Nc[1] = pl.Nc[1];
+    ma.cdir = (const int *)d_cdir;
+    ma.Mtab = d_Mt;
+    ma.Dtab = d_Dt;
+    ma.NcP = pl.NcP;
+    ma.NmP = pl.NmP;
+    ma.Qc = d_Qc;
+    ma.q = d_q;
+    ma.psi = d_psi;
+    ma.part = d_part;
+    ma.state = (const RhsState *)d_state;
+
+    SweepArgs sw;
+    sw.nx = nx;
+    sw.ny = ny;
+    sw.nz = nz;
+    sw.C = C;
+    sw.N = N;
+    sw.B = B;
+    sw.G = G;
+    sw.BK = pl.BK;
+    sw.NBJ = pl.NBJ;
+    sw.NBK = pl.NBK;
+    sw.nblk = pl.nblk;
+    sw.dirs = (const double *)d_dirs;
+    sw.dx = ctx->dx;
+    sw.dy = ctx->dy;
+    sw.dz = ctx->dz;
+    sw.q = d_q;
+    sw.psi = d_psi;
+    sw.sigc = d_sigc;
+    sw.yface = d_yf;
+    sw.zface = d_zf;
+    sw.leak_part = (double *)d_leak;
+    sw.state = (const RhsState *)d_state;
+    sw.inflow = (const double *)d_infl;
+    sw.fixup = o.fixup;
+
+    CombArgs cb;
+    cb.geo = geo;
+    cb.G = G;
+    cb.L = L;
+    cb.Nm = Nm;
+    cb.B = B;
+    cb.mat = (const uint8_t *)d_mat;
+    cb.rho = (const double *)d_rho;
+    cb.ss = (const double *)d_ss;
+    cb.part = d_part;
+    cb.ext = d_ext;
+    cb.phi_all = d_phi;
+    cb.Qc = d_Qc;
+    cb.state = (RhsState *)d_state;
+    cb.iters = (int *)d_iters;
+    cb.eps = (double *)d_eps;
+    cb.fixed_iters = (const int *)d_fixed;
+    cb.tol = o.tol;
+    cb.max_iter = o.max_iter;
+
+    // upper bound of iteration sets: every group at its cap plus one transition each
+    long cap_sets = 2;
+    for (int g = 0; g < G; ++g) cap_sets += (o.fixed_iters ? o.fixed_iters[g] : o.max_iter) + 1;
+    const int chunk = o.chunk > 0 ? o.chunk : 4;
+    int nprof = 0;
+    auto enqueue_set = [&]() -> hipError_t {
+        hipError_t e = launch_transition(tr, is64, s);
+        if (e != hipSuccess) return e;
+        if ((e = launch_mmap(ma, mode, s)) != hipSuccess) return e;
+        for (int d = 0; d < pl.ndiag; ++d) {
+            sw.diag = d;
+            if (o.profile) {
+                while ((int)ctx->evpool.size() < 2 * (nprof + 1)) {
+                    hipEvent_t ev;
+                    if ((e = hipEventCreate(&ev)) != hipSuccess) return e;
+                    ctx->evpool.push_back(ev);
+                }
+                if ((e = hipEventRecord(ctx->evpool[2 * nprof], s)) != hipSuccess) return e;
+            }
+            if ((e = launch_sweep(sw, is64, s)) != hipSuccess) return e;
+            if (o.profile) {
+                if ((e = hipEventRecord(ctx->evpool[2 * nprof + 1], s)) != hipSuccess) return e;
+                ++nprof;
+            }
+        }
+        if ((e = launch_dmap(ma, mode, s)) != hipSuccess) return e;
+        return launch_combine(cb, is64, s);
+    };
+
+    long sets = 0;
+    int kpoll = 0;
+    bool done = false;
+    while (sets < cap_sets && !done) {
+        for (int c = 0; c < chunk && sets < cap_sets; ++c, ++sets) HC(enqueue_set());
+        HC(hipMemcpyAsync(&ctx->h_unf[kpoll & 1], d_unf, 4, hipMemcpyDeviceToHost, s));
+        HC(hipEventRecord(ctx->ev_poll[kpoll & 1], s));
+        if (kpoll > 0) {
+            HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
+            if (ctx->h_unf[(kpoll - 1) & 1] == 0) done = true;
+        }
+        ++kpoll;
+    }
+    HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
+    int unfinished = ctx->h_unf[(kpoll - 1) & 1];
+
+    DoseArgs da;
+    da.C = C;
+    da.G = G;
+    da.B = B;
+    da.Nm = Nm;
+    da.mat = (const uint8_t *)d_mat;
+    da.kap = (const double *)d_kap;
+    da.phi_u = (const double *)d_phiu;
+    da.phi_all = d_phi;
+    da.dose = (double *)d_dose;
+    da.phi_c = nullptr;
+    da.phi_u_out = nullptr;
+    da.summed = 0;
+    HC(launch_dose(da, is64, s));
+    HC(hipEventRecord(ctx->ev_t1, s));
+    HC(hipEventSynchronize(ctx->ev_t1));
+
+    std::vector<RhsState> fin(B);
+    HC(hipMemcpy(fin.data(), d_state, (size_t)B * sizeof(RhsState), hipMemcpyDeviceToHost));
+    std::vector<int> iters((size_t)B * G);
+    HC(hipMemcpy(iters.data(), d_iters, iters.size() * 4, hipMemcpyDeviceToHost));
+    int status = DCT_OK;
+    bool any_nan = false, any_nc = false;
+    for (int b = 0; b < B; ++b) {
+        any_nan = any_nan || fin[b].nan;
+        any_nc = any_nc || fin[b].notconv;
+    }
+    if (stats) {
+        if (stats->iters) std::memcpy(stats->iters, iters.data(), iters.size() * 4);
+        if (stats->eps) HC(hipMemcpy(stats->eps, d_eps, (size_t)B * G * 8, hipMemcpyDeviceToHost));
+        if (stats->balance) HC(hipMemcpy(stats->balance, d_bal, (size_t)B * G * 3 * 8, hipMemcpyDeviceToHost));
+        long long upd = 0;
+        for (size_t i = 0; i < iters.size(); ++i) upd += (long long)iters[i] * C * N;
+        stats->sweep_updates = upd;
+        float ms = 0;
+        HC(hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+        stats->solve_ms = ms;
+        double swms = 0;
+        for (int i = 0; i < nprof; ++i) {
+            float t = 0;
+            HC(hipEventElapsedTime(&t, ctx->evpool[2 * i], ctx->evpool[2 * i + 1]));
+            swms += t;
+        }
+        stats->sweep_ms = swms;
+        stats->sweep_launches = nprof;
+        stats->iteration_sets = (int)sets;
+    }
+    ctx->solved = true;
+    ctx->solved_prec = o.precision;
+    ctx->solved_Nm = Nm;
+    if (unfinished != 0) {
+        ctx->solved = false;
+        return fail(ctx, DCT_ENOTCONV, "solve: iteration-set cap reached with unfinished right-hand sides");
+    }
+    if (any_nan) status = fail(ctx, DCT_ENUMERIC, "solve: NaN or Inf in a convergence reduction");
+    else if (any_nc) status = fail(ctx, DCT_ENOTCONV, "solve: some group stopped at max_iter above tol");
+    return status;
+}
+
+static int dose_common(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c, bool dev)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!ctx->solved) return fail(ctx, DCT_ESTATE, "dose: no valid solve since the last set_* call");
+    if (!dose && !phi_u && !phi_c) return DCT_OK;
+    HC(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const long C = (long)ctx->nx * ctx->ny * ctx->nz;
+    const int B = ctx->B, G = ctx->G;
+    double *o_dose = dose, *o_pu = phi_u, *o_pc = phi_c;
+    if (!dev) {
+        void *t;
+        if (dose) { HC(dbuf(ctx, "o_dose", (size_t)(summed ? 1 : B) * C * 8, &t)); o_dose = (double *)t; }
+        if (phi_u) { HC(dbuf(ctx, "o_pu", (size_t)B * G * C * 8, &t)); o_pu = (double *)t; }
+        if (phi_c) { HC(dbuf(ctx, "o_pc", (size_t)B * G * C * 8, &t)); o_pc = (double *)t; }
+    }
+    double *scratch = nullptr;
+    if (!o_dose) {
+        void *t;
+        HC(dbuf(ctx, "o_scratch", (size_t)B * C * 8, &t));
+        scratch = (double *)t;
+    }
+    DoseArgs da;
+    da.C = C;
+    da.G = G;
+    da.B = B;
+    da.Nm = ctx->solved_Nm;
+    da.mat = (const uint8_t *)ctx->bufs["mat"].p;
+    da.kap = (const double *)ctx->bufs["kap"].p;
+    da.phi_u = (const double *)ctx->bufs["phiu"].p;
+    da.phi_all = ctx->bufs["phi"].p;
+    da.dose = o_dose ? o_dose : scratch;
+    da.phi_c = o_pc;
+    da.phi_u_out = o_pu;
+    da.summed = o_dose ? summed : 0;
+    HC(launch_dose(da, ctx->solved_prec == DCT_FP64, s));
+    if (!dev) {
+        if (dose) HC(hipMemcpyAsync(dose, o_dose, (size_t)(summed ? 1 : B) * C * 8, hipMemcpyDeviceToHost, s));
+        if (phi_u) HC(hipMemcpyAsync(phi_u, o_pu, (size_t)B * G * C * 8, hipMemcpyDeviceToHost, s));
+        if (phi_c) HC(hipMemcpyAsync(phi_c, o_pc, (size_t)B * G * C * 8, hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+    }
+    return DCT_OK;
+}
+
+extern "C" int dct_dose(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c)
+{
+    return dose_common(ctx, dose, summed, phi_u, phi_c, false);
+}
+
+extern "C" int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c)
+{
+    return dose_common(ctx, dose, summed, phi_u, phi_c, true);
+}
+
+extern "C" int dct_moments(dct_ctx *ctx, double *phi)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!ctx->solved) return fail(ctx, DCT_ESTATE, "moments: no valid solve since the last set_* call");
+    if (!phi) return fail(ctx, DCT_EINVAL, "moments: NULL output");
+    HC(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const long n = (long)ctx->B * ctx->G * ctx->solved_Nm * ctx->nx * ctx->ny * ctx->nz;
+    void *t;
+    HC(dbuf(ctx, "o_mom", (size_t)n * 8, &t));
+    HC(launch_moments_out(ctx->bufs["phi"].p, n, (double *)t, ctx->solved_prec == DCT_FP64, s));
+    HC(hipMemcpyAsync(phi, t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    return DCT_OK;
+}

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+Bars (from the arithmetic): FP64 solves agree with the oracle to 1e-10
+relative (max-norm over the array, summation order is the only difference);
+FP32 solves have dose L2 relative error <= 1e-4; bf16 map inputs are reported
+with a loose bound.  Parity runs lock the per-group iteration counts to the
+oracle's (fixed_iters) so that rounding cannot move the stopping point.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1811_12391_amd import dctsn, inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dctsn.lib()
+    yield
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    s = np.abs(b).max()
+    return float(np.abs(a - b).max() / s) if s > 0 else float(np.abs(a).max())
+
+
+def l2rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def gpu_solve(prob, **kw):
+    s = dctsn.Solver(prob)
+    try:
+        st = s.solve(**kw)
+        dose, pu, pc = s.dose(want_phi=True)
+        mom = s.moments()
+    finally:
+        s.close()
+    return st, dose, pu, mom
+
+
+_ORACLE = {}
+
+
+def oracle_result(name, **kw):
+    import oracle
+
+    key = (name, tuple(sorted(kw.items())))
+    if key not in _ORACLE:
+        _ORACLE[key] = oracle.solve_problem(I.make_problem(name), **kw)
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_abd", "c1"])
+def test_fp64_parity_small(name):
+    prob = I.make_problem(name)
+    _say(f"[parity fp64] {name} grid={prob.phantom.nx}x{prob.phantom.ny}x{prob.phantom.nz} G={prob.G} N={prob.N} L={prob.L}")
+    ref = oracle_result(name)
+    st, dose, pu, mom = gpu_solve(prob, precision="fp64", fixed_iters=ref.iters[0])
+    assert np.array_equal(st.iters, ref.iters)
+    assert rel(pu, ref.phi_u) < 1e-12
+    assert rel(mom, ref.phi) < 1e-10
+    assert rel(dose, ref.dose) < 1e-10
+
+
+def test_stopping_rule_matches():
+    """With the tolerance rule on both sides the per-group counts agree."""
+    prob = I.make_problem("tiny_abd")
+    ref = oracle_result("tiny_abd")
+    st, dose, _, _ = gpu_solve(prob, precision="fp64", tol=1e-6)
+    assert np.abs(st.iters - ref.iters).max() <= 1
+    assert rel(dose, ref.dose) < 1e-6
+
+
+def _multiblock_problem():
+    """ny > 64 and nz > 16: several y- and z-blocks per sweep (block faces
+    through global memory, block-diagonal launches); ragged sizes."""
+    ph = I.cylinder_phantom(7, 70, 18, 0.6)
+    xs = I.xs_tables(ph.material_names, 2, 1)
+    d, w = I.lq_quadrature(4)
+    pos, axis = I.top_source()
+    return I.Problem("multiblock", ph, xs, d, w, 1, pos, axis, 60.0, 30.0, I.kramers_weights(xs.edges))
+
+
+def test_fp64_parity_multiblock():
+    import oracle
+
+    prob = _multiblock_problem()
+    _say("[parity fp64] multiblock 7x70x18")
+    ref = oracle.solve_problem(prob)
+    st, dose, pu, mom = gpu_solve(prob, precision="fp64", fixed_iters=ref.iters[0])
+    assert rel(mom, ref.phi) < 1e-10
+    assert rel(dose, ref.dose) < 1e-10
+
+
+def test_batched_sources_match_separate():
+    """Three ring positions as one batched solve: each RHS equals the oracle
+    and equals its own single-source solve bit for bit."""
+    import oracle
+
+    base = I.make_problem("tiny")
+    pos, axis = I.ring_sources(36)
+    sel = [0, 5, 13]
+    prob = I.Problem("tiny3", base.phantom, base.xs, base.dirs, base.weights, base.L, pos[sel], axis[sel],
+                     base.fan_deg, base.cone_deg, base.group_w)
+    _say("[batched] tiny B=3")
+    ref = oracle.solve_problem(prob, tol=1e-12)
+    st, dose, pu, mom = gpu_solve(prob, precision="fp64", tol=1e-12)
+    for b in range(3):
+        assert rel(dose[b], ref.dose[b]) < 1e-10
+        one = I.Problem("tiny1", base.phantom, base.xs, base.dirs, base.weights, base.L, pos[sel[b]:sel[b] + 1],
+                        axis[sel[b]:sel[b] + 1], base.fan_deg, base.cone_deg, base.group_w)
+        st1, d1, _, _ = gpu_solve(one, precision="fp64", tol=1e-12)
+        assert np.array_equal(d1[0], dose[b])
+        assert np.array_equal(st1.iters[0], st.iters[b])
+
+
+def test_infinite_medium_closed_form():
+    """Uniform source + isotropic inflow phi/(4 pi): phi_g = (S_g + sum_{g'<g}
+    s0^{g'g} phi_g') / (sigma_t,g - s0^{gg}) in every voxel."""
+    ph = I.cylinder_phantom(9, 7, 5, 1.0)
+    ph.material[:] = 1
+    ph.density[:] = 1.0
+    xs = I.xs_tables(ph.material_names, 4, 1)
+    G = 4
+    S = np.array([1.0, 0.5, 0.25, 2.0])
+    st, s0 = xs.sigma_t[1], xs.sigma_s[1, 0]
+    phi = np.zeros(G)
+    for g in range(G):
+        phi[g] = (S[g] + sum(s0[gp, g] * phi[gp] for gp in range(g))) / (st[g] - s0[g, g])
+    d, w = I.lq_quadrature(4)
+    prob = I.Problem("inf", ph, xs, d, w, 1, np.array([[0.0, 40.0, 0.0]]), np.array([[0.0, -1.0, 0.0]]), 20.0,
+                     10.0, np.zeros(G))
+    s = dctsn.Solver(prob)
+    try:
+        dctsn.set_volume_source(s.h, np.repeat(S[:, None], ph.C, axis=1))
+        s.solve(precision="fp64", tol=1e-13, test_inflow=phi / (4 * math.pi))
+        mom = s.moments()
+    finally:
+        s.close()
+    assert rel(mom[0, :, 0], np.repeat(phi[:, None], ph.C, axis=1)) < 1e-11
+
+
+def test_balance_tight():
+    """Production = removal + leakage per group at a tight tolerance."""
+    prob = I.make_problem("tiny_abd")
+    st, _, _, _ = gpu_solve(prob, precision="fp64", tol=1e-13)
+    P, R, Lk = st.balance[0].T
+    assert np.all(np.abs(P - R - Lk) <= 1e-10 * P)
+
+
+def test_deterministic():
+    prob = I.make_problem("tiny_abd")
+    a = gpu_solve(prob, precision="fp32")
+    b = gpu_solve(prob, precision="fp32")
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+
+
+def test_edge_cases():
+    """Beam that misses the grid (zero uncollided flux: zero dose, no NaN,
+    one iteration per group); a 1x1x1 grid; single-layer grids."""
+    base = I.make_problem("tiny")
+    away = I.Problem("away", base.phantom, base.xs, base.dirs, base.weights, base.L, base.src_pos,
+                     np.array([[0.0, 1.0, 0.0]]), 20.0, 10.0, base.group_w)
+    st, dose, pu, mom = gpu_solve(away, precision="fp64")
+    assert np.all(dose == 0) and np.all(pu == 0) and np.all(st.iters == 1)
+    import oracle
+
+    for shape in [(1, 1, 1), (5, 1, 3), (4, 6, 1), (1, 3, 2)]:
+        ph = I.cylinder_phantom(*shape, 5.0)
+        ph.material[:] = 1
+        ph.density[:] = 1.0
+        prob = I.Problem("edge", ph, base.xs, base.dirs, base.weights, base.L, base.src_pos, base.src_axis, 90.0,
+                         90.0, base.group_w)
+        ref = oracle.solve_problem(prob)
+        st, dose, pu, mom = gpu_solve(prob, precision="fp64", fixed_iters=ref.iters[0])
+        assert rel(dose, ref.dose) < 1e-10, shape
+
+
+def test_status_codes_on_gpu():
+    prob = I.make_problem("tiny")
+    s = dctsn.Solver(prob)
+    try:
+        st = s.solve(precision="fp64", tol=1e-14, max_iter=1, allow_notconv=True)
+        assert st.status == dctsn.DCT_ENOTCONV and np.all(st.iters == 1)
+        d = s.dose()
+        assert np.all(np.isfinite(d))
+        # P2 on S2 is not integrated exactly by the quadrature -> ESTATE
+        d2, w2 = I.lq_quadrature(2)
+        dctsn.set_quadrature(s.h, 8, d2, w2)
+        with pytest.raises(dctsn.DctError) as e:
+            s.solve(precision="fp64")
+        assert e.value.code == dctsn.DCT_ESTATE
+    finally:
+        s.close()
+
+
+# ------------------------------------------------------------------ full size (config 2)
+@pytest.fixture(scope="module")
+def c2_ref():
+    _say("[c2] oracle solve (64x64x16, 19 groups, S8, P3)")
+    return oracle_result("c2")
+
+
+def test_c2_fp64_parity(c2_ref):
+    prob = I.make_problem("c2")
+    _say("[c2] GPU fp64 solve")
+    st, dose, pu, mom = gpu_solve(prob, precision="fp64", fixed_iters=c2_ref.iters[0])
+    assert rel(pu, c2_ref.phi_u) < 1e-12
+    assert rel(dose, c2_ref.dose) < 1e-10
+    assert rel(mom[0, :, 0], c2_ref.phi[0, :, 0]) < 1e-10
+
+
+def test_c2_fp32_error(c2_ref):
+    prob = I.make_problem("c2")
+    _say("[c2] GPU fp32 solve")
+    st, dose, pu, mom = gpu_solve(prob, precision="fp32", fixed_iters=c2_ref.iters[0])
+    err = l2rel(dose, c2_ref.dose)
+    _say(f"[c2] fp32 dose L2 rel err = {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_c2_bf16_maps_error(c2_ref):
+    prob = I.make_problem("c2")
+    _say("[c2] GPU fp32 + bf16 maps solve")
+    st, dose, pu, mom = gpu_solve(prob, precision="fp32_bf16map", fixed_iters=c2_ref.iters[0])
+    err = l2rel(dose, c2_ref.dose)
+    _say(f"[c2] bf16-map dose L2 rel err = {err:.3e}")
+    assert err <= 2e-2
