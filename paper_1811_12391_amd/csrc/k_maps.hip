@@ -12,7 +12,8 @@
 // placement (64 lanes, lane = col + 16 * krow):
 //   A[i][k]: lane i + 16 k        (16x16x16 bf16: k in [4 krow, 4 krow + 4) packed)
 //   B[k][j]: lane j + 16 k
-//   D[i][j]: lane j + 16 (i / 4), element i % 4
+//   D[i][j]: f32 / bf16: lane j + 16 (i / 4), element i % 4
+//            f64:        lane j + 16 (i % 4), element i / 4
 // The 16 lanes of one k-row load 16 consecutive positions, so every load and
 // store of q / psi / Q / part is a 16-element contiguous run.
 #include "dct_internal.h"
@@ -29,6 +30,10 @@ __device__ inline f4_t mfma_k4(float a, float b, f4_t c) { return __builtin_amdg
 template <typename T> struct acc4;
 template <> struct acc4<double> { typedef d4_t type; };
 template <> struct acc4<float> { typedef f4_t type; };
+
+// output row (within a 16-row tile) held by lane group kr in element r
+template <typename T> __device__ inline int out_row(int kr, int r) { return 4 * kr + r; }
+template <> __device__ inline int out_row<double>(int kr, int r) { return kr + 4 * r; }
 
 // round-to-nearest-even fp32 -> bf16 bits
 __device__ inline short to_bf16(float f)
@@ -67,7 +72,7 @@ __global__ __launch_bounds__(256) void k_mmap(MapArgs a)
         for (int s = 0; s < NS; ++s) acc = mfma_k4(Mt[(rb * 16 + col) * a.NmP + 4 * s + kr], bq[s], acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            int nl = rb * 16 + 4 * kr + r;
+            int nl = rb * 16 + out_row<T>(kr, r);
             if (nl < Nc && inb) q[(long)cd[nl] * C + p] = acc[r];
         }
     }
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            int lm = rb * 16 + 4 * kr + r;
+            int lm = rb * 16 + out_row<T>(kr, r);
             if (lm < Nm && inb) part[(long)lm * C + p] = acc[r];
         }
     }

@@ -200,7 +200,10 @@ def test_status_codes_on_gpu():
         assert st.status == dctsn.DCT_ENOTCONV and np.all(st.iters == 1)
         d = s.dose()
         assert np.all(np.isfinite(d))
-        # P2 on S2 is not integrated exactly by the quadrature -> ESTATE
+        # P2 moments are not integrated exactly by S2 (D M != I) -> ESTATE
+        xs2 = I.xs_tables(prob.phantom.material_names, prob.G, 2)
+        dctsn.set_xs(s.h, xs2.G, xs2.edges, xs2.M, 2, xs2.sigma_t, xs2.sigma_s, xs2.kerma)
+        dctsn.set_source(s.h, 1, prob.src_pos, prob.src_axis, 20.0, 10.0, prob.group_w)
         d2, w2 = I.lq_quadrature(2)
         dctsn.set_quadrature(s.h, 8, d2, w2)
         with pytest.raises(dctsn.DctError) as e:
