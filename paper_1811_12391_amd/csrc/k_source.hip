@@ -190,6 +190,7 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     if (st->finished) return;
     const int g = st->g;
     const int nx = a.geo.nx, ny = a.geo.ny;
+    const unsigned nblocks_b = gridDim.x * gridDim.z;   // blocks of this RHS (slabs x moments)
     const long C = a.geo.C;
     const int G = a.G, Nm = a.Nm, L = a.L;
     const int nslj = (ny + 15) >> 4;
@@ -204,7 +205,8 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     const T *ext = (const T *)a.ext + (long)b * Nm * C;
     T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
     double dmax = 0.0, fmax_ = 0.0;
-    for (int lm = 0; lm < Nm; ++lm) {
+    {
+        const int lm = blockIdx.z;
         const int l = l_of(lm);
         // class A half, rotated rows -> natural tile
         for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
@@ -259,11 +261,13 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     double dm = block_max(dmax, red);
     double fm = block_max(fmax_, red);
     if (threadIdx.x == 0) {
-        atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
-        atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
+        if (blockIdx.z == 0) {
+            atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
+            atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
+        }
         __threadfence();
         unsigned prev = atomicAdd(&st->cnt_combine, 1u);
-        if (prev == gridDim.x - 1) {
+        if (prev == nblocks_b - 1) {
             __threadfence();
             double num = __longlong_as_double((long long)atomicAdd(&st->eps_num, 0ull));
             double den = __longlong_as_double((long long)atomicAdd(&st->eps_den, 0ull));
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
 hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s)
 {
     const int nslj = (a.geo.ny + 15) >> 4;
-    dim3 grid((unsigned)(a.geo.nz * nslj), a.B);
+    dim3 grid((unsigned)(a.geo.nz * nslj), a.B, a.Nm);
     size_t shm = (size_t)16 * (a.geo.nx + 1) * (is_f64 ? 8 : 4);
     if (is_f64) hipLaunchKernelGGL(k_combine<double>, grid, dim3(256), shm, s, a);
     else hipLaunchKernelGGL(k_combine<float>, grid, dim3(256), shm, s, a);

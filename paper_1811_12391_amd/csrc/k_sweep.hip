@@ -24,36 +24,82 @@
 
 namespace dct {
 
-template <typename T>
-__device__ inline void dd_cell(T qv, T sv, T cx, T cy, T cz, T csum, T xin, T yin, T zin, int fixup, T &pc,
-                               T &xo, T &yo, T &zo)
+// q / d for d > 0 (d >= sum of the face coefficients, never tiny): hardware
+// reciprocal refined by Newton-Raphson, then one residual correction of the
+// quotient (Markstein); FP64 keeps full precision, FP32 is within an ulp.
+__device__ inline double qdiv(double n, double d)
 {
-    T num = qv + cx * xin + cy * yin + cz * zin;
-    pc = num / (sv + csum);
-    xo = pc + pc - xin;
-    yo = pc + pc - yin;
-    zo = pc + pc - zin;
-    if (fixup && (xo < (T)0 || yo < (T)0 || zo < (T)0)) {
-        bool fx = false, fy = false, fz = false;
-        for (int pass = 0; pass < 3; ++pass) {
-            bool fresh = false;
-            if (!fx && xo < (T)0) { fx = true; fresh = true; }
-            if (!fy && yo < (T)0) { fy = true; fresh = true; }
-            if (!fz && zo < (T)0) { fz = true; fresh = true; }
-            if (!fresh) break;
-            T n2 = qv, d2 = sv;
-            if (fx) n2 += (T)0.5 * cx * xin; else { n2 += cx * xin; d2 += cx; }
-            if (fy) n2 += (T)0.5 * cy * yin; else { n2 += cy * yin; d2 += cy; }
-            if (fz) n2 += (T)0.5 * cz * zin; else { n2 += cz * zin; d2 += cz; }
-            pc = n2 / d2;
-            xo = fx ? (T)0 : pc + pc - xin;
-            yo = fy ? (T)0 : pc + pc - yin;
-            zo = fz ? (T)0 : pc + pc - zin;
-        }
-    }
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    double q = n * y;
+    double r = fma(-d, q, n);
+    return fma(y, r, q);
+}
+__device__ inline float qdiv(float n, float d)
+{
+    float y = __builtin_amdgcn_rcpf(d);
+    float q = n * y;
+    float r = fmaf(-d, q, n);
+    return fmaf(y, r, q);
 }
 
-template <typename T, int PF>
+// Set-to-zero fixup of one cell (rare path): faces with a negative outflow are
+// closed (outflow 0, inflow weighted c_a / 2 in the balance) until no new
+// negative face appears.  Returns (psi_c, out_x, out_y, out_z) by value.
+template <typename T> struct Cell4 { T pc, xo, yo, zo; };
+
+template <typename T>
+__device__ __attribute__((noinline)) Cell4<T> dd_fixup(T qv, T sv, T cx, T cy, T cz, T xin, T yin, T zin,
+                                                         Cell4<T> c)
+{
+    bool fx = false, fy = false, fz = false;
+    for (int pass = 0; pass < 3; ++pass) {
+        bool fresh = false;
+        if (!fx && c.xo < (T)0) { fx = true; fresh = true; }
+        if (!fy && c.yo < (T)0) { fy = true; fresh = true; }
+        if (!fz && c.zo < (T)0) { fz = true; fresh = true; }
+        if (!fresh) break;
+        T n2 = qv, d2 = sv;
+        if (fx) n2 += (T)0.5 * cx * xin; else { n2 += cx * xin; d2 += cx; }
+        if (fy) n2 += (T)0.5 * cy * yin; else { n2 += cy * yin; d2 += cy; }
+        if (fz) n2 += (T)0.5 * cz * zin; else { n2 += cz * zin; d2 += cz; }
+        c.pc = n2 / d2;
+        c.xo = fx ? (T)0 : c.pc + c.pc - xin;
+        c.yo = fy ? (T)0 : c.pc + c.pc - yin;
+        c.zo = fz ? (T)0 : c.pc + c.pc - zin;
+    }
+    return c;
+}
+
+__device__ inline int wrap_row(int r, int nx) { return r == nx ? 0 : (r < 0 ? nx - 1 : r); }
+
+template <typename T>
+__device__ inline T lane_shift_up(T v);
+// lane l receives lane l-1's value (DPP wave_shr:1); lane 0 keeps its own
+template <>
+__device__ inline double lane_shift_up<double>(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <>
+__device__ inline float lane_shift_up<float>(float v)
+{
+    int x = __float_as_int(v);
+    x = __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false);
+    return __int_as_float(x);
+}
+
+// One workgroup = one (source, direction, block).  The step loop has no
+// divergent branch around any memory access: prefetch loads are issued for
+// every lane from an always-valid address, so the compiler can wait on
+// exactly the load a step consumes (PF steps after it was issued).
+template <typename T, int PF, bool MULTI>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     __shared__ T zbuf[2][16][64];
@@ -65,8 +111,8 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const int g = a.state[b].g;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const long C = a.C;
-    const int bj = max(0, a.diag - (a.NBK - 1)) + (int)blockIdx.y;
-    const int bk = a.diag - bj;
+    const int bj = MULTI ? max(0, a.diag - (a.NBK - 1)) + (int)blockIdx.y : 0;
+    const int bk = MULTI ? a.diag - bj : 0;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double ox = a.dirs[3 * n], oy = a.dirs[3 * n + 1], oz = a.dirs[3 * n + 2];
     const bool sx = ox > 0, sy = oy > 0, sz = oz > 0;
@@ -83,71 +129,106 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const T *qb = (const T *)a.q + (long)item * C;
     T *pb = (T *)a.psi + (long)item * C;
     const T *sg = (const T *)a.sigc + ((long)cls * a.G + g) * C;
-    T *yf = (T *)a.yface + (long)item * nx * nz;
-    T *zf = (T *)a.zface + (long)item * nx * ny;
+    // block faces, ping-pong by block parity so a block never reads a location
+    // that a block of the same launch writes
+    const long nitems = (long)a.B * a.N;
+    const T *yf_in = (const T *)a.yface + ((long)(bj & 1) * nitems + item) * nx * nz;
+    T *yf_out = (T *)a.yface + ((long)((bj + 1) & 1) * nitems + item) * nx * nz;
+    const T *zf_in = (const T *)a.zface + ((long)(bk & 1) * nitems + item) * nx * ny;
+    T *zf_out = (T *)a.zface + ((long)((bk + 1) & 1) * nitems + item) * nx * ny;
+    const int jpc = min(jp, ny - 1), kpc = min(kp, nz - 1);   // clamped for padded lanes/waves
     const T bc = a.inflow ? (T)a.inflow[g] : (T)0;
     const int fixup = a.fixup;
     const int NT = nx + nl + nw - 2;
+    const int NTp = ((NT + PF - 1) / PF) * PF;
+    const int t0l = l + w;                          // step at which this lane starts its row
+    const int dr = sx ? 1 : -1;                     // rotated-row increment per x step
+    const int rstart = rot_row(cls, sx ? 0 : nx - 1, jm, nx);
+    const bool ylast = jp == ny - 1, zlast = kp == nz - 1;
 
-    // prefetch ring: slot u holds step t0 + u
-    T qr[PF], sr[PF];
-    auto pos_of = [&](int t, bool &act) -> long {
-        int ip = t - l - w;
-        act = valid && ip >= 0 && ip < nx;
-        int i = sx ? ip : nx - 1 - ip;
-        int r = rot_row(cls, act ? i : 0, jm, nx);
-        return rowbase + (long)r * ny;
-    };
+    T qr[PF], sr[PF], yr[MULTI ? PF : 1], zr[MULTI ? PF : 1];
+    int rp = rstart, rc = rstart;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-        bool act;
-        long pos = pos_of(u, act);
-        qr[u] = act ? qb[pos] : (T)0;
-        sr[u] = act ? sg[pos] : (T)0;
+        const long pp = rowbase + (long)rp * ny;
+        qr[u] = qb[pp];
+        sr[u] = sg[pp];
+        const bool inp = valid && (unsigned)(u - t0l) < (unsigned)nx;
+        if (MULTI) {
+            const int ipc = inp ? u - t0l : 0;
+            yr[u] = yf_in[ipc + nx * kpc];
+            zr[u] = zf_in[ipc + nx * jpc];
+        }
+        rp = inp ? wrap_row(rp + dr, nx) : rp;
     }
-    T xo = 0, yo = 0, zo = 0;
-    double lx = 0.0, ly = 0.0, lz = 0.0;
-    for (int t0 = 0; t0 < NT; t0 += PF) {
+    T xo = bc, yo = 0, zo = 0;
+    double lyv = 0.0, lzv = 0.0;
+    for (int tb = 0; tb < NTp; tb += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
-            const int t = t0 + u;
-            if (t < NT) {
-                const T qv = qr[u], sv = sr[u];
-                {
-                    bool actn;
-                    long posn = pos_of(t + PF, actn);
-                    actn = actn && (t + PF < NT);
-                    qr[u] = actn ? qb[posn] : (T)0;
-                    sr[u] = actn ? sg[posn] : (T)0;
-                }
-                bool act;
-                const long pos = pos_of(t, act);
-                const int ip = t - l - w;
-                T yin = __shfl_up(yo, 1, 64);
-                if (l == 0) yin = (jp == 0) ? bc : (act ? yf[ip + nx * kp] : (T)0);
-                T zin;
-                if (w == 0) zin = (kp == 0) ? bc : (act ? zf[ip + nx * jp] : (T)0);
-                else zin = zbuf[(t + 1) & 1][w - 1][l];
-                const T xin = (ip == 0) ? bc : xo;
-                if (act) {
-                    T pc, ax_, ay_, az_;
-                    dd_cell<T>(qv, sv, cx, cy, cz, csum, xin, yin, zin, fixup, pc, ax_, ay_, az_);
-                    pb[pos] = pc;
-                    if (ip == nx - 1) lx += (double)ax_;
-                    if (jp == ny - 1) ly += (double)ay_;
-                    if (kp == nz - 1) lz += (double)az_;
-                    if (l == nl - 1 && jp < ny - 1) yf[ip + nx * kp] = ay_;
-                    if (w == nw - 1 && kp < nz - 1) zf[ip + nx * jp] = az_;
-                    xo = ax_;
-                    yo = ay_;
-                    zo = az_;
-                }
-                zbuf[t & 1][w][l] = zo;
-                __syncthreads();
+            const int t = tb + u;
+            const T qv = qr[u], sv = sr[u];
+            T yface_in = (T)0, zface_in = (T)0;
+            if (MULTI) {
+                yface_in = yr[MULTI ? u : 0];
+                zface_in = zr[MULTI ? u : 0];
             }
+            {
+                const int tp = t + PF;
+                const long pp = rowbase + (long)rp * ny;
+                qr[u] = qb[pp];
+                sr[u] = sg[pp];
+                const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
+                if (MULTI) {
+                    const int ipc = inp ? tp - t0l : 0;
+                    yr[MULTI ? u : 0] = yf_in[ipc + nx * kpc];
+                    zr[MULTI ? u : 0] = zf_in[ipc + nx * jpc];
+                }
+                rp = inp ? wrap_row(rp + dr, nx) : rp;
+            }
+            const int ip = t - t0l;
+            const bool act = valid && (unsigned)ip < (unsigned)nx;
+            T yin = lane_shift_up<T>(yo);
+            T zin = zbuf[(t + 1) & 1][w > 0 ? w - 1 : 0][l];
+            if (MULTI) {
+                if (l == 0) yin = (jp == 0) ? bc : yface_in;
+                if (w == 0) zin = (kp == 0) ? bc : zface_in;
+            } else {
+                if (l == 0) yin = bc;
+                if (w == 0) zin = bc;
+            }
+            const T xin = (ip == 0) ? bc : xo;
+            if (act) {
+                const T num = qv + cx * xin + cy * yin + cz * zin;
+                Cell4<T> c;
+                c.pc = qdiv(num, sv + csum);
+                c.xo = c.pc + c.pc - xin;
+                c.yo = c.pc + c.pc - yin;
+                c.zo = c.pc + c.pc - zin;
+                if (fixup && __builtin_expect(fmin(c.xo, fmin(c.yo, c.zo)) < (T)0, 0))
+                    c = dd_fixup<T>(qv, sv, cx, cy, cz, xin, yin, zin, c);
+                const T pc = c.pc, ax_ = c.xo, ay_ = c.yo, az_ = c.zo;
+                pb[rowbase + (long)rc * ny] = pc;
+                rc = wrap_row(rc + dr, nx);
+                lyv += (double)ay_;
+                lzv += (double)az_;
+                if (MULTI) {
+                    if (l == nl - 1 && jp < ny - 1) yf_out[ip + nx * kp] = ay_;
+                    if (w == nw - 1 && kp < nz - 1) zf_out[ip + nx * jp] = az_;
+                }
+                xo = ax_;
+                yo = ay_;
+                zo = az_;
+            }
+            zbuf[t & 1][w][l] = zo;
+            __syncthreads();
         }
     }
-    // boundary outflow sums of this block (for the particle balance)
+    // boundary outflow sums of this block (for the particle balance): the last
+    // x outflow of every row, and the y / z outflows of the boundary rows
+    double lx = valid ? (double)xo : 0.0;
+    double ly = (valid && ylast) ? lyv : 0.0;
+    double lz = (valid && zlast) ? lzv : 0.0;
     for (int o = 32; o > 0; o >>= 1) {
         lx += __shfl_down(lx, o, 64);
         ly += __shfl_down(ly, o, 64);
@@ -173,8 +254,14 @@ hipError_t launch_sweep(const SweepArgs &a, int is_f64, hipStream_t s)
     int hi = min(a.diag, NBJ - 1);
     dim3 grid((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
     dim3 block(64 * a.BK);
-    if (is_f64) hipLaunchKernelGGL((k_sweep<double, 4>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_sweep<float, 8>), grid, block, 0, s, a);
+    const bool multi = NBJ > 1 || NBK > 1;
+    if (is_f64) {
+        if (multi) hipLaunchKernelGGL((k_sweep<double, 4, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sweep<double, 4, false>), grid, block, 0, s, a);
+    } else {
+        if (multi) hipLaunchKernelGGL((k_sweep<float, 8, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sweep<float, 8, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -494,8 +494,9 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(dbuf(ctx, "psi", (size_t)B * N * C * ts, &d_psi));
     HC(dbuf(ctx, "part", (size_t)2 * B * Nm * C * ts, &d_part));
     HC(dbuf(ctx, "phi", (size_t)B * G * Nm * C * ts, &d_phi));
-    HC(dbuf(ctx, "yf", pl.NBJ > 1 ? (size_t)B * N * nx * nz * ts : 0, &d_yf));
-    HC(dbuf(ctx, "zf", pl.NBK > 1 ? (size_t)B * N * nx * ny * ts : 0, &d_zf));
+    // block-face buffers, two copies each (ping-pong by block parity)
+    HC(dbuf(ctx, "yf", (size_t)2 * B * N * nx * nz * ts, &d_yf));
+    HC(dbuf(ctx, "zf", (size_t)2 * B * N * nx * ny * ts, &d_zf));
     HC(dbuf(ctx, "leak", (size_t)B * N * pl.nblk * 3 * 8, &d_leak));
     HC(dbuf(ctx, "state", (size_t)B * sizeof(RhsState), &d_state));
     HC(dbuf(ctx, "bal", (size_t)B * G * 3 * 8, &d_bal));
