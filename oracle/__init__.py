@@ -64,6 +64,18 @@ def _declare(L):
     L.orc_sweep.argtypes = ([ct.c_int] * 3 + [ct.c_double] * 3 + [_d, ct.c_int, _d, _d, _d, ct.c_int,
                             ct.c_int, _d, _d])
     L.orc_sweep.restype = ct.c_long
+    L.orc_sweep2.argtypes = ([ct.c_int] * 3 + [ct.c_double] * 3 + [_d, ct.c_int, _d, _d, _d, ct.c_int,
+                             ct.c_int, _d, _d, _u8, _u8])
+    L.orc_sweep2.restype = ct.c_long
+    L.orc_sweep_adjoint.argtypes = ([ct.c_int] * 3 + [ct.c_double] * 3 + [_d, ct.c_int, _d, _d, _u8, ct.c_int, _d])
+    L.orc_sweep_adjoint.restype = ct.c_int
+    L.orc_adjoint.argtypes = ([ct.c_int] * 3 + [ct.c_double] * 3 + [_d, _u8, _d,
+                              ct.c_int, ct.c_int, ct.c_int, _d, _d, _d,
+                              ct.c_int, _d, _d,
+                              ct.c_int, _d, _d, ct.c_double, ct.c_double, _d, _d,
+                              ct.c_double, ct.c_int, _i, _i, ct.c_int, ct.c_int,
+                              _d, _d, _d, _i])
+    L.orc_adjoint.restype = ct.c_int
     L.orc_first_collision.argtypes = ([ct.c_int] * 3 + [ct.c_double] * 3 + [_d, _u8, _d, ct.c_int, ct.c_int, _d,
                                       _d, _d, _d, ct.c_int, _d])
     L.orc_first_collision.restype = ct.c_int
@@ -139,6 +151,71 @@ def sweep(shape, spacing, sigt, dirs, q, inflow=None, fixup=True, threads=None):
     nf = lib().orc_sweep(nx, ny, nz, dx, dy, dz, _p(sigt), N, _p(dirs), _p(q), _p(infl), int(fixup),
                          threads or default_threads(), _p(psi), _p(leak))
     return psi, leak, nf
+
+
+def sweep_masked(shape, spacing, sigt, dirs, q, fixup=True, mask_in=None, threads=None):
+    """Sweep with vacuum inflow returning (psi, mask): the fixed-face set of
+    every cell (bits x=1, y=2, z=4); with mask_in the fixup is frozen to it."""
+    nx, ny, nz = shape
+    dx, dy, dz = spacing
+    sigt, dirs, q = _f64(sigt), _f64(dirs), _f64(q)
+    N = dirs.shape[0]
+    psi = np.zeros((N, nx * ny * nz))
+    mask = np.zeros((N, nx * ny * nz), dtype=np.uint8)
+    mi = None if mask_in is None else np.ascontiguousarray(mask_in, dtype=np.uint8)
+    lib().orc_sweep2(nx, ny, nz, dx, dy, dz, _p(sigt), N, _p(dirs), _p(q), None, int(fixup),
+                     threads or default_threads(), _p(psi), None, _p(mi, _u8), _p(mask, _u8) if mi is None else None)
+    return psi, (mask if mi is None else mi)
+
+
+def sweep_adjoint(shape, spacing, sigt, dirs, s, mask, threads=None):
+    """Transpose of the frozen-mask sweep: weights on psi -> weights on q."""
+    nx, ny, nz = shape
+    dx, dy, dz = spacing
+    sigt, dirs, s = _f64(sigt), _f64(dirs), _f64(s)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    lam = np.zeros_like(s)
+    lib().orc_sweep_adjoint(nx, ny, nz, dx, dy, dz, _p(sigt), dirs.shape[0], _p(dirs), _p(s), _p(mask, _u8),
+                            threads or default_threads(), _p(lam))
+    return lam
+
+
+@dataclass
+class AdjointResult:
+    R: float               # sum_b sum_v roi_v dose_b(v)
+    d_density: np.ndarray  # [C]
+    d_group_w: np.ndarray  # [G]
+    iters_adj: np.ndarray  # [B][G]
+
+
+def adjoint(ph, xs, dirs, w, L, pos, axis, fan_deg, cone_deg, group_w, roi, *, tol=1e-6, max_iter=1000,
+            fixed_iters=None, fixed_iters_adj=None, fixup=True, threads=None) -> AdjointResult:
+    G, M = xs.sigma_t.shape[1], xs.sigma_t.shape[0]
+    st, ss, ka = _f64(xs.sigma_t), _f64(xs.sigma_s[:, : L + 1]), _f64(xs.kerma)
+    dirs, w = _f64(dirs), _f64(w)
+    pos, axis = _f64(pos).reshape(-1, 3), _f64(axis).reshape(-1, 3)
+    B = pos.shape[0]
+    mat = np.ascontiguousarray(ph.material, dtype=np.uint8)
+    rho, org, gw, roi = _f64(ph.density), _f64(ph.origin), _f64(group_w), _f64(roi)
+    fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, dtype=np.int32)
+    fa = None if fixed_iters_adj is None else np.ascontiguousarray(fixed_iters_adj, dtype=np.int32)
+    R = np.zeros(1)
+    dr = np.zeros(ph.C)
+    dg = np.zeros(G)
+    ia = np.zeros((B, G), dtype=np.int32)
+    rc = lib().orc_adjoint(ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, _p(org), _p(mat, _u8), _p(rho),
+                           G, M, L, _p(st), _p(ss), _p(ka), dirs.shape[0], _p(dirs), _p(w),
+                           B, _p(pos), _p(axis), float(fan_deg), float(cone_deg), _p(gw), _p(roi),
+                           float(tol), int(max_iter), _p(fi, _i), _p(fa, _i), int(fixup), threads or default_threads(),
+                           _p(R), _p(dr), _p(dg), _p(ia, _i))
+    if rc != 0:
+        raise RuntimeError("oracle adjoint failed: %d" % rc)
+    return AdjointResult(float(R[0]), dr, dg, ia)
+
+
+def adjoint_problem(prob, roi, **kw) -> AdjointResult:
+    return adjoint(prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos, prob.src_axis,
+                   prob.fan_deg, prob.cone_deg, prob.group_w, roi, **kw)
 
 
 def uncollided(ph, xs_sigma_t, pos, axis, fan_deg, cone_deg, group_w, threads=None):

@@ -226,8 +226,8 @@ int orc_uncollided(int nx, int ny, int nz, double dx, double dy, double dz, cons
 /* the balance with that face removed, until no new negative face appears.     */
 /* Returns the number of fixed faces.                                          */
 /* ------------------------------------------------------------------------ */
-int orc_dd_cell(double q, double sig, const double *c, const double *pin, int fixup,
-                double *pc, double *pout)
+static int dd_cell_decide(double q, double sig, const double *c, const double *pin, int fixup,
+                          double *pc, double *pout, int *F)
 {
     double num = q + 2.0 * (c[0] * pin[0] + c[1] * pin[1] + c[2] * pin[2]);
     double den = sig + 2.0 * (c[0] + c[1] + c[2]);
@@ -251,17 +251,58 @@ int orc_dd_cell(double q, double sig, const double *c, const double *pin, int fi
         }
     }
     *pc = psi;
+    if (F) *F = fixed[0] | (fixed[1] << 1) | (fixed[2] << 2);
     return nf;
+}
+
+int orc_dd_cell(double q, double sig, const double *c, const double *pin, int fixup,
+                double *pc, double *pout)
+{
+    return dd_cell_decide(q, sig, c, pin, fixup, pc, pout, NULL);
+}
+
+/* The same cell with a frozen set F of fixed faces (bit a set: face a fixed):
+ * the linear map (q, inflow) -> (psi_c, outflow) that the fixup produced. */
+static void dd_cell_frozen(double q, double sig, const double *c, const double *pin, int F, double *pc,
+                           double *pout)
+{
+    double num = q, den = sig;
+    for (int a = 0; a < 3; ++a) {
+        if ((F >> a) & 1) num += c[a] * pin[a];
+        else { num += 2.0 * c[a] * pin[a]; den += 2.0 * c[a]; }
+    }
+    double psi = num / den;
+    for (int a = 0; a < 3; ++a) pout[a] = ((F >> a) & 1) ? 0.0 : 2.0 * psi - pin[a];
+    *pc = psi;
+}
+
+/* Transpose of dd_cell_frozen.  Inputs: weight s on psi_c and weights fin on
+ * the outflow faces (the adjoint face values coming back from the downwind
+ * neighbours); outputs: weight lc on q and fout on the inflow faces.  With
+ * gamma_a = 0 for fixed faces (1 otherwise) and alpha_a = c_a (fixed) or
+ * 2 c_a:  lc = (s + 2 sum gamma_a fin_a) / (sig + sum_{a not fixed} 2 c_a),
+ *         fout_a = alpha_a lc - gamma_a fin_a. */
+static void dd_cell_adjoint(double s, double sig, const double *c, const double *fin, int F, double *lc,
+                            double *fout)
+{
+    double num = s, den = sig;
+    for (int a = 0; a < 3; ++a)
+        if (!((F >> a) & 1)) { num += 2.0 * fin[a]; den += 2.0 * c[a]; }
+    double l = num / den;
+    for (int a = 0; a < 3; ++a) fout[a] = ((F >> a) & 1) ? c[a] * l : 2.0 * c[a] * l - fin[a];
+    *lc = l;
 }
 
 /* One transport sweep for every direction: cells visited in upwind order
  * (lexicographic in the octant's reflected coordinates), incoming boundary
  * angular flux = inflow[n] (0 for vacuum).  psi[N][C] receives the cell-centre
  * angular flux; leak[N][3] (optional) the sum of outgoing boundary face fluxes
- * per axis.  Returns the total number of fixed faces. */
-long orc_sweep(int nx, int ny, int nz, double dx, double dy, double dz, const double *sigt,
-               int N, const double *dirs, const double *q, const double *inflow, int fixup,
-               int nthreads, double *psi, double *leak)
+ * per axis.  mask_out[N][C] (optional) records each cell's final fixed-face
+ * set; with mask_in[N][C] the fixup is not decided but frozen to the given
+ * sets (a linear map).  Returns the total number of fixed faces. */
+long orc_sweep2(int nx, int ny, int nz, double dx, double dy, double dz, const double *sigt,
+                int N, const double *dirs, const double *q, const double *inflow, int fixup,
+                int nthreads, double *psi, double *leak, const uint8_t *mask_in, uint8_t *mask_out)
 {
     size_t C = (size_t)nx * ny * nz;
     long nfix = 0;
@@ -288,7 +329,13 @@ long orc_sweep(int nx, int ny, int nz, double dx, double dy, double dz, const do
                     size_t v = (size_t)i + (size_t)nx * (j + (size_t)ny * k);
                     double pin[3] = {fx[j + (size_t)ny * k], fy[i + (size_t)nx * k], fz[i + (size_t)nx * j]};
                     double pc, pout[3];
-                    nfix += orc_dd_cell(qn[v], sigt[v], c, pin, fixup, &pc, pout);
+                    if (mask_in) {
+                        dd_cell_frozen(qn[v], sigt[v], c, pin, mask_in[(size_t)n * C + v], &pc, pout);
+                    } else {
+                        int F = 0;
+                        nfix += dd_cell_decide(qn[v], sigt[v], c, pin, fixup, &pc, pout, &F);
+                        if (mask_out) mask_out[(size_t)n * C + v] = (uint8_t)F;
+                    }
                     pn[v] = pc;
                     fx[j + (size_t)ny * k] = pout[0];
                     fy[i + (size_t)nx * k] = pout[1];
@@ -309,6 +356,56 @@ long orc_sweep(int nx, int ny, int nz, double dx, double dy, double dz, const do
         free(fz);
     }
     return nfix;
+}
+
+long orc_sweep(int nx, int ny, int nz, double dx, double dy, double dz, const double *sigt,
+               int N, const double *dirs, const double *q, const double *inflow, int fixup,
+               int nthreads, double *psi, double *leak)
+{
+    return orc_sweep2(nx, ny, nz, dx, dy, dz, sigt, N, dirs, q, inflow, fixup, nthreads, psi, leak, NULL, NULL);
+}
+
+/* Transpose of the frozen-mask sweep with vacuum inflow: given weights s[N][C]
+ * on the cell-centre fluxes, returns lam[N][C], the weights on the sources q
+ * (<s, L^-1 q> = <L^-T s, q>).  Cells are visited in the reverse of the
+ * forward order; the adjoint face values travel upwind, starting from 0 at
+ * the outflow boundary. */
+int orc_sweep_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, const double *sigt,
+                      int N, const double *dirs, const double *s, const uint8_t *mask, int nthreads,
+                      double *lam)
+{
+    size_t C = (size_t)nx * ny * nz;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int n = 0; n < N; ++n) {
+        const double *om = dirs + 3 * n;
+        double c[3] = {fabs(om[0]) / dx, fabs(om[1]) / dy, fabs(om[2]) / dz};
+        double *fx = (double *)calloc((size_t)ny * nz, sizeof(double));
+        double *fy = (double *)calloc((size_t)nx * nz, sizeof(double));
+        double *fz = (double *)calloc((size_t)nx * ny, sizeof(double));
+        const double *sn = s + (size_t)n * C;
+        double *ln = lam + (size_t)n * C;
+        for (int kk = nz - 1; kk >= 0; --kk) {
+            int k = om[2] > 0 ? kk : nz - 1 - kk;
+            for (int jj = ny - 1; jj >= 0; --jj) {
+                int j = om[1] > 0 ? jj : ny - 1 - jj;
+                for (int ii = nx - 1; ii >= 0; --ii) {
+                    int i = om[0] > 0 ? ii : nx - 1 - ii;
+                    size_t v = (size_t)i + (size_t)nx * (j + (size_t)ny * k);
+                    double fin[3] = {fx[j + (size_t)ny * k], fy[i + (size_t)nx * k], fz[i + (size_t)nx * j]};
+                    double lc, fout[3];
+                    dd_cell_adjoint(sn[v], sigt[v], c, fin, mask[(size_t)n * C + v], &lc, fout);
+                    ln[v] = lc;
+                    fx[j + (size_t)ny * k] = fout[0];
+                    fy[i + (size_t)nx * k] = fout[1];
+                    fz[i + (size_t)nx * j] = fout[2];
+                }
+            }
+        }
+        free(fx);
+        free(fy);
+        free(fz);
+    }
+    return 0;
 }
 
 /* First-collision source of one right-hand side: the uncollided flux at voxel
@@ -357,6 +454,165 @@ int orc_first_collision(int nx, int ny, int nz, double dx, double dy, double dz,
 /* iteration with downscatter -> dose.  Each right-hand side (source) b is      */
 /* solved on its own with its own stopping point.                               */
 /* ------------------------------------------------------------------------ */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    const double *org;
+    const uint8_t *mat;
+    const double *rho;
+    int G, M, L, Nm, N;
+    const double *st, *ss, *kap, *dirs, *w;
+    const double *Mmap, *Dmap;
+    const int *lof;
+} Prob;
+
+static double ss_at(const Prob *P, int m, int l, int gf, int gt)
+{
+    return P->ss[(((size_t)m * (P->L + 1) + l) * P->G + gf) * P->G + gt];
+}
+
+/* Forward solve of one right-hand side.  pu = its uncollided flux [G][C].
+ * Outputs phi[G][Nm][C], dose[C], iters[G], eps[G], bal[G][3].  When
+ * psi_store / mask_store are given, the cell fluxes [G][N][C] and fixed-face
+ * sets of the final sweep of every group are kept (for the adjoint). */
+static int forward_rhs(const Prob *P, const double *p, const double *pu, const double *ext_iso,
+                       double tol, int max_iter, const int *fixed_iters, int fixup, const double *test_inflow,
+                       int nthreads, double *phi, double *dose, int *iters, double *eps, double *bal,
+                       long *nfix_total, double *psi_store, uint8_t *mask_store)
+{
+    const int G = P->G, Nm = P->Nm, N = P->N, L = P->L;
+    const size_t C = (size_t)P->nx * P->ny * P->nz;
+    const double V = P->dx * P->dy * P->dz;
+    const double Ax = P->dy * P->dz, Ay = P->dx * P->dz, Az = P->dx * P->dy;
+    double *ext = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
+    double *Q = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *q = (double *)malloc(sizeof(double) * (size_t)N * C);
+    double *ps = (double *)malloc(sizeof(double) * (size_t)N * C);
+    double *cur = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *nxt = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *sigt = (double *)malloc(sizeof(double) * C);
+    double *leak = (double *)malloc(sizeof(double) * 3 * N);
+    double *inflow = (double *)malloc(sizeof(double) * N);
+    uint8_t *mask = (uint8_t *)malloc((size_t)N * C);
+    if (!ext || !Q || !q || !ps || !cur || !nxt || !sigt || !leak || !inflow || !mask) return -4;
+    orc_first_collision(P->nx, P->ny, P->nz, P->dx, P->dy, P->dz, P->org, P->mat, P->rho, G, L, P->ss, p, pu,
+                        ext_iso, nthreads, ext);
+    for (int g = 0; g < G; ++g) {
+        double bc = test_inflow ? test_inflow[g] : 0.0;
+        for (int n = 0; n < N; ++n) inflow[n] = bc;
+        for (size_t v = 0; v < C; ++v) sigt[v] = P->rho[v] * P->st[(size_t)P->mat[v] * G + g];
+        double *eg = ext + (size_t)g * Nm * C;
+        /* production: volumetric source plus boundary inflow */
+        double Pr = 0.0;
+        for (size_t v = 0; v < C; ++v) Pr += eg[v];
+        Pr *= V;
+        if (bc != 0.0)
+            for (int n = 0; n < N; ++n)
+                Pr += bc * P->w[n] * (fabs(P->dirs[3 * n]) * Ax * P->ny * P->nz + fabs(P->dirs[3 * n + 1]) * Ay * P->nx * P->nz +
+                                      fabs(P->dirs[3 * n + 2]) * Az * P->nx * P->ny);
+        memset(cur, 0, sizeof(double) * (size_t)Nm * C);
+        int it = 0;
+        double e = 0.0;
+        for (;;) {
+            /* scattering source within the group plus the fixed source */
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+            for (long v = 0; v < (long)C; ++v) {
+                int m = P->mat[v];
+                for (int lm = 0; lm < Nm; ++lm)
+                    Q[(size_t)lm * C + v] = eg[(size_t)lm * C + v] + P->rho[v] * ss_at(P, m, P->lof[lm], g, g) * cur[(size_t)lm * C + v];
+            }
+            /* moments -> directions */
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+            for (long v = 0; v < (long)C; ++v)
+                for (int n = 0; n < N; ++n) {
+                    double acc = 0.0;
+                    for (int lm = 0; lm < Nm; ++lm) acc += P->Mmap[(size_t)n * Nm + lm] * Q[(size_t)lm * C + v];
+                    q[(size_t)n * C + v] = acc;
+                }
+            *nfix_total += orc_sweep2(P->nx, P->ny, P->nz, P->dx, P->dy, P->dz, sigt, N, P->dirs, q, inflow, fixup,
+                                      nthreads, ps, leak, NULL, mask);
+            /* directions -> moments (row 0 is the scalar flux, eq. 3) */
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+            for (long v = 0; v < (long)C; ++v)
+                for (int lm = 0; lm < Nm; ++lm) {
+                    double acc = 0.0;
+                    for (int n = 0; n < N; ++n) acc += P->Dmap[(size_t)lm * N + n] * ps[(size_t)n * C + v];
+                    nxt[(size_t)lm * C + v] = acc;
+                }
+            double dmax = 0.0, fmax = 0.0;
+            for (size_t v = 0; v < C; ++v) {
+                double df = fabs(nxt[v] - cur[v]);
+                double f = fabs(nxt[v]);
+                if (df > dmax) dmax = df;
+                if (f > fmax) fmax = f;
+            }
+            e = fmax > 0.0 ? dmax / fmax : 0.0;
+            double *t = cur; cur = nxt; nxt = t;
+            ++it;
+            if (fixed_iters) { if (it >= fixed_iters[g]) break; }
+            else if (e <= tol || it >= max_iter) break;
+        }
+        iters[g] = it;
+        eps[g] = e;
+        if (psi_store) memcpy(psi_store + (size_t)g * N * C, ps, sizeof(double) * (size_t)N * C);
+        if (mask_store) memcpy(mask_store + (size_t)g * N * C, mask, (size_t)N * C);
+        /* balance of the final sweep's group: production, removal, leakage */
+        double R = 0.0;
+        for (size_t v = 0; v < C; ++v) R += (sigt[v] - P->rho[v] * ss_at(P, P->mat[v], 0, g, g)) * cur[v];
+        R *= V;
+        double Lk = 0.0;
+        for (int n = 0; n < N; ++n)
+            Lk += P->w[n] * (fabs(P->dirs[3 * n]) * Ax * leak[3 * n] + fabs(P->dirs[3 * n + 1]) * Ay * leak[3 * n + 1] +
+                             fabs(P->dirs[3 * n + 2]) * Az * leak[3 * n + 2]);
+        bal[g * 3 + 0] = Pr;
+        bal[g * 3 + 1] = R;
+        bal[g * 3 + 2] = Lk;
+        /* downscatter into every lower-energy group */
+        for (int g2 = g + 1; g2 < G; ++g2) {
+            double *e2 = ext + (size_t)g2 * Nm * C;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+            for (long v = 0; v < (long)C; ++v) {
+                int m = P->mat[v];
+                for (int lm = 0; lm < Nm; ++lm)
+                    e2[(size_t)lm * C + v] += P->rho[v] * ss_at(P, m, P->lof[lm], g, g2) * cur[(size_t)lm * C + v];
+            }
+        }
+        memcpy(phi + (size_t)g * Nm * C, cur, sizeof(double) * (size_t)Nm * C);
+        /* dose: collision kerma of uncollided + collided scalar fluence */
+        for (size_t v = 0; v < C; ++v) {
+            double k0 = P->kap[(size_t)P->mat[v] * G + g];
+            if (g == 0) dose[v] = 0.0;
+            dose[v] += k0 * (pu[(size_t)g * C + v] + cur[v]);
+        }
+    }
+    free(ext); free(Q); free(q); free(ps); free(cur); free(nxt); free(sigt); free(leak); free(inflow); free(mask);
+    return 0;
+}
+
+static void make_prob(Prob *P, int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+                      const uint8_t *mat, const double *rho, int G, int M, int L, const double *st, const double *ss,
+                      const double *kap, int N, const double *dirs, const double *w, int *lof)
+{
+    (void)M;
+    P->nx = nx; P->ny = ny; P->nz = nz; P->dx = dx; P->dy = dy; P->dz = dz; P->org = org;
+    P->mat = mat; P->rho = rho; P->G = G; P->M = M; P->L = L; P->Nm = (L + 1) * (L + 1); P->N = N;
+    P->st = st; P->ss = ss; P->kap = kap; P->dirs = dirs; P->w = w;
+    for (int l = 0; l <= L; ++l)
+        for (int m = -l; m <= l; ++m) lof[l * l + l + m] = l;
+    P->lof = lof;
+    double *Mmap = (double *)malloc(sizeof(double) * N * P->Nm);
+    double *Dmap = (double *)malloc(sizeof(double) * N * P->Nm);
+    orc_moment_maps(L, N, dirs, w, Mmap, Dmap);
+    P->Mmap = Mmap;
+    P->Dmap = Dmap;
+}
+
+static void free_prob(Prob *P)
+{
+    free((void *)P->Mmap);
+    free((void *)P->Dmap);
+}
+
 int orc_solve(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
               const uint8_t *mat, const double *rho,
               int G, int M, int L, const double *st, const double *ss, const double *kap,
@@ -369,132 +625,198 @@ int orc_solve(int nx, int ny, int nz, double dx, double dy, double dz, const dou
               long *nfix_out)
 {
     size_t C = (size_t)nx * ny * nz;
-    int Nm = (L + 1) * (L + 1);
     int lof[289];
-    for (int l = 0; l <= L; ++l)
-        for (int m = -l; m <= l; ++m) lof[l * l + l + m] = l;
-    double *Mmap = (double *)malloc(sizeof(double) * N * Nm);
-    double *Dmap = (double *)malloc(sizeof(double) * N * Nm);
-    orc_moment_maps(L, N, dirs, w, Mmap, Dmap);
-    double V = dx * dy * dz;
-    double Ax = dy * dz, Ay = dx * dz, Az = dx * dy;
+    Prob P;
+    make_prob(&P, nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, L, st, ss, kap, N, dirs, w, lof);
+    orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg, cone_deg, gw, nthreads,
+                   phi_u);
+    long nfix = 0;
+    int rc = 0;
+    for (int b = 0; b < B && rc == 0; ++b)
+        rc = forward_rhs(&P, pos + 3 * b, phi_u + (size_t)b * G * C, ext_iso, tol, max_iter, fixed_iters, fixup,
+                         test_inflow, nthreads, phi + (size_t)b * G * P.Nm * C, dose + (size_t)b * C, iters + b * G,
+                         eps + b * G, bal + (size_t)b * G * 3, &nfix, NULL, NULL);
+    if (nfix_out) *nfix_out = nfix;
+    free_prob(&P);
+    return rc;
+}
 
-    orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg,
-                   cone_deg, gw, nthreads, phi_u);
-
-    double *ext = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
-    double *Q = (double *)malloc(sizeof(double) * (size_t)Nm * C);
-    double *q = (double *)malloc(sizeof(double) * (size_t)N * C);
-    double *ps = (double *)malloc(sizeof(double) * (size_t)N * C);
+/* ------------------------------------------------------------------------ */
+/* Adjoint: gradient of R = sum_b sum_v roi_v dose_b(v) with respect to every  */
+/* voxel density and every source group weight, at the converged forward      */
+/* state with the fixup frozen (the solve is then linear in its sources).      */
+/*                                                                            */
+/* Within a group the converged moments satisfy Q = ext + S phi, phi = T Q     */
+/* with T = D L^-1 M (L: the frozen sweep) and S = rho s_l^{gg}.  The adjoint  */
+/* moments lam solve lam = T^T (phibar + S lam), iterated like the forward     */
+/* (T^T = M^T L^-T D^T, L^-T the reversed sweep); groups run from the lowest   */
+/* energy up, each adding rho s_l^{g->g''} lam_{g''} to the moment weight of   */
+/* every higher group that fed it.  Then                                        */
+/*   dR/dsigma_t,g(v) = - sum_n lamc_n(v) psi_n(v)   (cell-centre adjoint x flux) */
+/*   dR/drho_v = sum_g [ t_g dR/dsigma_t,g + sum_lm lam_lm,g dQ_lm,g/drho_v ]    */
+/*   phibar_u,g(v) = roi kappa_g + sum_{g''>=g} sum_lm rho s_l^{g->g''} Y_lm lam  */
+/* and the optical depth of every ray takes back d phi_u / d rho_u =           */
+/* -phi_u l_{v,u} t_g[m_u] (ray back-projection); dR/dw_g follows from phi_u   */
+/* being linear in w_g.                                                         */
+/* ------------------------------------------------------------------------ */
+int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+                const uint8_t *mat, const double *rho,
+                int G, int M, int L, const double *st, const double *ss, const double *kap,
+                int N, const double *dirs, const double *w,
+                int B, const double *pos, const double *axis, double fan_deg, double cone_deg,
+                const double *gw, const double *roi,
+                double tol, int max_iter, const int *fixed_iters, const int *fixed_iters_adj, int fixup,
+                int nthreads, double *R_out, double *d_rho, double *d_gw, int *iters_adj)
+{
+    const size_t C = (size_t)nx * ny * nz;
+    int lof[289];
+    Prob P;
+    make_prob(&P, nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, L, st, ss, kap, N, dirs, w, lof);
+    const int Nm = P.Nm;
+    double *phi_u = (double *)malloc(sizeof(double) * (size_t)B * G * C);
+    double *unit = (double *)malloc(sizeof(double) * (size_t)B * G * C);
+    double *ones = (double *)malloc(sizeof(double) * G);
+    for (int g = 0; g < G; ++g) ones[g] = 1.0;
+    orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg, cone_deg, gw, nthreads,
+                   phi_u);
+    orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg, cone_deg, ones, nthreads,
+                   unit);
+    double *phi = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)G * N * C);
+    uint8_t *mask = (uint8_t *)malloc((size_t)G * N * C);
+    double *dose = (double *)malloc(sizeof(double) * C);
+    int *it_f = (int *)malloc(sizeof(int) * G);
+    double *eps_f = (double *)malloc(sizeof(double) * G);
+    double *bal = (double *)malloc(sizeof(double) * 3 * G);
+    double *lam = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
+    double *pb = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *mu = (double *)malloc(sizeof(double) * (size_t)Nm * C);
+    double *sdir = (double *)malloc(sizeof(double) * (size_t)N * C);
+    double *lc = (double *)malloc(sizeof(double) * (size_t)N * C);
     double *cur = (double *)malloc(sizeof(double) * (size_t)Nm * C);
     double *nxt = (double *)malloc(sizeof(double) * (size_t)Nm * C);
     double *sigt = (double *)malloc(sizeof(double) * C);
-    double *leak = (double *)malloc(sizeof(double) * 3 * N);
-    double *inflow = (double *)malloc(sizeof(double) * N);
-    if (!ext || !Q || !q || !ps || !cur || !nxt || !sigt || !leak || !inflow) return -4;
-    long nfix_total = 0;
-
+    double *pbu = (double *)malloc(sizeof(double) * (size_t)G * C);
+    long nfix = 0;
+    double R = 0.0;
+    memset(d_rho, 0, sizeof(double) * C);
+    memset(d_gw, 0, sizeof(double) * G);
     for (int b = 0; b < B; ++b) {
         const double *p = pos + 3 * b;
         const double *pu = phi_u + (size_t)b * G * C;
-        orc_first_collision(nx, ny, nz, dx, dy, dz, org, mat, rho, G, L, ss, p, pu, ext_iso,
-                            nthreads, ext);
-
-        for (int g = 0; g < G; ++g) {
-            double bc = test_inflow ? test_inflow[g] : 0.0;
-            for (int n = 0; n < N; ++n) inflow[n] = bc;
+        forward_rhs(&P, p, pu, NULL, tol, max_iter, fixed_iters, fixup, NULL, nthreads, phi, dose, it_f, eps_f, bal,
+                    &nfix, psi, mask);
+        for (size_t v = 0; v < C; ++v) R += roi[v] * dose[v];
+        /* direct weights of the dose on both fluence parts */
+        for (int g = 0; g < G; ++g)
+            for (size_t v = 0; v < C; ++v) pbu[(size_t)g * C + v] = roi[v] * kap[(size_t)mat[v] * G + g];
+        memset(lam, 0, sizeof(double) * (size_t)G * Nm * C);
+        for (int g = G - 1; g >= 0; --g) {
             for (size_t v = 0; v < C; ++v) sigt[v] = rho[v] * st[(size_t)mat[v] * G + g];
-            double *eg = ext + (size_t)g * Nm * C;
-            /* production: volumetric source plus boundary inflow */
-            double P = 0.0;
-            for (size_t v = 0; v < C; ++v) P += eg[v];
-            P *= V;
-            if (bc != 0.0)
-                for (int n = 0; n < N; ++n)
-                    P += bc * w[n] * (fabs(dirs[3 * n]) * Ax * ny * nz + fabs(dirs[3 * n + 1]) * Ay * nx * nz +
-                                      fabs(dirs[3 * n + 2]) * Az * nx * ny);
+            /* moment weight of phi_g: dose seed + what the lower groups took from it */
+            for (int lm = 0; lm < Nm; ++lm)
+                for (size_t v = 0; v < C; ++v) {
+                    double acc = lm == 0 ? roi[v] * kap[(size_t)mat[v] * G + g] : 0.0;
+                    for (int g2 = g + 1; g2 < G; ++g2)
+                        acc += rho[v] * ss_at(&P, mat[v], lof[lm], g, g2) * lam[((size_t)g2 * Nm + lm) * C + v];
+                    pb[(size_t)lm * C + v] = acc;
+                }
             memset(cur, 0, sizeof(double) * (size_t)Nm * C);
             int it = 0;
-            double e = 0.0;
+            const uint8_t *mg = mask + (size_t)g * N * C;
             for (;;) {
-                /* scattering source within the group plus the fixed source */
-#pragma omp parallel for schedule(static) num_threads(nthreads)
-                for (long v = 0; v < (long)C; ++v) {
-                    int m = mat[v];
-                    for (int lm = 0; lm < Nm; ++lm) {
-                        double s = ss[(((size_t)m * (L + 1) + lof[lm]) * G + g) * G + g];
-                        Q[(size_t)lm * C + v] = eg[(size_t)lm * C + v] + rho[v] * s * cur[(size_t)lm * C + v];
-                    }
-                }
-                /* moments -> directions */
+                for (int lm = 0; lm < Nm; ++lm)
+                    for (size_t v = 0; v < C; ++v)
+                        mu[(size_t)lm * C + v] = pb[(size_t)lm * C + v] +
+                                                 rho[v] * ss_at(&P, mat[v], lof[lm], g, g) * cur[(size_t)lm * C + v];
+                /* D^T: moment weights -> direction weights */
 #pragma omp parallel for schedule(static) num_threads(nthreads)
                 for (long v = 0; v < (long)C; ++v)
                     for (int n = 0; n < N; ++n) {
                         double acc = 0.0;
-                        for (int lm = 0; lm < Nm; ++lm) acc += Mmap[(size_t)n * Nm + lm] * Q[(size_t)lm * C + v];
-                        q[(size_t)n * C + v] = acc;
+                        for (int lm = 0; lm < Nm; ++lm) acc += P.Dmap[(size_t)lm * N + n] * mu[(size_t)lm * C + v];
+                        sdir[(size_t)n * C + v] = acc;
                     }
-                nfix_total += orc_sweep(nx, ny, nz, dx, dy, dz, sigt, N, dirs, q, inflow, fixup, nthreads, ps, leak);
-                /* directions -> moments (row 0 is the scalar flux, eq. 3) */
+                orc_sweep_adjoint(nx, ny, nz, dx, dy, dz, sigt, N, dirs, sdir, mg, nthreads, lc);
+                /* M^T: direction weights -> moment weights */
 #pragma omp parallel for schedule(static) num_threads(nthreads)
                 for (long v = 0; v < (long)C; ++v)
                     for (int lm = 0; lm < Nm; ++lm) {
                         double acc = 0.0;
-                        for (int n = 0; n < N; ++n) acc += Dmap[(size_t)lm * N + n] * ps[(size_t)n * C + v];
+                        for (int n = 0; n < N; ++n) acc += P.Mmap[(size_t)n * Nm + lm] * lc[(size_t)n * C + v];
                         nxt[(size_t)lm * C + v] = acc;
                     }
                 double dmax = 0.0, fmax = 0.0;
                 for (size_t v = 0; v < C; ++v) {
-                    double df = fabs(nxt[v] - cur[v]);
-                    double f = fabs(nxt[v]);
+                    double df = fabs(nxt[v] - cur[v]), f = fabs(nxt[v]);
                     if (df > dmax) dmax = df;
                     if (f > fmax) fmax = f;
                 }
-                e = fmax > 0.0 ? dmax / fmax : 0.0;
+                double e = fmax > 0.0 ? dmax / fmax : 0.0;
                 double *t = cur; cur = nxt; nxt = t;
                 ++it;
-                if (fixed_iters) { if (it >= fixed_iters[g]) break; }
+                if (fixed_iters_adj) { if (it >= fixed_iters_adj[g]) break; }
                 else if (e <= tol || it >= max_iter) break;
             }
-            iters[b * G + g] = it;
-            eps[b * G + g] = e;
-            /* balance of the final sweep's group: production, removal, leakage */
-            double R = 0.0;
+            if (iters_adj) iters_adj[b * G + g] = it;
+            memcpy(lam + (size_t)g * Nm * C, cur, sizeof(double) * (size_t)Nm * C);
+            const double *psg = psi + (size_t)g * N * C;
+            const double *phg = phi + (size_t)g * Nm * C;
             for (size_t v = 0; v < C; ++v) {
-                double s0 = rho[v] * ss[(((size_t)mat[v] * (L + 1) + 0) * G + g) * G + g];
-                R += (sigt[v] - s0) * cur[v];
-            }
-            R *= V;
-            double Lk = 0.0;
-            for (int n = 0; n < N; ++n)
-                Lk += w[n] * (fabs(dirs[3 * n]) * Ax * leak[3 * n] + fabs(dirs[3 * n + 1]) * Ay * leak[3 * n + 1] +
-                              fabs(dirs[3 * n + 2]) * Az * leak[3 * n + 2]);
-            bal[(b * G + g) * 3 + 0] = P;
-            bal[(b * G + g) * 3 + 1] = R;
-            bal[(b * G + g) * 3 + 2] = Lk;
-            /* downscatter into every lower-energy group */
-            for (int g2 = g + 1; g2 < G; ++g2) {
-                double *e2 = ext + (size_t)g2 * Nm * C;
-#pragma omp parallel for schedule(static) num_threads(nthreads)
-                for (long v = 0; v < (long)C; ++v) {
-                    int m = mat[v];
-                    for (int lm = 0; lm < Nm; ++lm) {
-                        double s = ss[(((size_t)m * (L + 1) + lof[lm]) * G + g) * G + g2];
-                        e2[(size_t)lm * C + v] += rho[v] * s * cur[(size_t)lm * C + v];
+                const int m = mat[v];
+                /* total cross section (cell-centre adjoint x flux of the final sweeps) */
+                double sbar = 0.0;
+                for (int n = 0; n < N; ++n) sbar -= lc[(size_t)n * C + v] * psg[(size_t)n * C + v];
+                double drv = st[(size_t)m * G + g] * sbar;
+                /* dQ/drho: within-group scatter, downscatter in, first collision */
+                double dx_ = (org[0] + ((v % nx) + 0.5) * dx) - p[0];
+                double dy_ = (org[1] + (((v / nx) % ny) + 0.5) * dy) - p[1];
+                double dz_ = (org[2] + ((v / ((size_t)nx * ny)) + 0.5) * dz) - p[2];
+                double r = sqrt(dx_ * dx_ + dy_ * dy_ + dz_ * dz_);
+                double Y[289];
+                orc_real_sh(L, dx_ / r, dy_ / r, dz_ / r, Y);
+                for (int lm = 0; lm < Nm; ++lm) {
+                    double lv = cur[(size_t)lm * C + v];
+                    double dq = ss_at(&P, m, lof[lm], g, g) * phg[(size_t)lm * C + v];
+                    for (int gp = 0; gp < g; ++gp)
+                        dq += ss_at(&P, m, lof[lm], gp, g) * phi[((size_t)gp * Nm + lm) * C + v];
+                    for (int gp = 0; gp <= g; ++gp) {
+                        double s = ss_at(&P, m, lof[lm], gp, g);
+                        dq += s * pu[(size_t)gp * C + v] * Y[lm];
+                        /* the first-collision source also weighs the uncollided flux */
+                        pbu[(size_t)gp * C + v] += rho[v] * s * Y[lm] * lv;
                     }
+                    drv += lv * dq;
                 }
-            }
-            memcpy(phi + ((size_t)b * G + g) * Nm * C, cur, sizeof(double) * (size_t)Nm * C);
-            /* dose: collision kerma of uncollided + collided scalar fluence */
-            for (size_t v = 0; v < C; ++v) {
-                double k0 = kap[(size_t)mat[v] * G + g];
-                if (g == 0) dose[(size_t)b * C + v] = 0.0;
-                dose[(size_t)b * C + v] += k0 * (pu[(size_t)g * C + v] + cur[v]);
+                d_rho[v] += drv;
             }
         }
+        /* ray back-projection of the uncollided weights, and the group weights */
+        int cap = nx + ny + nz + 4;
+        int *vox = (int *)malloc(sizeof(int) * cap);
+        double *len = (double *)malloc(sizeof(double) * cap);
+        for (size_t v = 0; v < C; ++v) {
+            double amat[256];
+            int any = 0;
+            for (int m = 0; m < M; ++m) amat[m] = 0.0;
+            for (int g = 0; g < G; ++g) {
+                double wu = pbu[(size_t)g * C + v] * pu[(size_t)g * C + v];
+                d_gw[g] += pbu[(size_t)g * C + v] * unit[((size_t)b * G + g) * C + v];
+                if (wu != 0.0) any = 1;
+                for (int m = 0; m < M; ++m) amat[m] += st[(size_t)m * G + g] * wu;
+            }
+            if (!any) continue;
+            double x[3] = {org[0] + ((v % nx) + 0.5) * dx, org[1] + (((v / nx) % ny) + 0.5) * dy,
+                           org[2] + ((v / ((size_t)nx * ny)) + 0.5) * dz};
+            int ns = orc_siddon(nx, ny, nz, dx, dy, dz, org, p, x, cap, vox, len);
+            for (int sgi = 0; sgi < ns; ++sgi) d_rho[vox[sgi]] -= len[sgi] * amat[mat[vox[sgi]]];
+        }
+        free(vox);
+        free(len);
     }
-    if (nfix_out) *nfix_out = nfix_total;
-    free(Mmap); free(Dmap); free(ext); free(Q); free(q); free(ps); free(cur); free(nxt);
-    free(sigt); free(leak); free(inflow);
+    if (R_out) *R_out = R;
+    free(phi_u); free(unit); free(ones); free(phi); free(psi); free(mask); free(dose); free(it_f); free(eps_f);
+    free(bal); free(lam); free(pb); free(mu); free(sdir); free(lc); free(cur); free(nxt); free(sigt); free(pbu);
+    free_prob(&P);
     return 0;
 }
