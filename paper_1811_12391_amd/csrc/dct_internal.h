@@ -189,6 +189,8 @@ struct SweepArgs {
     const RhsState *state;
     const double *inflow;     // [G] or null
     int fixup;
+    int sync;                 // 0: barrier per step, 1: LDS progress counters between waves
+    int *err;                 // set to non-zero when a bounded wait overflowed
 };
 
 struct DoseArgs {

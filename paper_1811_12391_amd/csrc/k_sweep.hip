@@ -76,6 +76,22 @@ __device__ __attribute__((noinline)) Cell4<T> dd_fixup(T qv, T sv, T cx, T cy, T
 
 __device__ inline int wrap_row(int r, int nx) { return r == nx ? 0 : (r < 0 ? nx - 1 : r); }
 
+// lane l receives lane l-1's value of v (DPP wave_shr:1); lane 0 receives old
+template <typename T>
+__device__ inline T dpp_shift_up_or(T v, T old);
+template <>
+__device__ inline double dpp_shift_up_or<double>(double v, double old)
+{
+    int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), 0x138, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <>
+__device__ inline float dpp_shift_up_or<float>(float v, float old)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
 template <typename T>
 __device__ inline T lane_shift_up(T v);
 // lane l receives lane l-1's value (DPP wave_shr:1); lane 0 keeps its own
@@ -95,14 +111,33 @@ __device__ inline float lane_shift_up<float>(float v)
     return __int_as_float(x);
 }
 
+// Relaxed LDS int access for the inter-wave progress counters.
+__device__ inline int lds_ld(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void lds_st(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+#define DCT_SPIN_LIMIT (1 << 20)
+
 // One workgroup = one (source, direction, block).  The step loop has no
 // divergent branch around any memory access: prefetch loads are issued for
 // every lane from an always-valid address, so the compiler can wait on
 // exactly the load a step consumes (PF steps after it was issued).
-template <typename T, int PF, bool MULTI>
+//
+// Wave coupling (SYNC = 1): instead of a workgroup barrier per step, wave w
+// publishes its completed step count in LDS (prog[w]) after writing its z
+// outflow into a ring of ZR slots; wave w+1 waits only until prog[w] covers
+// the step it needs, and wave w waits for wave w+1 only when it would
+// overwrite a slot not yet read.  Waves therefore drift out of phase and hide
+// each other's latency.  No deadlock: a wave blocked on its successor is
+// ahead of it, so the successor is not blocked on data; the last wave never
+// waits on a successor.  Every wait is bounded (DCT_SPIN_LIMIT polls); on
+// overflow the kernel raises a->err and leaves the loop.
+// SYNC = 0 keeps one barrier per step (reference schedule).
+template <typename T, int PF, bool MULTI, int SYNC>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
-    __shared__ T zbuf[2][16][64];
+    constexpr int ZR = 4;                                   // z-face ring depth (SYNC = 1)
+    __shared__ T zbuf[SYNC ? 16 : 2][SYNC ? ZR : 16][64];
+    __shared__ int prog[16];
     __shared__ double red[3][16];
     const int item = blockIdx.x;
     const int b = item / a.N;
@@ -114,6 +149,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const int bj = MULTI ? max(0, a.diag - (a.NBK - 1)) + (int)blockIdx.y : 0;
     const int bk = MULTI ? a.diag - bj : 0;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nwv = blockDim.x >> 6;
     const double ox = a.dirs[3 * n], oy = a.dirs[3 * n + 1], oz = a.dirs[3 * n + 2];
     const bool sx = ox > 0, sy = oy > 0, sz = oz > 0;
     const int cls = dir_class(ox, oy);
@@ -125,7 +161,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const int j = valid ? (sy ? jp : ny - 1 - jp) : 0;
     const int k = valid ? (sz ? kp : nz - 1 - kp) : 0;
     const int jm = j % nx;
-    const long rowbase = (long)k * nx * ny + j;
+    const int rowbase = k * nx * ny + j;                    // element offsets fit in 32 bits (C < 2^31)
     const T *qb = (const T *)a.q + (long)item * C;
     T *pb = (T *)a.psi + (long)item * C;
     const T *sg = (const T *)a.sigc + ((long)cls * a.G + g) * C;
@@ -141,16 +177,21 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const int fixup = a.fixup;
     const int NT = nx + nl + nw - 2;
     const int NTp = ((NT + PF - 1) / PF) * PF;
-    const int t0l = l + w;                          // step at which this lane starts its row
-    const int dr = sx ? 1 : -1;                     // rotated-row increment per x step
+    const int t0l = l + w;                                  // step at which this lane starts its row
+    const int dr = sx ? 1 : -1;                             // rotated-row increment per x step
+    const int wrap_at = sx ? nx : -1, wrap_to = sx ? 0 : nx - 1;
     const int rstart = rot_row(cls, sx ? 0 : nx - 1, jm, nx);
     const bool ylast = jp == ny - 1, zlast = kp == nz - 1;
+    if (SYNC) {
+        if (threadIdx.x < 16) prog[threadIdx.x] = 0;
+        __syncthreads();
+    }
 
     T qr[PF], sr[PF], yr[MULTI ? PF : 1], zr[MULTI ? PF : 1];
     int rp = rstart, rc = rstart;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-        const long pp = rowbase + (long)rp * ny;
+        const int pp = rowbase + rp * ny;
         qr[u] = qb[pp];
         sr[u] = sg[pp];
         const bool inp = valid && (unsigned)(u - t0l) < (unsigned)nx;
@@ -159,23 +200,26 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             yr[u] = yf_in[ipc + nx * kpc];
             zr[u] = zf_in[ipc + nx * jpc];
         }
-        rp = inp ? wrap_row(rp + dr, nx) : rp;
+        int rn = rp + dr;
+        rn = rn == wrap_at ? wrap_to : rn;
+        rp = inp ? rn : rp;
     }
-    T xo = bc, yo = 0, zo = 0;
+    T xo = bc, yo = 0, zo = 0;                              // x inflow of a row starts at the boundary value
     double lyv = 0.0, lzv = 0.0;
+    int known_prev = 0, known_next = 0, spins = 0;   // wave-uniform
     for (int tb = 0; tb < NTp; tb += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int t = tb + u;
             const T qv = qr[u], sv = sr[u];
-            T yface_in = (T)0, zface_in = (T)0;
+            T yface_in = bc, zface_in = bc;
             if (MULTI) {
-                yface_in = yr[MULTI ? u : 0];
-                zface_in = zr[MULTI ? u : 0];
+                yface_in = (jp == 0) ? bc : yr[MULTI ? u : 0];
+                zface_in = (kp == 0) ? bc : zr[MULTI ? u : 0];
             }
             {
                 const int tp = t + PF;
-                const long pp = rowbase + (long)rp * ny;
+                const int pp = rowbase + rp * ny;
                 qr[u] = qb[pp];
                 sr[u] = sg[pp];
                 const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
@@ -184,21 +228,37 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                     yr[MULTI ? u : 0] = yf_in[ipc + nx * kpc];
                     zr[MULTI ? u : 0] = zf_in[ipc + nx * jpc];
                 }
-                rp = inp ? wrap_row(rp + dr, nx) : rp;
+                int rn = rp + dr;
+                rn = rn == wrap_at ? wrap_to : rn;
+                rp = inp ? rn : rp;
             }
             const int ip = t - t0l;
             const bool act = valid && (unsigned)ip < (unsigned)nx;
-            T yin = lane_shift_up<T>(yo);
-            T zin = zbuf[(t + 1) & 1][w > 0 ? w - 1 : 0][l];
-            if (MULTI) {
-                if (l == 0) yin = (jp == 0) ? bc : yface_in;
-                if (w == 0) zin = (kp == 0) ? bc : zface_in;
+            // y inflow: lane l-1's outflow of the previous step; lane 0 takes the
+            // boundary / block face value through the DPP "old" operand
+            const T yin = dpp_shift_up_or<T>(yo, yface_in);
+            T zin;
+            if (SYNC) {
+                if (w > 0) {
+                    // wave-uniform bounded wait; an exhausted budget makes every
+                    // later wait fall through (the error flag is raised below)
+                    while (known_prev < t && spins < DCT_SPIN_LIMIT) {
+                        known_prev = __builtin_amdgcn_readfirstlane(lds_ld(&prog[w - 1]));
+                        if (known_prev < t) {
+                            __builtin_amdgcn_s_sleep(1);
+                            ++spins;
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                    zin = zbuf[w - 1][(t - 1) & (ZR - 1)][l];
+                } else {
+                    zin = zface_in;
+                }
             } else {
-                if (l == 0) yin = bc;
-                if (w == 0) zin = bc;
+                zin = (w > 0) ? zbuf[(t + 1) & 1][w > 0 ? w - 1 : 0][l] : zface_in;
             }
-            const T xin = (ip == 0) ? bc : xo;
             if (act) {
+                const T xin = xo;
                 const T num = qv + cx * xin + cy * yin + cz * zin;
                 Cell4<T> c;
                 c.pc = qdiv(num, sv + csum);
@@ -207,23 +267,40 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 c.zo = c.pc + c.pc - zin;
                 if (fixup && __builtin_expect(fmin(c.xo, fmin(c.yo, c.zo)) < (T)0, 0))
                     c = dd_fixup<T>(qv, sv, cx, cy, cz, xin, yin, zin, c);
-                const T pc = c.pc, ax_ = c.xo, ay_ = c.yo, az_ = c.zo;
-                pb[rowbase + (long)rc * ny] = pc;
-                rc = wrap_row(rc + dr, nx);
-                lyv += (double)ay_;
-                lzv += (double)az_;
+                pb[rowbase + rc * ny] = c.pc;
+                int rn = rc + dr;
+                rc = rn == wrap_at ? wrap_to : rn;
+                lyv += (double)c.yo;
+                lzv += (double)c.zo;
                 if (MULTI) {
-                    if (l == nl - 1 && jp < ny - 1) yf_out[ip + nx * kp] = ay_;
-                    if (w == nw - 1 && kp < nz - 1) zf_out[ip + nx * jp] = az_;
+                    if (l == nl - 1 && jp < ny - 1) yf_out[ip + nx * kp] = c.yo;
+                    if (w == nw - 1 && kp < nz - 1) zf_out[ip + nx * jp] = c.zo;
                 }
-                xo = ax_;
-                yo = ay_;
-                zo = az_;
+                xo = c.xo;
+                yo = c.yo;
+                zo = c.zo;
             }
-            zbuf[t & 1][w][l] = zo;
-            __syncthreads();
+            if (SYNC) {
+                if (w + 1 < nwv) {
+                    const int need = t - ZR + 2;                // successor must have read slot t - ZR
+                    while (known_next < need && spins < DCT_SPIN_LIMIT) {
+                        known_next = __builtin_amdgcn_readfirstlane(lds_ld(&prog[w + 1]));
+                        if (known_next < need) {
+                            __builtin_amdgcn_s_sleep(1);
+                            ++spins;
+                        }
+                    }
+                }
+                zbuf[w][t & (ZR - 1)][l] = zo;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                if (l == 0) lds_st(&prog[w], t + 1);
+            } else {
+                zbuf[t & 1][w][l] = zo;
+                __syncthreads();
+            }
         }
     }
+    if (SYNC && spins >= DCT_SPIN_LIMIT && l == 0) atomicOr(a.err, 1);
     // boundary outflow sums of this block (for the particle balance): the last
     // x outflow of every row, and the y / z outflows of the boundary rows
     double lx = valid ? (double)xo : 0.0;
@@ -242,7 +319,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     __syncthreads();
     if (threadIdx.x < 3) {
         double s = 0.0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[threadIdx.x][q];
+        for (int q = 0; q < nwv; ++q) s += red[threadIdx.x][q];
         a.leak_part[((long)item * a.nblk + bj * a.NBK + bk) * 3 + threadIdx.x] = s;
     }
 }
@@ -255,13 +332,15 @@ hipError_t launch_sweep(const SweepArgs &a, int is_f64, hipStream_t s)
     dim3 grid((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
     dim3 block(64 * a.BK);
     const bool multi = NBJ > 1 || NBK > 1;
-    if (is_f64) {
-        if (multi) hipLaunchKernelGGL((k_sweep<double, 4, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sweep<double, 4, false>), grid, block, 0, s, a);
+#define DCT_LAUNCH_SWEEP(T, PF, M, S) hipLaunchKernelGGL((k_sweep<T, PF, M, S>), grid, block, 0, s, a)
+    if (a.sync) {
+        if (is_f64) { if (multi) DCT_LAUNCH_SWEEP(double, 4, true, 1); else DCT_LAUNCH_SWEEP(double, 4, false, 1); }
+        else { if (multi) DCT_LAUNCH_SWEEP(float, 8, true, 1); else DCT_LAUNCH_SWEEP(float, 8, false, 1); }
     } else {
-        if (multi) hipLaunchKernelGGL((k_sweep<float, 8, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sweep<float, 8, false>), grid, block, 0, s, a);
+        if (is_f64) { if (multi) DCT_LAUNCH_SWEEP(double, 4, true, 0); else DCT_LAUNCH_SWEEP(double, 4, false, 0); }
+        else { if (multi) DCT_LAUNCH_SWEEP(float, 8, true, 0); else DCT_LAUNCH_SWEEP(float, 8, false, 0); }
     }
+#undef DCT_LAUNCH_SWEEP
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -503,6 +504,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(dbuf(ctx, "iters", (size_t)B * G * 4, &d_iters));
     HC(dbuf(ctx, "eps", (size_t)B * G * 8, &d_eps));
     HC(dbuf(ctx, "unf", 256, &d_unf));
+    void *d_err;
+    HC(dbuf(ctx, "err", 256, &d_err));
     HC(dbuf(ctx, "dose", (size_t)B * C * 8, &d_dose));
 
     // ---------------- inputs: uploaded once, kept on the device until a set_* call
@@ -590,6 +593,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(hipMemsetAsync(d_iters, 0, (size_t)B * G * 4, s));
     HC(hipMemsetAsync(d_eps, 0, (size_t)B * G * 8, s));
     HC(hipMemsetAsync(d_leak, 0, (size_t)B * N * pl.nblk * 3 * 8, s));
+    HC(hipMemsetAsync(d_err, 0, 4, s));
 
     Geo geo;
     geo.nx = nx;
@@ -692,6 +696,11 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     sw.state = (const RhsState *)d_state;
     sw.inflow = (const double *)d_infl;
     sw.fixup = o.fixup;
+    {
+        const char *e = getenv("DCT_SWEEP_SYNC");
+        sw.sync = e ? atoi(e) : 1;
+    }
+    sw.err = (int *)d_err;
 
     CombArgs cb;
     cb.geo = geo;
@@ -779,6 +788,12 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(hipMemcpy(fin.data(), d_state, (size_t)B * sizeof(RhsState), hipMemcpyDeviceToHost));
     std::vector<int> iters((size_t)B * G);
     HC(hipMemcpy(iters.data(), d_iters, iters.size() * 4, hipMemcpyDeviceToHost));
+    int h_err = 0;
+    HC(hipMemcpy(&h_err, d_err, 4, hipMemcpyDeviceToHost));
+    if (h_err) {
+        ctx->solved = false;
+        return fail(ctx, DCT_EDEVICE, "solve: a sweep wave wait exceeded its bound (inter-wave synchronisation)");
+    }
     int status = DCT_OK;
     bool any_nan = false, any_nc = false;
     for (int b = 0; b < B; ++b) {
