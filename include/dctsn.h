@@ -67,6 +67,8 @@ typedef struct dct_opts {
     int chunk;                /* iterations enqueued between host convergence polls (0 = auto) */
     int use_graph;            /* 1: capture one iteration in a HIP graph and replay it */
     int profile;              /* 1: time every sweep launch with HIP events (dct_stats) */
+    int keep_adjoint;         /* 1: keep every group's final angular flux and fixup pattern
+                                 on the device so that dct_adjoint can follow this solve */
 } dct_opts;
 
 typedef struct dct_stats {
@@ -106,7 +108,7 @@ int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy,
 /* Multigroup cross sections per unit density (Sec. II-B / II-D: multigroup
  * library; eq. (2) with a Legendre expansion of the scattering kernel).
  *   G >= 1 groups, edges_keV[G+1] strictly descending (may be NULL);
- *   M in [1, 8] materials; L in [0, 7] Legendre order;
+ *   M in [1, 8] materials; L in [0, 5] Legendre order;
  *   sigma_t[M][G] cm^2/g total;
  *   sigma_s[M][L+1][G][G] cm^2/g Legendre moments s_l^{g->g'} (from, to),
  *     zero for g' < g (no upscatter);
@@ -161,6 +163,23 @@ int dct_dose(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_
 /* As dct_dose, into DEVICE buffers of the context's device, written on the
  * context's stream (asynchronous). */
 int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c);
+
+/* Gradient of the response R = sum_b sum_v roi[v] dose_b(v) with respect to
+ * every voxel density and every source group weight, by the adjoint of the
+ * discretised solve at the converged state of the last dct_solve (which must
+ * have run with keep_adjoint = 1): the fixup pattern is frozen, groups are
+ * traversed from the lowest energy up, the within-group adjoint is iterated
+ * with the transposed maps and reverse-direction sweeps, and the uncollided
+ * flux's dependence on every density along each ray is back-projected.
+ * (The paper computes the dose only, Sec. II-A; the gradient is an addition
+ * built on the same discrete equations.)
+ *   roi[C] host weights; opts: tol / max_iter / fixed_iters of the adjoint
+ *   iterations (precision is that of the forward solve; NULL = tol 1e-6);
+ *   outputs (host, caller-allocated, any may be NULL): R[1], d_density[C]
+ *   (per g/cm^3), d_group_w[G].
+ * ESTATE if there is no kept solve. */
+int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
+                double *d_group_w, dct_stats *stats);
 
 /* All collided flux moments of the last solve into a host buffer
  * phi[B][G][Nm][C] (FP64 whatever the precision). */

@@ -97,6 +97,9 @@ struct RhsState {
     unsigned int cnt_combine, cnt_trans;   // last-block-done counters
 };
 
+// group actually processed at position g of the group sequence
+__host__ __device__ inline int eff_group(int g, int G, int reverse) { return reverse ? G - 1 - g : g; }
+
 struct Geo {
     int nx, ny, nz;
     long C;
@@ -156,6 +159,7 @@ struct CombArgs {
     double tol;
     int max_iter;
     int nblocks_per_b;
+    int reverse;              // groups run from G-1 down to 0
 };
 
 struct MapArgs {
@@ -168,7 +172,9 @@ struct MapArgs {
     int NcP, NmP;
     const void *Qc;           // T [2][B][Nm][C]
     void *q;                  // T [B][N][C]
-    const void *psi;          // T [B][N][C]
+    const void *psi;          // T, slot (b*psi_bs + g*psi_gs + n) * C
+    long psi_bs, psi_gs;
+    int G, reverse;
     void *part;               // T [2][B][Nm][C]
     const RhsState *state;
 };
@@ -181,7 +187,11 @@ struct SweepArgs {
     const double *dirs;
     double dx, dy, dz;
     const void *q;            // T [B][N][C]
-    void *psi;                // T [B][N][C]
+    void *psi;                // T, direction n of RHS b in group g at (b*psi_bs + g*psi_gs + n) * C
+    long psi_bs, psi_gs;      // slot strides (in units of C): N, 0 normally; G*N, N when kept per group
+    uint8_t *mask;            // fixed-face sets [B][G][N][C] (kept per group) or null
+    int reverse;              // groups run from G-1 down to 0 (adjoint machine)
+    int adjoint;              // transposed sweep: reverse traversal, frozen masks, no fixup decisions
     const void *sigc;         // T [2][G][C]
     void *yface;              // T [B*N][nx*nz]
     void *zface;              // T [B*N][nx*ny]
@@ -191,6 +201,42 @@ struct SweepArgs {
     int fixup;
     int sync;                 // 0: barrier per step, 1: LDS progress counters between waves
     int *err;                 // set to non-zero when a bounded wait overflowed
+};
+
+struct AdjTransArgs {
+    Geo geo;
+    int G, M, L, Nm, N, B;
+    const uint8_t *mat;
+    const double *rho;
+    const double *st, *ss, *kap;
+    const double *pos;        // [B][3]
+    const double *roi;        // [C]
+    const double *phi_u;      // [B][G][C]
+    const void *phi_all;      // T [B][G][Nm][C] forward moments
+    const void *psi_keep;     // T forward cell fluxes, slot (b*G*N + g*N + n) * C, class layouts
+    const void *lamc;         // T adjoint cell values [B][N][C], class layouts
+    const double *dirs;
+    void *lam_all;            // T [B][G][Nm][C]
+    void *phibar;             // T [B][Nm][C]
+    void *Qc;                 // T [2][B][Nm][C]
+    double *pbu;              // [B][G][C] weights on the uncollided flux
+    double *drho;             // [B][C]
+    RhsState *state;
+    int *n_unfinished;
+};
+
+struct AdjRayArgs {
+    Geo geo;
+    const uint8_t *mat;
+    const double *rho;
+    const double *st;         // [M][G]
+    int G, M, B;
+    const double *pos, *axis;
+    double half_fan, half_cone;
+    const double *gw;
+    const double *pbu;        // [B][G][C]
+    double *drho_ray;         // [C] (atomics)
+    double *dgw;              // [G] (atomics)
 };
 
 struct DoseArgs {
@@ -216,6 +262,10 @@ hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_dose(const DoseArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_adj_ray(const AdjRayArgs &a, hipStream_t s);
+hipError_t launch_adj_init(long C, int G, int B, const uint8_t *mat, const double *kap, const double *roi,
+                           double *pbu, hipStream_t s);
 hipError_t launch_moments_out(const void *phi_all, long n, double *out, int is_f64, hipStream_t s);
 
 }  // namespace dct

@@ -129,7 +129,8 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
     const bool inb = p < C;
     const int Nm = a.Nm, Nc = a.Nc[c];
     const int *cd = a.cdir + c * a.N;
-    const T *psi = (const T *)a.psi + (long)b * a.N * C;
+    const int g = eff_group(a.state[b].g, a.G, a.reverse);
+    const T *psi = (const T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
     const T *Dt = (const T *)a.Dtab + (long)c * a.NmP * a.NcP;
     T *part = (T *)a.part + ((long)c * a.B + b) * Nm * C;
     for (int rb = 0; rb * 16 < Nm; ++rb) {
@@ -157,7 +158,8 @@ __global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
     const bool inb = p < C;
     const int Nm = a.Nm, Nc = a.Nc[c];
     const int *cd = a.cdir + c * a.N;
-    const float *psi = (const float *)a.psi + (long)b * a.N * C;
+    const int g = eff_group(a.state[b].g, a.G, a.reverse);
+    const float *psi = (const float *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
     const short *Dt = (const short *)a.Dtab + (long)c * a.NmP * a.NcP;
     float *part = (float *)a.part + ((long)c * a.B + b) * Nm * C;
     for (int rb = 0; rb * 16 < Nm; ++rb) {

@@ -169,6 +169,119 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
     }
 }
 
+// Adjoint machine transition (groups from G-1 down to 0).  When group gp has
+// converged it adds that group's terms of dR/drho_v (cross-section term
+// -sum_n lamc_n psi_n t_g and the source terms sum_lm lam_lm dQ_lm/drho) and
+// moves the first-collision part of the adjoint onto the uncollided flux
+// weights; then it builds the adjoint moment source of the next (higher)
+// group: the dose seed plus what every lower group took from it by
+// downscatter, and starts its iteration from lam = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
+{
+    const int b = blockIdx.y;
+    RhsState *st = a.state + b;
+    if (!st->pending) return;
+    const int gs = st->g;                          // position in the reversed group sequence
+    const int G = a.G, L = a.L, Nm = a.Nm, N = a.N;
+    const Geo &geo = a.geo;
+    const long C = geo.C;
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    if (v < C) {
+        const int m = a.mat[v];
+        const double rho = a.rho[v];
+        const int i = (int)(v % geo.nx);
+        const int j = (int)((v / geo.nx) % geo.ny);
+        const int k = (int)(v / ((long)geo.nx * geo.ny));
+        const double *p = a.pos + 3 * b;
+        double d0 = geo.org[0] + (i + 0.5) * geo.dx - p[0];
+        double d1 = geo.org[1] + (j + 0.5) * geo.dy - p[1];
+        double d2 = geo.org[2] + (k + 0.5) * geo.dz - p[2];
+        double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        double Y[DCT_MAXNM];
+        real_sh_cart<double>(L, d0 / r, d1 / r, d2 / r, Y);
+        const T *phi_all = (const T *)a.phi_all;
+        T *lam_all = (T *)a.lam_all;
+        if (gs > 0) {
+            const int gp = G - gs;                 // the group that just converged
+            // cross-section term from the final sweeps of group gp
+            const T *pk = (const T *)a.psi_keep + ((long)b * G + gp) * N * C;
+            const T *lc = (const T *)a.lamc + (long)b * N * C;
+            const long pos0 = cls_pos(0, i, j, k, geo.nx, geo.ny), pos1 = cls_pos(1, i, j, k, geo.nx, geo.ny);
+            double sbar = 0.0;
+            for (int n = 0; n < N; ++n) {
+                const long pp = dir_class(a.dirs[3 * n], a.dirs[3 * n + 1]) == 0 ? pos0 : pos1;
+                sbar -= (double)lc[(long)n * C + pp] * (double)pk[(long)n * C + pp];
+            }
+            double drv = a.st[m * G + gp] * sbar;
+            const T *lamg = lam_all + ((long)b * G + gp) * Nm * C;
+            for (int lm = 0; lm < Nm; ++lm) {
+                const int l = l_of(lm);
+                const double *sl = a.ss + ((long)m * (L + 1) + l) * G * G;
+                const double lv = (double)lamg[(long)lm * C + v];
+                double dq = sl[gp * G + gp] * (double)phi_all[(((long)b * G + gp) * Nm + lm) * C + v];
+                for (int g2 = 0; g2 < gp; ++g2) {
+                    double s = sl[g2 * G + gp];
+                    if (s != 0.0) dq += s * (double)phi_all[(((long)b * G + g2) * Nm + lm) * C + v];
+                }
+                for (int g2 = 0; g2 <= gp; ++g2) {
+                    double s = sl[g2 * G + gp];
+                    if (s != 0.0) {
+                        const double pu = a.phi_u[((long)b * G + g2) * C + v];
+                        dq += s * pu * Y[lm];
+                        a.pbu[((long)b * G + g2) * C + v] += rho * s * Y[lm] * lv;
+                    }
+                }
+                drv += lv * dq;
+            }
+            a.drho[(long)b * C + v] += drv;
+        }
+        if (gs < G) {
+            const int g = G - 1 - gs;              // the group to set up
+            T *pb = (T *)a.phibar + (long)b * Nm * C;
+            T *QA = (T *)a.Qc + (long)b * Nm * C;
+            T *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
+            const long pA = cls_pos(0, i, j, k, geo.nx, geo.ny), pB = cls_pos(1, i, j, k, geo.nx, geo.ny);
+            for (int lm = 0; lm < Nm; ++lm) {
+                const int l = l_of(lm);
+                const double *sl = a.ss + ((long)m * (L + 1) + l) * G * G;
+                double e = lm == 0 ? a.roi[v] * a.kap[m * G + g] : 0.0;
+                for (int g2 = g + 1; g2 < G; ++g2) {
+                    double s = sl[g * G + g2];
+                    if (s != 0.0) e += rho * s * (double)lam_all[(((long)b * G + g2) * Nm + lm) * C + v];
+                }
+                const T et = (T)e;
+                pb[(long)lm * C + v] = et;
+                lam_all[(((long)b * G + g) * Nm + lm) * C + v] = (T)0;
+                QA[(long)lm * C + pA] = et;
+                QB[(long)lm * C + pB] = et;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned prev = atomicAdd(&st->cnt_trans, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            st->cnt_trans = 0;
+            st->pending = 0;
+            if (gs >= G) {
+                st->finished = 1;
+                atomicSub(a.n_unfinished, 1);
+            }
+        }
+    }
+}
+
+hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
+    if (is_f64) hipLaunchKernelGGL(k_adj_transition<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_adj_transition<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s)
 {
     dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
@@ -188,7 +301,8 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     const int b = blockIdx.y;
     RhsState *st = a.state + b;
     if (st->finished) return;
-    const int g = st->g;
+    const int gseq = st->g;
+    const int g = eff_group(gseq, a.G, a.reverse);
     const int nx = a.geo.nx, ny = a.geo.ny;
     const unsigned nblocks_b = gridDim.x * gridDim.z;   // blocks of this RHS (slabs x moments)
     const long C = a.geo.C;
@@ -288,7 +402,7 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             if (stop) {
                 a.iters[(long)b * G + g] = it;
                 a.eps[(long)b * G + g] = e;
-                st->g = bad ? G : g + 1;
+                st->g = bad ? G : gseq + 1;
                 st->it = 0;
                 st->pending = 1;
             }

@@ -49,7 +49,7 @@ __device__ inline float qdiv(float n, float d)
 // Set-to-zero fixup of one cell (rare path): faces with a negative outflow are
 // closed (outflow 0, inflow weighted c_a / 2 in the balance) until no new
 // negative face appears.  Returns (psi_c, out_x, out_y, out_z) by value.
-template <typename T> struct Cell4 { T pc, xo, yo, zo; };
+template <typename T> struct Cell4 { T pc, xo, yo, zo; int fixed; };
 
 template <typename T>
 __device__ __attribute__((noinline)) Cell4<T> dd_fixup(T qv, T sv, T cx, T cy, T cz, T xin, T yin, T zin,
@@ -71,6 +71,7 @@ __device__ __attribute__((noinline)) Cell4<T> dd_fixup(T qv, T sv, T cx, T cy, T
         c.yo = fy ? (T)0 : c.pc + c.pc - yin;
         c.zo = fz ? (T)0 : c.pc + c.pc - zin;
     }
+    c.fixed = (fx ? 1 : 0) | (fy ? 2 : 0) | (fz ? 4 : 0);
     return c;
 }
 
@@ -132,7 +133,13 @@ __device__ inline void lds_st(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC
 // waits on a successor.  Every wait is bounded (DCT_SPIN_LIMIT polls); on
 // overflow the kernel raises a->err and leaves the loop.
 // SYNC = 0 keeps one barrier per step (reference schedule).
-template <typename T, int PF, bool MULTI, int SYNC>
+// ADJ: the transposed sweep of the frozen-fixup forward sweep (adjoint of the
+// cell relations): cells visited in the reverse order (the octant of -Omega),
+// the adjoint face values h enter exactly like DD inflows on faces that were
+// not fixed, while a fixed face contributes nothing and passes h_out = lambda:
+//   lambda = (s + sum_{a free} c_a h_a) / (sigma + sum_{a free} c_a),
+//   h_out,a = 2 lambda - h_a (free) or lambda (fixed).
+template <typename T, int PF, bool MULTI, int SYNC, bool ADJ>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     constexpr int ZR = 4;                                   // z-face ring depth (SYNC = 1)
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const int b = item / a.N;
     const int n = item - b * a.N;
     if (a.state[b].finished) return;
-    const int g = a.state[b].g;
+    const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const long C = a.C;
     const int bj = MULTI ? max(0, a.diag - (a.NBK - 1)) + (int)blockIdx.y : 0;
@@ -151,7 +158,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nwv = blockDim.x >> 6;
     const double ox = a.dirs[3 * n], oy = a.dirs[3 * n + 1], oz = a.dirs[3 * n + 2];
-    const bool sx = ox > 0, sy = oy > 0, sz = oz > 0;
+    const bool sx = ADJ ? !(ox > 0) : ox > 0, sy = ADJ ? !(oy > 0) : oy > 0, sz = ADJ ? !(oz > 0) : oz > 0;
     const int cls = dir_class(ox, oy);
     const T cx = (T)(2.0 * fabs(ox) / a.dx), cy = (T)(2.0 * fabs(oy) / a.dy), cz = (T)(2.0 * fabs(oz) / a.dz);
     const T csum = cx + cy + cz;
@@ -163,7 +170,8 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const int jm = j % nx;
     const int rowbase = k * nx * ny + j;                    // element offsets fit in 32 bits (C < 2^31)
     const T *qb = (const T *)a.q + (long)item * C;
-    T *pb = (T *)a.psi + (long)item * C;
+    T *pb = (T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs + n) * C;
+    uint8_t *mb = a.mask ? a.mask + (((long)b * a.G + g) * a.N + n) * C : nullptr;
     const T *sg = (const T *)a.sigc + ((long)cls * a.G + g) * C;
     // block faces, ping-pong by block parity so a block never reads a location
     // that a block of the same launch writes
@@ -188,12 +196,14 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     }
 
     T qr[PF], sr[PF], yr[MULTI ? PF : 1], zr[MULTI ? PF : 1];
+    int fr[ADJ ? PF : 1];
     int rp = rstart, rc = rstart;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const int pp = rowbase + rp * ny;
         qr[u] = qb[pp];
         sr[u] = sg[pp];
+        if (ADJ) fr[ADJ ? u : 0] = mb[pp];
         const bool inp = valid && (unsigned)(u - t0l) < (unsigned)nx;
         if (MULTI) {
             const int ipc = inp ? u - t0l : 0;
@@ -212,6 +222,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         for (int u = 0; u < PF; ++u) {
             const int t = tb + u;
             const T qv = qr[u], sv = sr[u];
+            const int fv = ADJ ? fr[ADJ ? u : 0] : 0;
             T yface_in = bc, zface_in = bc;
             if (MULTI) {
                 yface_in = (jp == 0) ? bc : yr[MULTI ? u : 0];
@@ -222,6 +233,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 const int pp = rowbase + rp * ny;
                 qr[u] = qb[pp];
                 sr[u] = sg[pp];
+                if (ADJ) fr[ADJ ? u : 0] = mb[pp];
                 const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
                 if (MULTI) {
                     const int ipc = inp ? tp - t0l : 0;
@@ -259,14 +271,26 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             }
             if (act) {
                 const T xin = xo;
-                const T num = qv + cx * xin + cy * yin + cz * zin;
                 Cell4<T> c;
-                c.pc = qdiv(num, sv + csum);
-                c.xo = c.pc + c.pc - xin;
-                c.yo = c.pc + c.pc - yin;
-                c.zo = c.pc + c.pc - zin;
-                if (fixup && __builtin_expect(fmin(c.xo, fmin(c.yo, c.zo)) < (T)0, 0))
-                    c = dd_fixup<T>(qv, sv, cx, cy, cz, xin, yin, zin, c);
+                if (ADJ) {
+                    const bool ux = !(fv & 1), uy = !(fv & 2), uz = !(fv & 4);
+                    const T ex = ux ? cx : (T)0, ey = uy ? cy : (T)0, ez = uz ? cz : (T)0;
+                    const T num = qv + ex * xin + ey * yin + ez * zin;
+                    c.pc = qdiv(num, sv + ex + ey + ez);
+                    c.xo = ux ? c.pc + c.pc - xin : c.pc;
+                    c.yo = uy ? c.pc + c.pc - yin : c.pc;
+                    c.zo = uz ? c.pc + c.pc - zin : c.pc;
+                } else {
+                    const T num = qv + cx * xin + cy * yin + cz * zin;
+                    c.pc = qdiv(num, sv + csum);
+                    c.xo = c.pc + c.pc - xin;
+                    c.yo = c.pc + c.pc - yin;
+                    c.zo = c.pc + c.pc - zin;
+                    c.fixed = 0;
+                    if (fixup && __builtin_expect(fmin(c.xo, fmin(c.yo, c.zo)) < (T)0, 0))
+                        c = dd_fixup<T>(qv, sv, cx, cy, cz, xin, yin, zin, c);
+                    if (mb) mb[rowbase + rc * ny] = (uint8_t)c.fixed;
+                }
                 pb[rowbase + rc * ny] = c.pc;
                 int rn = rc + dr;
                 rc = rn == wrap_at ? wrap_to : rn;
@@ -332,14 +356,17 @@ hipError_t launch_sweep(const SweepArgs &a, int is_f64, hipStream_t s)
     dim3 grid((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
     dim3 block(64 * a.BK);
     const bool multi = NBJ > 1 || NBK > 1;
-#define DCT_LAUNCH_SWEEP(T, PF, M, S) hipLaunchKernelGGL((k_sweep<T, PF, M, S>), grid, block, 0, s, a)
+#define DCT_LAUNCH_SWEEP(T, PF, M, S, A) hipLaunchKernelGGL((k_sweep<T, PF, M, S, A>), grid, block, 0, s, a)
+#define DCT_LAUNCH_SWEEP_A(T, PF, M, S) \
+    do { if (a.adjoint) DCT_LAUNCH_SWEEP(T, PF, M, S, true); else DCT_LAUNCH_SWEEP(T, PF, M, S, false); } while (0)
     if (a.sync) {
-        if (is_f64) { if (multi) DCT_LAUNCH_SWEEP(double, 4, true, 1); else DCT_LAUNCH_SWEEP(double, 4, false, 1); }
-        else { if (multi) DCT_LAUNCH_SWEEP(float, 8, true, 1); else DCT_LAUNCH_SWEEP(float, 8, false, 1); }
+        if (is_f64) { if (multi) DCT_LAUNCH_SWEEP_A(double, 4, true, 1); else DCT_LAUNCH_SWEEP_A(double, 4, false, 1); }
+        else { if (multi) DCT_LAUNCH_SWEEP_A(float, 8, true, 1); else DCT_LAUNCH_SWEEP_A(float, 8, false, 1); }
     } else {
-        if (is_f64) { if (multi) DCT_LAUNCH_SWEEP(double, 4, true, 0); else DCT_LAUNCH_SWEEP(double, 4, false, 0); }
-        else { if (multi) DCT_LAUNCH_SWEEP(float, 8, true, 0); else DCT_LAUNCH_SWEEP(float, 8, false, 0); }
+        if (is_f64) { if (multi) DCT_LAUNCH_SWEEP_A(double, 4, true, 0); else DCT_LAUNCH_SWEEP_A(double, 4, false, 0); }
+        else { if (multi) DCT_LAUNCH_SWEEP_A(float, 8, true, 0); else DCT_LAUNCH_SWEEP_A(float, 8, false, 0); }
     }
+#undef DCT_LAUNCH_SWEEP_A
 #undef DCT_LAUNCH_SWEEP
     return hipGetLastError();
 }

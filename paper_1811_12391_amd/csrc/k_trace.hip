@@ -14,40 +14,14 @@
 
 namespace dct {
 
-__global__ __launch_bounds__(256) void k_trace(TraceArgs a)
+// Siddon march from p along d (target = p + d, inside the grid): calls
+// f(voxel, length) for every segment between consecutive plane crossings,
+// the voxel being the one holding the segment midpoint.
+template <class F>
+__device__ inline void siddon_march(const Geo &g, const double *p, const double *d, double r, F f)
 {
-    const Geo &g = a.geo;
-    long v = (long)blockIdx.x * 256 + threadIdx.x;
-    int b = blockIdx.y;
-    if (v >= g.C) return;
-    int i = (int)(v % g.nx);
-    int j = (int)((v / g.nx) % g.ny);
-    int k = (int)(v / ((long)g.nx * g.ny));
     const double del[3] = {g.dx, g.dy, g.dz};
     const int nn[3] = {g.nx, g.ny, g.nz};
-    const double *p = a.pos + 3 * b;
-    double d[3];
-    d[0] = g.org[0] + (i + 0.5) * g.dx - p[0];
-    d[1] = g.org[1] + (j + 0.5) * g.dy - p[1];
-    d[2] = g.org[2] + (k + 0.5) * g.dz - p[2];
-    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    double r = sqrt(r2);
-    double *out = a.phi_u + (long)b * a.G * g.C + v;
-
-    // beam window: azimuth about z from the projected axis, elevation from z = 0
-    double ax = a.axis[3 * b], ay = a.axis[3 * b + 1];
-    double an = hypot(ax, ay);
-    ax /= an;
-    ay /= an;
-    double along = d[0] * ax + d[1] * ay;
-    double across = -d[0] * ay + d[1] * ax;
-    double az = atan2(across, along);
-    double el = atan2(d[2], hypot(d[0], d[1]));
-    if (!(fabs(az) <= a.half_fan && fabs(el) <= a.half_cone)) {
-        for (int gg = 0; gg < a.G; ++gg) out[(long)gg * g.C] = 0.0;
-        return;
-    }
-
     // entry into the grid box (slab method); the target is inside the box
     double a_in = 0.0;
     for (int t = 0; t < 3; ++t) {
@@ -87,10 +61,6 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
         mpl[t] = m;
         anext[t] = tt;
     }
-
-    double acc[DCT_MAXMAT];
-#pragma unroll
-    for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] = 0.0;
     double a0 = a_in;
     const int cap = g.nx + g.ny + g.nz + 4;
     for (int it = 0; it < cap; ++it) {
@@ -105,11 +75,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
             int c = (int)floor((p[t] + mid * d[t] - g.org[t]) / del[t]);
             idx[t] = c < 0 ? 0 : (c > nn[t] - 1 ? nn[t] - 1 : c);
         }
-        long u = idx[0] + (long)g.nx * (idx[1] + (long)g.ny * idx[2]);
-        int m = a.mat[u];
-        double lr = len * a.rho[u];
-#pragma unroll
-        for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] += (m == mm) ? lr : 0.0;
+        f(idx[0] + (long)g.nx * (idx[1] + (long)g.ny * idx[2]), len);
         if (last) break;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
@@ -120,6 +86,52 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
         }
         a0 = a1;
     }
+}
+
+// beam window: azimuth about z from the projected axis, elevation from z = 0
+__device__ inline bool in_window(const double *d, const double *axis, double half_fan, double half_cone)
+{
+    double ax = axis[0], ay = axis[1];
+    double an = hypot(ax, ay);
+    ax /= an;
+    ay /= an;
+    double along = d[0] * ax + d[1] * ay;
+    double across = -d[0] * ay + d[1] * ax;
+    double az = atan2(across, along);
+    double el = atan2(d[2], hypot(d[0], d[1]));
+    return fabs(az) <= half_fan && fabs(el) <= half_cone;
+}
+
+__global__ __launch_bounds__(256) void k_trace(TraceArgs a)
+{
+    const Geo &g = a.geo;
+    long v = (long)blockIdx.x * 256 + threadIdx.x;
+    int b = blockIdx.y;
+    if (v >= g.C) return;
+    int i = (int)(v % g.nx);
+    int j = (int)((v / g.nx) % g.ny);
+    int k = (int)(v / ((long)g.nx * g.ny));
+    const double *p = a.pos + 3 * b;
+    double d[3];
+    d[0] = g.org[0] + (i + 0.5) * g.dx - p[0];
+    d[1] = g.org[1] + (j + 0.5) * g.dy - p[1];
+    d[2] = g.org[2] + (k + 0.5) * g.dz - p[2];
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double r = sqrt(r2);
+    double *out = a.phi_u + (long)b * a.G * g.C + v;
+    if (!in_window(d, a.axis + 3 * b, a.half_fan, a.half_cone)) {
+        for (int gg = 0; gg < a.G; ++gg) out[(long)gg * g.C] = 0.0;
+        return;
+    }
+    double acc[DCT_MAXMAT];
+#pragma unroll
+    for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] = 0.0;
+    siddon_march(g, p, d, r, [&](long u, double len) {
+        int m = a.mat[u];
+        double lr = len * a.rho[u];
+#pragma unroll
+        for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] += (m == mm) ? lr : 0.0;
+    });
     double inv = 1.0 / (4.0 * DCT_PI * r2);
     for (int gg = 0; gg < a.G; ++gg) {
         double tau = 0.0;
@@ -128,6 +140,100 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
             if (mm < a.M) tau += a.st[mm * a.G + gg] * acc[mm];
         out[(long)gg * g.C] = a.gw[gg] * exp(-tau) * inv;
     }
+}
+
+// Adjoint of the uncollided flux: with weights pbu_g(v) on phi_u,g(v),
+//   dR/dw_g      += pbu_g(v) exp(-tau_g(v)) / (4 pi r^2)
+//   dR/drho_u    -= l_{v,u} sum_g sigma_t,g[m_u]/rho * pbu_g(v) phi_u,g(v)
+// for every voxel u the ray to v crosses (FP64 atomics on the crossed voxels).
+__global__ __launch_bounds__(256) void k_adj_ray(AdjRayArgs a)
+{
+    __shared__ double red[4];
+    const Geo &g = a.geo;
+    long v = (long)blockIdx.x * 256 + threadIdx.x;
+    int b = blockIdx.y;
+    bool live = v < g.C;
+    double d[3] = {0, 0, 0}, r2 = 1.0, r = 1.0;
+    const double *p = a.pos + 3 * b;
+    if (live) {
+        int i = (int)(v % g.nx);
+        int j = (int)((v / g.nx) % g.ny);
+        int k = (int)(v / ((long)g.nx * g.ny));
+        d[0] = g.org[0] + (i + 0.5) * g.dx - p[0];
+        d[1] = g.org[1] + (j + 0.5) * g.dy - p[1];
+        d[2] = g.org[2] + (k + 0.5) * g.dz - p[2];
+        r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        r = sqrt(r2);
+        live = in_window(d, a.axis + 3 * b, a.half_fan, a.half_cone);
+    }
+    double acc[DCT_MAXMAT];
+#pragma unroll
+    for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] = 0.0;
+    if (live)
+        siddon_march(g, p, d, r, [&](long u, double len) {
+            int m = a.mat[u];
+            double lr = len * a.rho[u];
+#pragma unroll
+            for (int mm = 0; mm < DCT_MAXMAT; ++mm) acc[mm] += (m == mm) ? lr : 0.0;
+        });
+    const double inv = 1.0 / (4.0 * DCT_PI * r2);
+    double am[DCT_MAXMAT];
+#pragma unroll
+    for (int mm = 0; mm < DCT_MAXMAT; ++mm) am[mm] = 0.0;
+    for (int gg = 0; gg < a.G; ++gg) {
+        double unit = 0.0, wgt = 0.0;
+        if (live) {
+            double tau = 0.0;
+#pragma unroll
+            for (int mm = 0; mm < DCT_MAXMAT; ++mm)
+                if (mm < a.M) tau += a.st[mm * a.G + gg] * acc[mm];
+            unit = exp(-tau) * inv;
+            wgt = a.pbu[((long)b * a.G + gg) * g.C + v];
+#pragma unroll
+            for (int mm = 0; mm < DCT_MAXMAT; ++mm)
+                if (mm < a.M) am[mm] += a.st[mm * a.G + gg] * wgt * a.gw[gg] * unit;
+        }
+        // group-weight gradient: block reduction, one atomic per block and group
+        double x = wgt * unit;
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&a.dgw[gg], red[0] + red[1] + red[2] + red[3]);
+    }
+    if (live)
+        siddon_march(g, p, d, r, [&](long u, double len) {
+            int m = a.mat[u];
+            double t = 0.0;
+#pragma unroll
+            for (int mm = 0; mm < DCT_MAXMAT; ++mm) t = (m == mm) ? am[mm] : t;
+            if (t != 0.0) atomicAdd(&a.drho_ray[u], -len * t);
+        });
+}
+
+// Direct weight of the ROI dose on the uncollided flux: pbu[b][g][v] = roi_v kappa_g[m_v].
+__global__ __launch_bounds__(256) void k_adj_init(long C, int G, int B, const uint8_t *mat, const double *kap,
+                                                  const double *roi, double *pbu)
+{
+    long v = (long)blockIdx.x * 256 + threadIdx.x;
+    if (v >= C) return;
+    const int m = mat[v];
+    for (int b = 0; b < B; ++b)
+        for (int g = 0; g < G; ++g) pbu[((long)b * G + g) * C + v] = roi[v] * kap[m * G + g];
+}
+
+hipError_t launch_adj_init(long C, int G, int B, const uint8_t *mat, const double *kap, const double *roi,
+                           double *pbu, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_init, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, s, C, G, B, mat, kap, roi, pbu);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_ray(const AdjRayArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
+    hipLaunchKernelGGL(k_adj_ray, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_trace(const TraceArgs &a, hipStream_t s)

@@ -65,6 +65,7 @@ struct dct_ctx {
     bool solved = false;
     int solved_prec = 0;
     int solved_Nm = 0;
+    bool kept = false;          // the last solve kept per-group fluxes and fixup sets
 
     std::vector<hipEvent_t> evpool;
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
@@ -114,6 +115,7 @@ static bool finite_all(const double *p, size_t n)
 static void invalidate(dct_ctx *ctx)
 {
     ctx->solved = false;
+    ctx->kept = false;
     ctx->dev_dirty = true;
     ctx->tab_prec = -1;
 }
@@ -492,7 +494,10 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(dbuf(ctx, "ext", (size_t)B * Nm * C * ts, &d_ext));
     HC(dbuf(ctx, "Qc", (size_t)2 * B * Nm * C * ts, &d_Qc));
     HC(dbuf(ctx, "q", (size_t)B * N * C * ts, &d_q));
-    HC(dbuf(ctx, "psi", (size_t)B * N * C * ts, &d_psi));
+    const bool keep = o.keep_adjoint != 0;
+    HC(dbuf(ctx, "psi", (size_t)B * (keep ? G : 1) * N * C * ts, &d_psi));
+    void *d_mask = nullptr;
+    if (keep) HC(dbuf(ctx, "mask", (size_t)B * G * N * C, &d_mask));
     HC(dbuf(ctx, "part", (size_t)2 * B * Nm * C * ts, &d_part));
     HC(dbuf(ctx, "phi", (size_t)B * G * Nm * C * ts, &d_phi));
     // block-face buffers, two copies each (ping-pong by block parity)
@@ -668,6 +673,10 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     ma.Qc = d_Qc;
     ma.q = d_q;
     ma.psi = d_psi;
+    ma.psi_bs = keep ? (long)G * N : N;
+    ma.psi_gs = keep ? N : 0;
+    ma.G = G;
+    ma.reverse = 0;
     ma.part = d_part;
     ma.state = (const RhsState *)d_state;
 
@@ -689,6 +698,11 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     sw.dz = ctx->dz;
     sw.q = d_q;
     sw.psi = d_psi;
+    sw.psi_bs = keep ? (long)G * N : N;
+    sw.psi_gs = keep ? N : 0;
+    sw.mask = (uint8_t *)d_mask;
+    sw.reverse = 0;
+    sw.adjoint = 0;
     sw.sigc = d_sigc;
     sw.yface = d_yf;
     sw.zface = d_zf;
@@ -721,6 +735,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     cb.fixed_iters = (const int *)d_fixed;
     cb.tol = o.tol;
     cb.max_iter = o.max_iter;
+    cb.reverse = 0;
 
     // upper bound of iteration sets: every group at its cap plus one transition each
     long cap_sets = 2;
@@ -823,6 +838,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     ctx->solved = true;
     ctx->solved_prec = o.precision;
     ctx->solved_Nm = Nm;
+    ctx->kept = keep;
     if (unfinished != 0) {
         ctx->solved = false;
         return fail(ctx, DCT_ENOTCONV, "solve: iteration-set cap reached with unfinished right-hand sides");
@@ -902,5 +918,307 @@ extern "C" int dct_moments(dct_ctx *ctx, double *phi)
     HC(launch_moments_out(ctx->bufs["phi"].p, n, (double *)t, ctx->solved_prec == DCT_FP64, s));
     HC(hipMemcpyAsync(phi, t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
     HC(hipStreamSynchronize(s));
+    return DCT_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
+                           double *d_group_w, dct_stats *stats)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!ctx->solved || !ctx->kept)
+        return fail(ctx, DCT_ESTATE, "adjoint: needs a preceding dct_solve with keep_adjoint = 1 and no set_* since");
+    if (!roi) return fail(ctx, DCT_EINVAL, "adjoint: roi is NULL");
+    const int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz, G = ctx->G, M = ctx->M, L = ctx->L, N = ctx->N, B = ctx->B;
+    const long C = (long)nx * ny * nz;
+    if (!finite_all(roi, C)) return fail(ctx, DCT_EINVAL, "adjoint: roi not finite");
+    dct_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.tol = 1e-6;
+    o.max_iter = 1000;
+    if (opts) {
+        o.tol = opts->tol;
+        o.max_iter = opts->max_iter;
+        o.fixed_iters = opts->fixed_iters;
+        o.chunk = opts->chunk;
+    }
+    o.precision = ctx->solved_prec;
+    o.fixup = 1;
+    Plan pl;
+    int rc = check_consistency(ctx, o, pl);
+    if (rc != DCT_OK) return rc;
+    HC(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int Nm = pl.Nm;
+    const size_t ts = pl.tsz;
+    const int is64 = o.precision == DCT_FP64;
+    const int mode = o.precision == DCT_FP64 ? 0 : (o.precision == DCT_FP32 ? 1 : 2);
+    auto B_ = [&](const char *n) { return ctx->bufs[n].p; };
+
+    void *d_roi, *d_amt, *d_adt, *d_lamc, *d_lam, *d_pbar, *d_pbu, *d_drho, *d_dray, *d_dgw, *d_ait, *d_aeps, *d_fix;
+    HC(dbuf(ctx, "a_roi", (size_t)C * 8, &d_roi));
+    const size_t tabsz = (size_t)2 * pl.NcP * pl.NmP * (mode == 2 ? 2 : ts);
+    HC(dbuf(ctx, "a_Mt", tabsz, &d_amt));
+    HC(dbuf(ctx, "a_Dt", tabsz, &d_adt));
+    HC(dbuf(ctx, "a_lamc", (size_t)B * N * C * ts, &d_lamc));
+    HC(dbuf(ctx, "a_lam", (size_t)B * G * Nm * C * ts, &d_lam));
+    HC(dbuf(ctx, "a_pbar", (size_t)B * Nm * C * ts, &d_pbar));
+    HC(dbuf(ctx, "a_pbu", (size_t)B * G * C * 8, &d_pbu));
+    HC(dbuf(ctx, "a_drho", (size_t)B * C * 8, &d_drho));
+    HC(dbuf(ctx, "a_dray", (size_t)C * 8, &d_dray));
+    HC(dbuf(ctx, "a_dgw", (size_t)G * 8, &d_dgw));
+    HC(dbuf(ctx, "a_iters", (size_t)B * G * 4, &d_ait));
+    HC(dbuf(ctx, "a_eps", (size_t)B * G * 8, &d_aeps));
+    HC(dbuf(ctx, "a_fixed", (size_t)G * 4, &d_fix));
+
+    // transposed maps: the "M" slot gets D^T (moments -> direction weights) and the
+    // "D" slot gets M^T (direction weights -> moments)
+    std::vector<unsigned char> Mt(tabsz, 0), Dt(tabsz, 0);
+    {
+        std::vector<double> Y(Nm);
+        for (int c = 0; c < 2; ++c)
+            for (int nl = 0; nl < pl.Nc[c]; ++nl) {
+                int n = pl.cdir[(size_t)c * N + nl];
+                real_sh_cart<double>(L, ctx->dirs[3 * n], ctx->dirs[3 * n + 1], ctx->dirs[3 * n + 2], Y.data());
+                for (int lm = 0; lm < Nm; ++lm) {
+                    int l = 0;
+                    while ((l + 1) * (l + 1) <= lm) ++l;
+                    double dT = ctx->w[n] * Y[lm];                         // D[lm][n] at (n, lm)
+                    double mT = (2.0 * l + 1.0) / (4.0 * DCT_PI) * Y[lm]; // M[n][lm] at (lm, n)
+                    size_t im = ((size_t)c * pl.NcP + nl) * pl.NmP + lm;
+                    size_t id = ((size_t)c * pl.NmP + lm) * pl.NcP + nl;
+                    if (mode == 0) {
+                        ((double *)Mt.data())[im] = dT;
+                        ((double *)Dt.data())[id] = mT;
+                    } else if (mode == 1) {
+                        ((float *)Mt.data())[im] = (float)dT;
+                        ((float *)Dt.data())[id] = (float)mT;
+                    } else {
+                        ((uint16_t *)Mt.data())[im] = bf16_bits(dT);
+                        ((uint16_t *)Dt.data())[id] = bf16_bits(mT);
+                    }
+                }
+            }
+    }
+    std::vector<RhsState> hst(B);
+    for (int b = 0; b < B; ++b) {
+        std::memset(&hst[b], 0, sizeof(RhsState));
+        hst[b].pending = 1;
+    }
+    int h_unf0 = B;
+    HC(hipMemcpyAsync(d_roi, roi, (size_t)C * 8, hipMemcpyHostToDevice, s));
+    HC(hipMemcpyAsync(d_amt, Mt.data(), tabsz, hipMemcpyHostToDevice, s));
+    HC(hipMemcpyAsync(d_adt, Dt.data(), tabsz, hipMemcpyHostToDevice, s));
+    HC(hipMemcpyAsync(B_("state"), hst.data(), (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
+    HC(hipMemcpyAsync(B_("unf"), &h_unf0, 4, hipMemcpyHostToDevice, s));
+    if (o.fixed_iters) HC(hipMemcpyAsync(d_fix, o.fixed_iters, (size_t)G * 4, hipMemcpyHostToDevice, s));
+    HC(hipMemsetAsync(d_drho, 0, (size_t)B * C * 8, s));
+    HC(hipMemsetAsync(d_dray, 0, (size_t)C * 8, s));
+    HC(hipMemsetAsync(d_dgw, 0, (size_t)G * 8, s));
+    HC(hipMemsetAsync(d_ait, 0, (size_t)B * G * 4, s));
+    HC(hipMemsetAsync(d_aeps, 0, (size_t)B * G * 8, s));
+    HC(hipMemsetAsync(B_("err"), 0, 4, s));
+    HC(launch_adj_init(C, G, B, (const uint8_t *)B_("mat"), (const double *)B_("kap"), (const double *)d_roi,
+                       (double *)d_pbu, s));
+    HC(hipStreamSynchronize(s));   // host tables must outlive the copies
+
+    Geo geo;
+    geo.nx = nx;
+    geo.ny = ny;
+    geo.nz = nz;
+    geo.C = C;
+    geo.dx = ctx->dx;
+    geo.dy = ctx->dy;
+    geo.dz = ctx->dz;
+    std::memcpy(geo.org, ctx->org, sizeof(geo.org));
+
+    AdjTransArgs at;
+    at.geo = geo;
+    at.G = G;
+    at.M = M;
+    at.L = L;
+    at.Nm = Nm;
+    at.N = N;
+    at.B = B;
+    at.mat = (const uint8_t *)B_("mat");
+    at.rho = (const double *)B_("rho");
+    at.st = (const double *)B_("st");
+    at.ss = (const double *)B_("ss");
+    at.kap = (const double *)B_("kap");
+    at.pos = (const double *)B_("pos");
+    at.roi = (const double *)d_roi;
+    at.phi_u = (const double *)B_("phiu");
+    at.phi_all = B_("phi");
+    at.psi_keep = B_("psi");
+    at.lamc = d_lamc;
+    at.dirs = (const double *)B_("dirs");
+    at.lam_all = d_lam;
+    at.phibar = d_pbar;
+    at.Qc = B_("Qc");
+    at.pbu = (double *)d_pbu;
+    at.drho = (double *)d_drho;
+    at.state = (RhsState *)B_("state");
+    at.n_unfinished = (int *)B_("unf");
+
+    MapArgs ma;
+    ma.C = C;
+    ma.B = B;
+    ma.N = N;
+    ma.Nm = Nm;
+    ma.Nc[0] = pl.Nc[0];
+    ma.Nc[1] = pl.Nc[1];
+    ma.cdir = (const int *)B_("cdir");
+    ma.Mtab = d_amt;
+    ma.Dtab = d_adt;
+    ma.NcP = pl.NcP;
+    ma.NmP = pl.NmP;
+    ma.Qc = B_("Qc");
+    ma.q = B_("q");
+    ma.psi = d_lamc;
+    ma.psi_bs = N;
+    ma.psi_gs = 0;
+    ma.G = G;
+    ma.reverse = 1;
+    ma.part = B_("part");
+    ma.state = (const RhsState *)B_("state");
+
+    SweepArgs sw;
+    sw.nx = nx;
+    sw.ny = ny;
+    sw.nz = nz;
+    sw.C = C;
+    sw.N = N;
+    sw.B = B;
+    sw.G = G;
+    sw.BK = pl.BK;
+    sw.NBJ = pl.NBJ;
+    sw.NBK = pl.NBK;
+    sw.nblk = pl.nblk;
+    sw.dirs = (const double *)B_("dirs");
+    sw.dx = ctx->dx;
+    sw.dy = ctx->dy;
+    sw.dz = ctx->dz;
+    sw.q = B_("q");
+    sw.psi = d_lamc;
+    sw.psi_bs = N;
+    sw.psi_gs = 0;
+    sw.mask = (uint8_t *)B_("mask");
+    sw.reverse = 1;
+    sw.adjoint = 1;
+    sw.sigc = B_("sigc");
+    sw.yface = B_("yf");
+    sw.zface = B_("zf");
+    sw.leak_part = (double *)B_("leak");
+    sw.state = (const RhsState *)B_("state");
+    sw.inflow = nullptr;
+    sw.fixup = 0;
+    {
+        const char *e = getenv("DCT_SWEEP_SYNC");
+        sw.sync = e ? atoi(e) : 1;
+    }
+    sw.err = (int *)B_("err");
+
+    CombArgs cb;
+    cb.geo = geo;
+    cb.G = G;
+    cb.L = L;
+    cb.Nm = Nm;
+    cb.B = B;
+    cb.mat = (const uint8_t *)B_("mat");
+    cb.rho = (const double *)B_("rho");
+    cb.ss = (const double *)B_("ss");
+    cb.part = B_("part");
+    cb.ext = d_pbar;
+    cb.phi_all = d_lam;
+    cb.Qc = B_("Qc");
+    cb.state = (RhsState *)B_("state");
+    cb.iters = (int *)d_ait;
+    cb.eps = (double *)d_aeps;
+    cb.fixed_iters = o.fixed_iters ? (const int *)d_fix : nullptr;
+    cb.tol = o.tol;
+    cb.max_iter = o.max_iter;
+    cb.reverse = 1;
+
+    long cap_sets = 2;
+    for (int g = 0; g < G; ++g) cap_sets += (o.fixed_iters ? o.fixed_iters[g] : o.max_iter) + 1;
+    const int chunk = o.chunk > 0 ? o.chunk : 4;
+    auto enqueue_set = [&]() -> hipError_t {
+        hipError_t e = launch_adj_transition(at, is64, s);
+        if (e != hipSuccess) return e;
+        if ((e = launch_mmap(ma, mode, s)) != hipSuccess) return e;
+        for (int d = 0; d < pl.ndiag; ++d) {
+            sw.diag = d;
+            if ((e = launch_sweep(sw, is64, s)) != hipSuccess) return e;
+        }
+        if ((e = launch_dmap(ma, mode, s)) != hipSuccess) return e;
+        return launch_combine(cb, is64, s);
+    };
+    HC(hipEventRecord(ctx->ev_t0, s));
+    long sets = 0;
+    int kpoll = 0;
+    bool done = false;
+    while (sets < cap_sets && !done) {
+        for (int c = 0; c < chunk && sets < cap_sets; ++c, ++sets) HC(enqueue_set());
+        HC(hipMemcpyAsync(&ctx->h_unf[kpoll & 1], B_("unf"), 4, hipMemcpyDeviceToHost, s));
+        HC(hipEventRecord(ctx->ev_poll[kpoll & 1], s));
+        if (kpoll > 0) {
+            HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
+            if (ctx->h_unf[(kpoll - 1) & 1] == 0) done = true;
+        }
+        ++kpoll;
+    }
+    HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
+    const int unfinished = ctx->h_unf[(kpoll - 1) & 1];
+
+    AdjRayArgs ar;
+    ar.geo = geo;
+    ar.mat = (const uint8_t *)B_("mat");
+    ar.rho = (const double *)B_("rho");
+    ar.st = (const double *)B_("st");
+    ar.G = G;
+    ar.M = M;
+    ar.B = B;
+    ar.pos = (const double *)B_("pos");
+    ar.axis = (const double *)B_("axis");
+    ar.half_fan = ctx->fan * DCT_PI / 360.0;
+    ar.half_cone = ctx->cone * DCT_PI / 360.0;
+    ar.gw = (const double *)B_("gw");
+    ar.pbu = (const double *)d_pbu;
+    ar.drho_ray = (double *)d_dray;
+    ar.dgw = (double *)d_dgw;
+    HC(launch_adj_ray(ar, s));
+    HC(hipEventRecord(ctx->ev_t1, s));
+    HC(hipEventSynchronize(ctx->ev_t1));
+    int h_err = 0;
+    HC(hipMemcpy(&h_err, B_("err"), 4, hipMemcpyDeviceToHost));
+    if (h_err) return fail(ctx, DCT_EDEVICE, "adjoint: a sweep wave wait exceeded its bound");
+    if (unfinished != 0) return fail(ctx, DCT_ENOTCONV, "adjoint: iteration-set cap reached");
+
+    std::vector<double> drho((size_t)B * C), dray(C), dose((size_t)B * C);
+    HC(hipMemcpy(drho.data(), d_drho, drho.size() * 8, hipMemcpyDeviceToHost));
+    HC(hipMemcpy(dray.data(), d_dray, dray.size() * 8, hipMemcpyDeviceToHost));
+    HC(hipMemcpy(dose.data(), B_("dose"), dose.size() * 8, hipMemcpyDeviceToHost));
+    if (d_density)
+        for (long v = 0; v < C; ++v) {
+            double t = dray[v];
+            for (int b = 0; b < B; ++b) t += drho[(size_t)b * C + v];
+            d_density[v] = t;
+        }
+    if (d_group_w) HC(hipMemcpy(d_group_w, d_dgw, (size_t)G * 8, hipMemcpyDeviceToHost));
+    if (R) {
+        double acc = 0.0;
+        for (int b = 0; b < B; ++b)
+            for (long v = 0; v < C; ++v) acc += roi[v] * dose[(size_t)b * C + v];
+        *R = acc;
+    }
+    if (stats) {
+        if (stats->iters) HC(hipMemcpy(stats->iters, d_ait, (size_t)B * G * 4, hipMemcpyDeviceToHost));
+        if (stats->eps) HC(hipMemcpy(stats->eps, d_aeps, (size_t)B * G * 8, hipMemcpyDeviceToHost));
+        float ms = 0;
+        HC(hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+        stats->solve_ms = ms;
+        stats->iteration_sets = (int)sets;
+    }
     return DCT_OK;
 }

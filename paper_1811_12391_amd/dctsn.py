@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "DCT_OK", -1: "DCT_EINVAL", -2: "DCT_ESTATE", -3: "DCT_EDEVIC
 # every symbol include/dctsn.h declares
 EXPORTS = ["dct_create", "dct_destroy", "dct_last_error", "dct_set_geometry", "dct_set_xs",
            "dct_set_quadrature", "dct_set_source", "dct_set_volume_source", "dct_solve", "dct_dose",
-           "dct_dose_dev", "dct_moments"]
+           "dct_dose_dev", "dct_adjoint", "dct_moments"]
 
 
 class DctError(RuntimeError):
@@ -38,7 +38,7 @@ class dct_opts(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("fixed_iters", ct.POINTER(ct.c_int)), ("fixup", ct.c_int),
                 ("test_inflow", ct.POINTER(ct.c_double)), ("chunk", ct.c_int), ("use_graph", ct.c_int),
-                ("profile", ct.c_int)]
+                ("profile", ct.c_int), ("keep_adjoint", ct.c_int)]
 
 
 class dct_stats(ct.Structure):
@@ -75,6 +75,7 @@ def lib():
         L.dct_solve.argtypes = [_vp, ct.POINTER(dct_opts), ct.POINTER(dct_stats)]
         L.dct_dose.argtypes = [_vp, _d, ct.c_int, _d, _d]
         L.dct_dose_dev.argtypes = [_vp, _vp, ct.c_int, _vp, _vp]
+        L.dct_adjoint.argtypes = [_vp, _d, ct.POINTER(dct_opts), _d, _d, _d, ct.POINTER(dct_stats)]
         L.dct_moments.argtypes = [_vp, _d]
         for n in EXPORTS:
             if n != "dct_last_error":
@@ -161,7 +162,8 @@ class SolveStats:
 
 
 def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=None, fixup=True,
-          test_inflow=None, chunk=0, use_graph=False, profile=False, allow_notconv=False) -> SolveStats:
+          test_inflow=None, chunk=0, use_graph=False, profile=False, keep_adjoint=False,
+          allow_notconv=False) -> SolveStats:
     o = dct_opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.tol = tol
@@ -174,6 +176,7 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     o.chunk = int(chunk)
     o.use_graph = int(use_graph)
     o.profile = int(profile)
+    o.keep_adjoint = int(keep_adjoint)
     iters = np.zeros((B, G), dtype=np.int32)
     eps = np.zeros((B, G))
     bal = np.zeros((B, G, 3))
@@ -200,6 +203,39 @@ def dose_dev(h, dose_t, summed=False, phi_u_t=None, phi_c_t=None):
     return _chk(h, lib().dct_dose_dev(h, _dev_ptr(dose_t), int(summed), _dev_ptr(phi_u_t), _dev_ptr(phi_c_t)))
 
 
+@dataclass
+class AdjointResult:
+    R: float
+    d_density: np.ndarray     # [C]
+    d_group_w: np.ndarray     # [G]
+    iters: np.ndarray         # [B][G] adjoint iterations
+    eps: np.ndarray
+    solve_ms: float
+
+
+def adjoint(h, B, G, C, roi, *, tol=1e-6, max_iter=1000, fixed_iters=None, chunk=0) -> AdjointResult:
+    """Gradient of sum_b sum_v roi[v] dose_b(v) after a solve with keep_adjoint=True."""
+    roi = _f64(roi).reshape(-1)
+    if roi.size != C:
+        raise ValueError(f"roi has {roi.size} entries, expected {C}")
+    o = dct_opts()
+    o.tol = tol
+    o.max_iter = max_iter
+    fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, dtype=np.int32)
+    o.fixed_iters = _p(fi, ct.POINTER(ct.c_int)) if fi is not None else None
+    o.chunk = int(chunk)
+    R = np.zeros(1)
+    dd = np.zeros(C)
+    dg = np.zeros(G)
+    iters = np.zeros((B, G), dtype=np.int32)
+    eps = np.zeros((B, G))
+    st = dct_stats()
+    st.iters = iters.ctypes.data_as(ct.POINTER(ct.c_int))
+    st.eps = _p(eps)
+    _chk(h, lib().dct_adjoint(h, _p(roi), ct.byref(o), _p(R), _p(dd), _p(dg), ct.byref(st)))
+    return AdjointResult(float(R[0]), dd, dg, iters, eps, st.solve_ms)
+
+
 def moments(h, B, G, Nm, C):
     out = np.zeros((B, G, Nm, C))
     _chk(h, lib().dct_moments(h, _p(out)))
@@ -224,6 +260,18 @@ class Solver:
 
     def dose(self, **kw):
         return dose(self.h, self.prob.B, self.prob.G, self.prob.phantom.C, **kw)
+
+    def adjoint(self, roi, **kw) -> AdjointResult:
+        return adjoint(self.h, self.prob.B, self.prob.G, self.prob.phantom.C, roi, **kw)
+
+    def set_density(self, density):
+        """Replace the voxel densities (same grid and materials)."""
+        ph = self.prob.phantom
+        set_geometry(self.h, ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, ph.origin, ph.material, density)
+
+    def set_group_weights(self, group_w):
+        p = self.prob
+        set_source(self.h, p.B, p.src_pos, p.src_axis, p.fan_deg, p.cone_deg, group_w)
 
     def moments(self):
         return moments(self.h, self.prob.B, self.prob.G, (self.prob.L + 1) ** 2, self.prob.phantom.C)

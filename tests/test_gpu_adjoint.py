@@ -1,0 +1,199 @@
+"""GPU adjoint (gradient of the ROI dose with respect to voxel densities and
+source group weights) against the FP64 oracle adjoint and against finite
+differences of the GPU forward solve.
+
+Both sides run the same fixed per-group iteration counts (forward and adjoint)
+so rounding cannot move a stopping point; the fixup sets are decided by each
+side's own forward sweep (they coincide at FP64 parity) and frozen for the
+adjoint.  Bars: FP64 1e-9 relative (max-norm), FP32 1e-4 L2 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1811_12391_amd import dctsn, inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dctsn.lib()
+    yield
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    s = np.abs(b).max()
+    return float(np.abs(a - b).max() / s) if s > 0 else float(np.abs(a).max())
+
+
+def l2rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _roi(ph, lo=(0.3, 0.3, 0.25), hi=(0.6, 0.65, 0.75)):
+    r = np.zeros((ph.nz, ph.ny, ph.nx))
+    r[int(lo[2] * ph.nz):max(int(hi[2] * ph.nz), int(lo[2] * ph.nz) + 1),
+      int(lo[1] * ph.ny):int(hi[1] * ph.ny), int(lo[0] * ph.nx):int(hi[0] * ph.nx)] = 1.0
+    return (r / r.sum()).reshape(-1)
+
+
+def _ring_problem():
+    """Two sources on a ring (two right-hand sides solved together)."""
+    base = I.make_problem("tiny_abd")
+    pos, axis = I.ring_sources(2, 30.0)
+    return I.Problem("tiny_abd_ring2", base.phantom, base.xs, base.dirs, base.weights, base.L, pos, axis,
+                     base.fan_deg, base.cone_deg, base.group_w)
+
+
+def _multiblock_problem():
+    ph = I.cylinder_phantom(7, 70, 18, 0.6)
+    xs = I.xs_tables(ph.material_names, 2, 1)
+    d, w = I.lq_quadrature(4)
+    pos, axis = I.top_source()
+    return I.Problem("multiblock", ph, xs, d, w, 1, pos, axis, 60.0, 30.0, I.kramers_weights(xs.edges))
+
+
+def _problem(name):
+    if name == "ring2":
+        return _ring_problem()
+    if name == "multiblock":
+        return _multiblock_problem()
+    return I.make_problem(name)
+
+
+_REF = {}
+
+
+def _oracle_adjoint(name):
+    """Oracle forward + adjoint at tight tolerance; then the iteration counts
+    it took are locked for both sides."""
+    import oracle
+
+    if name not in _REF:
+        prob = _problem(name)
+        roi = _roi(prob.phantom)
+        fw = oracle.solve_problem(prob, tol=1e-10)
+        fi = fw.iters.max(0)
+        a0 = oracle.adjoint_problem(prob, roi, tol=1e-10, fixed_iters=fi)
+        fa = a0.iters_adj.max(0)
+        a = oracle.adjoint_problem(prob, roi, fixed_iters=fi, fixed_iters_adj=fa)
+        _REF[name] = (prob, roi, fi, fa, a)
+    return _REF[name]
+
+
+def _gpu_adjoint(prob, roi, fi, fa, precision="fp64"):
+    s = dctsn.Solver(prob)
+    try:
+        s.solve(precision=precision, fixed_iters=fi, keep_adjoint=True)
+        return s.adjoint(roi, fixed_iters=fa)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_abd", "ring2", "multiblock"])
+def test_adjoint_fp64_matches_oracle(name):
+    prob, roi, fi, fa, ref = _oracle_adjoint(name)
+    ph = prob.phantom
+    _say(f"[adjoint fp64] {name} grid={ph.nx}x{ph.ny}x{ph.nz} G={prob.G} N={prob.N} L={prob.L} B={prob.B}")
+    a = _gpu_adjoint(prob, roi, fi, fa)
+    assert np.array_equal(a.iters, np.broadcast_to(fa, a.iters.shape))
+    assert abs(a.R - ref.R) <= 1e-10 * abs(ref.R)
+    assert rel(a.d_group_w, ref.d_group_w) < 1e-9
+    assert rel(a.d_density, ref.d_density) < 1e-9
+
+
+def test_adjoint_fp32_error():
+    prob, roi, fi, fa, ref = _oracle_adjoint("tiny_abd")
+    _say("[adjoint fp32] tiny_abd")
+    a = _gpu_adjoint(prob, roi, fi, fa, precision="fp32")
+    err_d, err_g = l2rel(a.d_density, ref.d_density), l2rel(a.d_group_w, ref.d_group_w)
+    _say(f"[adjoint fp32] d_density L2 rel {err_d:.3e}, d_group_w {err_g:.3e}")
+    assert err_d <= 1e-4 and err_g <= 1e-4
+
+
+def test_adjoint_gpu_finite_differences():
+    """Central differences of the GPU forward solve (tight tolerance) on a few
+    voxels of different materials agree with the GPU adjoint."""
+    prob = I.make_problem("tiny_abd")
+    ph = prob.phantom
+    roi = _roi(ph)
+    s = dctsn.Solver(prob)
+    try:
+        s.solve(precision="fp64", tol=1e-12, keep_adjoint=True)
+        a = s.adjoint(roi, tol=1e-12)
+
+        def R(rho):
+            s.set_density(rho)
+            s.solve(precision="fp64", tol=1e-12)
+            return float(np.dot(roi, s.dose(summed=True)))
+
+        rng = np.random.default_rng(7)
+        picks = []
+        for m in range(len(ph.material_names)):
+            ids = np.nonzero(ph.material == m)[0]
+            if len(ids):
+                picks.append(int(rng.choice(ids)))
+        picks.append(int(np.nonzero(roi > 0)[0][0]))
+        for v in picks:
+            h = 1e-4 * max(ph.density[v], 1e-2)
+            r1, r2 = ph.density.copy(), ph.density.copy()
+            r1[v] += h
+            r2[v] -= h
+            fd = (R(r1) - R(r2)) / (2 * h)
+            _say(f"[adjoint fd] voxel {v} material {ph.material[v]}: fd {fd:.6e} adjoint {a.d_density[v]:.6e}")
+            assert abs(fd - a.d_density[v]) <= 1e-6 * abs(fd) + 1e-9 * abs(a.R)
+    finally:
+        s.close()
+
+
+def test_adjoint_needs_kept_solve():
+    prob = I.make_problem("tiny")
+    s = dctsn.Solver(prob)
+    try:
+        with pytest.raises(dctsn.DctError) as e:
+            s.adjoint(np.ones(prob.phantom.C))
+        assert e.value.code == dctsn.DCT_ESTATE
+        s.solve(precision="fp64")
+        with pytest.raises(dctsn.DctError) as e:
+            s.adjoint(np.ones(prob.phantom.C))
+        assert e.value.code == dctsn.DCT_ESTATE
+        s.solve(precision="fp64", keep_adjoint=True)
+        s.adjoint(np.ones(prob.phantom.C))
+        s.set_density(prob.phantom.density)
+        with pytest.raises(dctsn.DctError) as e:
+            s.adjoint(np.ones(prob.phantom.C))
+        assert e.value.code == dctsn.DCT_ESTATE
+    finally:
+        s.close()
+
+
+def test_autograd_wrapper():
+    """torch.autograd through roi_dose gives the adjoint gradients."""
+    import torch
+
+    from paper_1811_12391_amd.autograd import roi_dose
+
+    prob, roi, fi, fa, ref = _oracle_adjoint("tiny_abd")
+    s = dctsn.Solver(prob)
+    try:
+        rho = torch.tensor(prob.phantom.density, dtype=torch.float64, requires_grad=True)
+        gw = torch.tensor(prob.group_w, dtype=torch.float64, requires_grad=True)
+        R = roi_dose(s, rho, gw, roi, fwd={"precision": "fp64", "fixed_iters": fi}, adj={"fixed_iters": fa})
+        (3.0 * R).backward()
+        assert abs(float(R) - ref.R) <= 1e-10 * abs(ref.R)
+        assert rel(rho.grad.numpy() / 3.0, ref.d_density) < 1e-9
+        assert rel(gw.grad.numpy() / 3.0, ref.d_group_w) < 1e-9
+    finally:
+        s.close()
