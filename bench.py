@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32,fp32_bf16map")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this solve is "
@@ -77,13 +79,19 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = I.make_problem("c2")
     C, G, N = prob.phantom.C, prob.G, prob.N
     solver = dctsn.Solver(prob, device=0, stream=ct_stream(stream))
     dose_dev = torch.empty(C, dtype=torch.float64, device="cuda")
 
     def run(precision, steps, warmup, tag, fixed=None):
-        kw = dict(precision=precision, tol=prob.tol, fixed_iters=fixed)
+        kw = dict(precision=precision, tol=prob.tol, fixed_iters=fixed, autotune=True)
         for _ in range(warmup):
             solver.solve(**kw)
             dctsn.dose_dev(solver.h, dose_dev, summed=True)
@@ -109,6 +117,8 @@ def main():
             "iters_per_group": stats[-1].iters[0].tolist(),
             "fixed_iters": fixed is not None,
             "iteration_sets": int(stats[-1].iteration_sets),
+            "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
+                               "wave_coupling": {1: "lds_counters", 2: "barrier"}[int(stats[-1].sweep_sync)]},
             "dose": dose,
         }
         _log(f"[bench] {tag}: {res['ms_per_step']:.2f} ms/solve wall, {res['device_ms_per_solve']:.2f} ms device, "
@@ -159,7 +169,7 @@ def main():
                    "voxels": C, "groups": G, "directions": N, "legendre_order": prob.L, "sources": 1,
                    "precision": best},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best),
                      "kernel": "k_sweep", "avg_launch_ms": avg_launch_ms,
                      "bytes_per_launch": bytes_per_solve / launches},
         "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()},
@@ -169,6 +179,34 @@ def main():
         line["cpu_baseline"] = cpu_baseline(prob)
     solver.close()
     print(json.dumps(line), flush=True)
+
+
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c2_hbm_traffic.txt")
+SWEEP_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_sweep.hip")
+
+
+def measured_traffic(precision):
+    """HBM bytes per sweep launch (FETCH_SIZE + WRITE_SIZE, scaled by the
+    same counters on a plain copy of known size) from the committed counter
+    summary, or None when there is none for this precision or the sweep
+    source has changed since the counters were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    with open(SWEEP_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("k_sweep_sha256") != sha:
+        return None
+    v = kv.get(f"bytes_per_launch_{precision}")
+    return float(v) if v is not None else None
 
 
 def ct_stream(stream):

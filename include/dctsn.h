@@ -64,11 +64,19 @@ typedef struct dct_opts {
     int fixup;                /* 1: set-to-zero negative-flux fixup in the sweep */
     const double *test_inflow;/* [G] or NULL: isotropic angular flux entering through every
                                  boundary face (NULL = vacuum, Sec. II-A) */
-    int chunk;                /* iterations enqueued between host convergence polls (0 = auto) */
-    int use_graph;            /* 1: capture one iteration in a HIP graph and replay it */
-    int profile;              /* 1: time every sweep launch with HIP events (dct_stats) */
+    int chunk;                /* iteration sets enqueued between host convergence polls (0 = 4) */
+    int use_graph;            /* 1: capture `chunk` iteration sets once in a HIP graph and
+                                 replay it until every right-hand side has converged */
+    int profile;              /* 1: time every sweep launch with HIP events (dct_stats);
+                                 ignored when use_graph = 1 */
     int keep_adjoint;         /* 1: keep every group's final angular flux and fixup pattern
                                  on the device so that dct_adjoint can follow this solve */
+    int autotune;             /* 1: time the candidate sweep schedules (z layers per
+                                 workgroup x wave coupling) on the first iteration and keep
+                                 the fastest for this problem shape in the context */
+    int sweep_bk;             /* z layers per sweep workgroup, 1..16 (0 = tuned or min(16, nz)) */
+    int sweep_sync;           /* wave coupling inside a sweep workgroup: 1 = LDS progress
+                                 counters, 2 = one barrier per step (0 = tuned or 1) */
 } dct_opts;
 
 typedef struct dct_stats {
@@ -82,6 +90,9 @@ typedef struct dct_stats {
     double sweep_ms;          /* summed device time of sweep launches (profile = 1) */
     double solve_ms;          /* device time of the whole dct_solve (HIP events) */
     int iteration_sets;       /* iteration launch sets enqueued (>= max over RHS of iterations) */
+    int sweep_bk;             /* sweep schedule that ran: z layers per workgroup */
+    int sweep_sync;           /* and wave coupling (1 LDS counters, 2 barriers) */
+    double tune_ms;           /* device time spent timing candidate schedules in this call */
 } dct_stats;
 
 /* Create a context on HIP device `device` using `stream` (a hipStream_t; NULL

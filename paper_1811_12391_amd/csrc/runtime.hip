@@ -67,6 +67,14 @@ struct dct_ctx {
     int solved_Nm = 0;
     bool kept = false;          // the last solve kept per-group fluxes and fixup sets
 
+    // sweep schedules chosen by the autotuner, per problem shape
+    struct Tuned {
+        int nx, ny, nz, N, B, prec, bk, sync;
+    };
+    std::vector<Tuned> tuned;
+    int last_bk = 16, last_sync = 1;   // schedule of the last solve (reused by the adjoint)
+    hipStream_t own_stream = nullptr;  // capture stream when the context's stream is the null stream
+
     std::vector<hipEvent_t> evpool;
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
@@ -173,6 +181,7 @@ int dct_destroy(dct_ctx *ctx)
         for (auto &kv : ctx->bufs)
             if (kv.second.p) (void)hipFree(kv.second.p);
         for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
         for (hipEvent_t e : {ctx->ev_poll[0], ctx->ev_poll[1], ctx->ev_t0, ctx->ev_t1})
             if (e) (void)hipEventDestroy(e);
         if (ctx->h_unf) (void)hipHostFree(ctx->h_unf);
@@ -357,6 +366,17 @@ struct Plan {
     std::vector<int> cdir;   // [2][N]
 };
 
+// Sweep blocks: 64 y rows (lanes) x bk z layers (waves) per workgroup; the
+// blocks of one sweep run as ndiag block diagonals.
+static void set_blocks(Plan &pl, int bk, int ny, int nz)
+{
+    pl.BK = std::min(bk, nz);
+    pl.NBJ = (ny + 63) / 64;
+    pl.NBK = (nz + pl.BK - 1) / pl.BK;
+    pl.nblk = pl.NBJ * pl.NBK;
+    pl.ndiag = pl.NBJ + pl.NBK - 1;
+}
+
 static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
 {
     if (!ctx->has_geo || !ctx->has_xs || !ctx->has_quad || !ctx->has_src)
@@ -421,11 +441,9 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
     pl.NcP = 16 * ((std::max(pl.Nc[0], pl.Nc[1]) + 15) / 16);
     if (pl.NcP == 0) pl.NcP = 16;
     pl.NmP = 16 * ((Nm + 15) / 16);
-    pl.BK = std::min(16, ctx->nz);
-    pl.NBJ = (ctx->ny + 63) / 64;
-    pl.NBK = (ctx->nz + pl.BK - 1) / pl.BK;
-    pl.nblk = pl.NBJ * pl.NBK;
-    pl.ndiag = pl.NBJ + pl.NBK - 1;
+    if (o.sweep_bk < 0 || o.sweep_bk > 16) return fail(ctx, DCT_EINVAL, "solve: sweep_bk must be in [0, 16]");
+    if (o.sweep_sync < 0 || o.sweep_sync > 2) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be 0, 1 or 2");
+    set_blocks(pl, o.sweep_bk > 0 ? o.sweep_bk : 16, ctx->ny, ctx->nz);
     return DCT_OK;
 }
 
@@ -503,7 +521,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // block-face buffers, two copies each (ping-pong by block parity)
     HC(dbuf(ctx, "yf", (size_t)2 * B * N * nx * nz * ts, &d_yf));
     HC(dbuf(ctx, "zf", (size_t)2 * B * N * nx * ny * ts, &d_zf));
-    HC(dbuf(ctx, "leak", (size_t)B * N * pl.nblk * 3 * 8, &d_leak));
+    const size_t leak_max = (size_t)B * N * pl.NBJ * nz * 3 * 8;   // any block split (z layers >= 1)
+    HC(dbuf(ctx, "leak", leak_max, &d_leak));
     HC(dbuf(ctx, "state", (size_t)B * sizeof(RhsState), &d_state));
     HC(dbuf(ctx, "bal", (size_t)B * G * 3 * 8, &d_bal));
     HC(dbuf(ctx, "iters", (size_t)B * G * 4, &d_iters));
@@ -597,7 +616,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(hipMemsetAsync(d_bal, 0, (size_t)B * G * 3 * 8, s));
     HC(hipMemsetAsync(d_iters, 0, (size_t)B * G * 4, s));
     HC(hipMemsetAsync(d_eps, 0, (size_t)B * G * 8, s));
-    HC(hipMemsetAsync(d_leak, 0, (size_t)B * N * pl.nblk * 3 * 8, s));
+    HC(hipMemsetAsync(d_leak, 0, leak_max, s));
     HC(hipMemsetAsync(d_err, 0, 4, s));
 
     Geo geo;
@@ -710,10 +729,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     sw.state = (const RhsState *)d_state;
     sw.inflow = (const double *)d_infl;
     sw.fixup = o.fixup;
-    {
-        const char *e = getenv("DCT_SWEEP_SYNC");
-        sw.sync = e ? atoi(e) : 1;
-    }
+    sw.sync = o.sweep_sync == 2 ? 0 : 1;
     sw.err = (int *)d_err;
 
     CombArgs cb;
@@ -737,48 +753,165 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     cb.max_iter = o.max_iter;
     cb.reverse = 0;
 
+    auto apply_blocks = [&](int bk) {
+        set_blocks(pl, bk, ny, nz);
+        sw.BK = pl.BK;
+        sw.NBJ = pl.NBJ;
+        sw.NBK = pl.NBK;
+        sw.nblk = pl.nblk;
+        tr.nblk = pl.nblk;
+    };
+    auto sweep_all = [&]() -> hipError_t {
+        for (int d = 0; d < pl.ndiag; ++d) {
+            sw.diag = d;
+            hipError_t e = launch_sweep(sw, is64, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+
+    // ---------------- sweep schedule: given, cached, or timed now
+    double tune_ms = 0.0;
+    {
+        int bk = o.sweep_bk > 0 ? o.sweep_bk : 16, sy = o.sweep_sync == 2 ? 0 : 1;
+        const bool free_bk = o.sweep_bk == 0, free_sync = o.sweep_sync == 0;
+        if (o.autotune && (free_bk || free_sync)) {
+            const dct_ctx::Tuned *hit = nullptr;
+            for (const auto &t : ctx->tuned)
+                if (t.nx == nx && t.ny == ny && t.nz == nz && t.N == N && t.B == B && t.prec == o.precision) hit = &t;
+            if (hit) {
+                if (free_bk) bk = hit->bk;
+                if (free_sync) sy = hit->sync;
+            } else {
+                // first iteration set up to the sweep: the transition sets up
+                // group 0 (the first real set then finds nothing pending) and
+                // the M map fills q; the candidate sweeps below all compute
+                // that same first sweep
+                HC(launch_transition(tr, is64, s));
+                HC(launch_mmap(ma, mode, s));
+                while (ctx->evpool.size() < 2) {
+                    hipEvent_t ev;
+                    HC(hipEventCreate(&ev));
+                    ctx->evpool.push_back(ev);
+                }
+                std::vector<int> bks;
+                if (free_bk) {
+                    for (int c : {16, 8, 4, 2}) {
+                        int v = std::min(c, nz);
+                        if (std::find(bks.begin(), bks.end(), v) == bks.end()) bks.push_back(v);
+                    }
+                } else {
+                    bks.push_back(std::min(bk, nz));
+                }
+                std::vector<int> sys = free_sync ? std::vector<int>{1, 0} : std::vector<int>{sy};
+                float best = 1e30f;
+                for (int cb : bks)
+                    for (int cs : sys) {
+                        apply_blocks(cb);
+                        sw.sync = cs;
+                        HC(sweep_all());   // warm-up
+                        HC(hipEventRecord(ctx->evpool[0], s));
+                        for (int r = 0; r < 3; ++r) HC(sweep_all());
+                        HC(hipEventRecord(ctx->evpool[1], s));
+                        HC(hipEventSynchronize(ctx->evpool[1]));
+                        float ms = 0.0f;
+                        HC(hipEventElapsedTime(&ms, ctx->evpool[0], ctx->evpool[1]));
+                        tune_ms += ms * 4.0 / 3.0;
+                        if (ms < best) {
+                            best = ms;
+                            bk = cb;
+                            sy = cs;
+                        }
+                    }
+                ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, bk, sy});
+            }
+        }
+        apply_blocks(bk);
+        sw.sync = sy;
+        ctx->last_bk = pl.BK;
+        ctx->last_sync = sy;
+    }
+
     // upper bound of iteration sets: every group at its cap plus one transition each
     long cap_sets = 2;
     for (int g = 0; g < G; ++g) cap_sets += (o.fixed_iters ? o.fixed_iters[g] : o.max_iter) + 1;
     const int chunk = o.chunk > 0 ? o.chunk : 4;
+    const bool profile = o.profile && !o.use_graph;
     int nprof = 0;
-    auto enqueue_set = [&]() -> hipError_t {
-        hipError_t e = launch_transition(tr, is64, s);
+    auto enqueue_set = [&](hipStream_t es) -> hipError_t {
+        hipError_t e = launch_transition(tr, is64, es);
         if (e != hipSuccess) return e;
-        if ((e = launch_mmap(ma, mode, s)) != hipSuccess) return e;
+        if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
         for (int d = 0; d < pl.ndiag; ++d) {
             sw.diag = d;
-            if (o.profile) {
+            if (profile) {
                 while ((int)ctx->evpool.size() < 2 * (nprof + 1)) {
                     hipEvent_t ev;
                     if ((e = hipEventCreate(&ev)) != hipSuccess) return e;
                     ctx->evpool.push_back(ev);
                 }
-                if ((e = hipEventRecord(ctx->evpool[2 * nprof], s)) != hipSuccess) return e;
+                if ((e = hipEventRecord(ctx->evpool[2 * nprof], es)) != hipSuccess) return e;
             }
-            if ((e = launch_sweep(sw, is64, s)) != hipSuccess) return e;
-            if (o.profile) {
-                if ((e = hipEventRecord(ctx->evpool[2 * nprof + 1], s)) != hipSuccess) return e;
+            if ((e = launch_sweep(sw, is64, es)) != hipSuccess) return e;
+            if (profile) {
+                if ((e = hipEventRecord(ctx->evpool[2 * nprof + 1], es)) != hipSuccess) return e;
                 ++nprof;
             }
         }
-        if ((e = launch_dmap(ma, mode, s)) != hipSuccess) return e;
-        return launch_combine(cb, is64, s);
+        if ((e = launch_dmap(ma, mode, es)) != hipSuccess) return e;
+        return launch_combine(cb, is64, es);
     };
 
+    // ---------------- iteration sets: enqueued in chunks (or one captured
+    // chunk replayed), the host polls the unfinished count one chunk behind
+    hipStream_t ls = s;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphGuard {
+        hipGraph_t &g;
+        hipGraphExec_t &x;
+        ~GraphGuard()
+        {
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } guard{graph, gexec};
+    if (o.use_graph) {
+        if (s == nullptr) {
+            // the null stream cannot be captured: run the iteration loop on a
+            // context-owned stream ordered after everything enqueued so far
+            if (!ctx->own_stream) HC(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+            ls = ctx->own_stream;
+            HC(hipEventRecord(ctx->ev_poll[0], s));
+            HC(hipStreamWaitEvent(ls, ctx->ev_poll[0], 0));
+        }
+        HC(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int c = 0; c < chunk && ce == hipSuccess; ++c) ce = enqueue_set(ls);
+        hipError_t ee = hipStreamEndCapture(ls, &graph);
+        HC(ce);
+        HC(ee);
+        HC(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
     long sets = 0;
     int kpoll = 0;
     bool done = false;
     while (sets < cap_sets && !done) {
-        for (int c = 0; c < chunk && sets < cap_sets; ++c, ++sets) HC(enqueue_set());
-        HC(hipMemcpyAsync(&ctx->h_unf[kpoll & 1], d_unf, 4, hipMemcpyDeviceToHost, s));
-        HC(hipEventRecord(ctx->ev_poll[kpoll & 1], s));
+        if (gexec) {
+            HC(hipGraphLaunch(gexec, ls));
+            sets += chunk;
+        } else {
+            for (int c = 0; c < chunk && sets < cap_sets; ++c, ++sets) HC(enqueue_set(ls));
+        }
+        HC(hipMemcpyAsync(&ctx->h_unf[kpoll & 1], d_unf, 4, hipMemcpyDeviceToHost, ls));
+        HC(hipEventRecord(ctx->ev_poll[kpoll & 1], ls));
         if (kpoll > 0) {
             HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
             if (ctx->h_unf[(kpoll - 1) & 1] == 0) done = true;
         }
         ++kpoll;
     }
+    if (ls != s) HC(hipStreamWaitEvent(s, ctx->ev_poll[(kpoll - 1) & 1], 0));
     HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
     int unfinished = ctx->h_unf[(kpoll - 1) & 1];
 
@@ -834,6 +967,9 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         stats->sweep_ms = swms;
         stats->sweep_launches = nprof;
         stats->iteration_sets = (int)sets;
+        stats->sweep_bk = pl.BK;
+        stats->sweep_sync = sw.sync ? 1 : 2;
+        stats->tune_ms = tune_ms;
     }
     ctx->solved = true;
     ctx->solved_prec = o.precision;
@@ -948,6 +1084,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     Plan pl;
     int rc = check_consistency(ctx, o, pl);
     if (rc != DCT_OK) return rc;
+    set_blocks(pl, ctx->last_bk, ctx->ny, ctx->nz);   // the forward solve's sweep schedule
     HC(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const int Nm = pl.Nm;
@@ -1113,10 +1250,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     sw.state = (const RhsState *)B_("state");
     sw.inflow = nullptr;
     sw.fixup = 0;
-    {
-        const char *e = getenv("DCT_SWEEP_SYNC");
-        sw.sync = e ? atoi(e) : 1;
-    }
+    sw.sync = ctx->last_sync;
     sw.err = (int *)B_("err");
 
     CombArgs cb;

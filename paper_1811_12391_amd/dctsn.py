@@ -38,14 +38,16 @@ class dct_opts(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("fixed_iters", ct.POINTER(ct.c_int)), ("fixup", ct.c_int),
                 ("test_inflow", ct.POINTER(ct.c_double)), ("chunk", ct.c_int), ("use_graph", ct.c_int),
-                ("profile", ct.c_int), ("keep_adjoint", ct.c_int)]
+                ("profile", ct.c_int), ("keep_adjoint", ct.c_int), ("autotune", ct.c_int),
+                ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int)]
 
 
 class dct_stats(ct.Structure):
     _fields_ = [("iters", ct.POINTER(ct.c_int)), ("eps", ct.POINTER(ct.c_double)),
                 ("balance", ct.POINTER(ct.c_double)), ("sweep_updates", ct.c_longlong),
                 ("sweep_launches", ct.c_int), ("sweep_ms", ct.c_double), ("solve_ms", ct.c_double),
-                ("iteration_sets", ct.c_int)]
+                ("iteration_sets", ct.c_int), ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int),
+                ("tune_ms", ct.c_double)]
 
 
 _lib = None
@@ -159,11 +161,14 @@ class SolveStats:
     sweep_ms: float
     solve_ms: float
     iteration_sets: int
+    sweep_bk: int
+    sweep_sync: int
+    tune_ms: float
 
 
 def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=None, fixup=True,
-          test_inflow=None, chunk=0, use_graph=False, profile=False, keep_adjoint=False,
-          allow_notconv=False) -> SolveStats:
+          test_inflow=None, chunk=0, use_graph=False, profile=False, keep_adjoint=False, autotune=False,
+          sweep_bk=0, sweep_sync=0, allow_notconv=False) -> SolveStats:
     o = dct_opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.tol = tol
@@ -177,6 +182,9 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     o.use_graph = int(use_graph)
     o.profile = int(profile)
     o.keep_adjoint = int(keep_adjoint)
+    o.autotune = int(autotune)
+    o.sweep_bk = int(sweep_bk)
+    o.sweep_sync = int(sweep_sync)
     iters = np.zeros((B, G), dtype=np.int32)
     eps = np.zeros((B, G))
     bal = np.zeros((B, G, 3))
@@ -187,7 +195,7 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     ok = (DCT_OK, DCT_ENOTCONV) if allow_notconv else (DCT_OK,)
     rc = _chk(h, lib().dct_solve(h, ct.byref(o), ct.byref(st)), ok)
     return SolveStats(rc, iters, eps, bal, st.sweep_updates, st.sweep_launches, st.sweep_ms, st.solve_ms,
-                      st.iteration_sets)
+                      st.iteration_sets, st.sweep_bk, st.sweep_sync, st.tune_ms)
 
 
 def dose(h, B, G, C, *, summed=False, want_phi=False):

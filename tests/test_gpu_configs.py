@@ -1,0 +1,134 @@
+"""GPU checks at the full sizes of the measured workloads (abdomen 128x128x32
+S8 P3, the 36-source axial scan, the adjoint on the 64x64x16 abdomen), in the
+launch configuration the benchmark uses (autotuned sweep schedule).
+
+The oracle cannot converge these sizes in seconds, so both sides run the same
+small fixed number of source iterations per group (parity holds for any
+iteration count), or the check uses properties that hold at any size:
+batched right-hand sides equal separate solves bit for bit, and the 90-degree
+rotation symmetry of the axial scan.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1811_12391_amd import dctsn, inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dctsn.lib()
+    yield
+
+
+def l2rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def test_c3_abdomen_fp32_vs_oracle_two_iterations():
+    """128x128x32 abdomen (two y-blocks per sweep), 19 groups, S8, P3, FP32
+    with FP64 reductions, two source iterations per group on both sides."""
+    import oracle
+
+    prob = I.make_problem("c3")
+    fi = np.full(prob.G, 2, dtype=np.int32)
+    _say("[c3] oracle, 2 iterations per group")
+    ref = oracle.solve_problem(prob, fixed_iters=fi)
+    s = dctsn.Solver(prob)
+    try:
+        _say("[c3] GPU fp32 autotuned")
+        st = s.solve(precision="fp32", fixed_iters=fi, autotune=True)
+        dose = s.dose()
+    finally:
+        s.close()
+    err = l2rel(dose, ref.dose)
+    _say(f"[c3] schedule bk={st.sweep_bk} sync={st.sweep_sync}; dose L2 rel err {err:.3e}")
+    assert err <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def c4_batched():
+    prob = I.make_problem("c4")
+    s = dctsn.Solver(prob)
+    try:
+        _say("[c4] batched 36 sources, fp32, autotuned, graph replay")
+        st = s.solve(precision="fp32", tol=prob.tol, autotune=True, use_graph=True, chunk=4)
+        dose = s.dose()
+    finally:
+        s.close()
+    return prob, st, dose
+
+
+def test_c4_batched_equals_separate_solves(c4_batched):
+    prob, st, dose = c4_batched
+    for b in (0, 5, 17, 35):
+        p1 = I.Problem("c4_one", prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos[b:b + 1],
+                       prob.src_axis[b:b + 1], prob.fan_deg, prob.cone_deg, prob.group_w)
+        s = dctsn.Solver(p1)
+        try:
+            st1 = s.solve(precision="fp32", tol=prob.tol)
+            d1 = s.dose()
+        finally:
+            s.close()
+        _say(f"[c4] source {b}: iterations {st1.iters.sum()} (batched {st.iters[b].sum()})")
+        assert np.array_equal(st1.iters[0], st.iters[b])
+        assert np.array_equal(d1[0], dose[b])
+
+
+def test_c4_rotation_symmetry(c4_batched):
+    """Source k + 9 is source k turned by 90 degrees about z; the grid, the
+    cylinder and the level-symmetric set are invariant under that turn, so
+    its dose is the turned dose (up to FP32 rounding order)."""
+    prob, st, dose = c4_batched
+    ph = prob.phantom
+    d = dose.reshape(36, ph.nz, ph.ny, ph.nx)
+    # p_k = 54 (sin a, cos a, 0); a turn by +90 deg of the direction angle maps
+    # (x, y) -> (y, -x): voxel (i, j) of source k lands at (j, nx-1-i)
+    for k in (0, 3):
+        a, b = d[k], d[k + 9]
+        turned = np.empty_like(a)
+        for i in range(ph.nx):
+            for j in range(ph.ny):
+                turned[:, ph.nx - 1 - i, j] = a[:, j, i]
+        err = l2rel(b, turned)
+        _say(f"[c4] rotation k={k}: L2 rel difference {err:.3e}")
+        assert err <= 1e-4
+
+
+def test_c5_adjoint_fp32_vs_oracle():
+    """64x64x16 abdomen, 19 groups, S6, P3: FP32 forward + adjoint against the
+    FP64 oracle adjoint, three iterations per group on both sides, mean dose
+    in the centred 10x10x4 ROI."""
+    import oracle
+
+    prob = I.make_problem("c5")
+    ph = prob.phantom
+    roi = np.zeros((ph.nz, ph.ny, ph.nx))
+    roi[6:10, 27:37, 27:37] = 1.0 / 400.0
+    roi = roi.reshape(-1)
+    fi = np.full(prob.G, 3, dtype=np.int32)
+    _say("[c5] oracle adjoint, 3 iterations per group")
+    ref = oracle.adjoint_problem(prob, roi, fixed_iters=fi, fixed_iters_adj=fi)
+    s = dctsn.Solver(prob)
+    try:
+        _say("[c5] GPU fp32 forward + adjoint")
+        s.solve(precision="fp32", fixed_iters=fi, keep_adjoint=True, autotune=True)
+        a = s.adjoint(roi, fixed_iters=fi)
+    finally:
+        s.close()
+    ed, eg = l2rel(a.d_density, ref.d_density), l2rel(a.d_group_w, ref.d_group_w)
+    _say(f"[c5] R rel err {abs(a.R - ref.R) / abs(ref.R):.3e}; d_density L2 {ed:.3e}; d_group_w L2 {eg:.3e}")
+    assert abs(a.R - ref.R) <= 1e-4 * abs(ref.R)
+    assert ed <= 1e-3 and eg <= 1e-4

@@ -245,3 +245,65 @@ def test_c2_bf16_maps_error(c2_ref):
     err = l2rel(dose, c2_ref.dose)
     _say(f"[c2] bf16-map dose L2 rel err = {err:.3e}")
     assert err <= 2e-2
+
+
+# ------------------------------------------------------------------ schedules, graphs, autotuning
+def _dose_with(prob, **kw):
+    s = dctsn.Solver(prob)
+    try:
+        st = s.solve(**kw)
+        return st, s.dose()
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("name", ["tiny_abd", "multiblock"])
+def test_sweep_schedules_are_bitwise_identical(name):
+    """Every cell's arithmetic is the same whatever the block split (z layers
+    per workgroup) and the wave coupling, so the dose is identical bit for bit."""
+    prob = _multiblock_problem() if name == "multiblock" else I.make_problem(name)
+    ref_st, ref = _dose_with(prob, precision="fp64", tol=1e-8)
+    for bk in (16, 5, 2, 1):
+        for sync in (1, 2):
+            _say(f"[schedule] {name} sweep_bk={bk} sweep_sync={sync}")
+            st, d = _dose_with(prob, precision="fp64", tol=1e-8, sweep_bk=bk, sweep_sync=sync)
+            assert st.sweep_bk == min(bk, prob.phantom.nz) and st.sweep_sync == sync
+            assert np.array_equal(st.iters, ref_st.iters)
+            assert np.array_equal(d, ref)
+
+
+def test_graph_replay_matches_stream_launches():
+    """One captured chunk of iteration sets replayed until convergence gives
+    the same result as launching every set; two solves in a row (the graph is
+    captured per solve), FP64 and FP32."""
+    prob = I.make_problem("tiny_abd")
+    for prec in ("fp64", "fp32"):
+        st0, d0 = _dose_with(prob, precision=prec, tol=1e-7, chunk=3)
+        s = dctsn.Solver(prob)
+        try:
+            for rep in range(2):
+                _say(f"[graph] {prec} replay solve {rep}")
+                st = s.solve(precision=prec, tol=1e-7, chunk=3, use_graph=True)
+                d = s.dose()
+                assert np.array_equal(st.iters, st0.iters)
+                assert st.iteration_sets % 3 == 0
+                assert np.array_equal(d, d0)
+        finally:
+            s.close()
+
+
+def test_autotune_picks_a_schedule_and_caches_it():
+    prob = _multiblock_problem()
+    ref_st, ref = _dose_with(prob, precision="fp32", tol=1e-6)
+    s = dctsn.Solver(prob)
+    try:
+        st1 = s.solve(precision="fp32", tol=1e-6, autotune=True)
+        _say(f"[autotune] chose bk={st1.sweep_bk} sync={st1.sweep_sync} in {st1.tune_ms:.2f} ms")
+        assert st1.tune_ms > 0 and 1 <= st1.sweep_bk <= 16 and st1.sweep_sync in (1, 2)
+        d1 = s.dose()
+        st2 = s.solve(precision="fp32", tol=1e-6, autotune=True)
+        assert st2.tune_ms == 0 and (st2.sweep_bk, st2.sweep_sync) == (st1.sweep_bk, st1.sweep_sync)
+        assert np.array_equal(st1.iters, ref_st.iters)
+        assert np.array_equal(d1, ref) and np.array_equal(s.dose(), ref)
+    finally:
+        s.close()
