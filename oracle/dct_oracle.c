@@ -178,8 +178,8 @@ static int in_beam(const double *d, const double *axis, double fan_deg, double c
 
 /* Uncollided fluence phi_u[B][G][C]: no scatter term, so it follows from the
  * optical depth along the straight ray from the source to each voxel centre
- * (first-collision paragraph of Sec. II-A; "calculated analytically" in
- * Sec. IV).  tau_g is summed in ray order, source to target. */
+ * (first-collision paragraph of Sec. II-A; Sec. IV obtains the uncollided
+ * part in closed form).  tau_g is summed in ray order, source to target. */
 int orc_uncollided(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
                    const uint8_t *mat, const double *rho, int G, int M, const double *st,
                    int B, const double *pos, const double *axis, double fan_deg, double cone_deg,
