@@ -75,8 +75,11 @@ typedef struct dct_opts {
                                  workgroup x wave coupling) on the first iteration and keep
                                  the fastest for this problem shape in the context */
     int sweep_bk;             /* z layers per sweep workgroup, 1..16 (0 = tuned or min(16, nz)) */
-    int sweep_sync;           /* wave coupling inside a sweep workgroup: 1 = LDS progress
-                                 counters, 2 = one barrier per step (0 = tuned or 1) */
+    int sweep_sync;           /* wave coupling: 1 = LDS progress counters between the waves of
+                                 a workgroup, 2 = one barrier per step, 3 = as 1 with all
+                                 blocks of a sweep in one launch, handing block faces over
+                                 as they are produced (needs >= 2 blocks of >= 2 z layers,
+                                 otherwise runs as 1); 0 = tuned or 1 */
 } dct_opts;
 
 typedef struct dct_stats {
@@ -91,7 +94,7 @@ typedef struct dct_stats {
     double solve_ms;          /* device time of the whole dct_solve (HIP events) */
     int iteration_sets;       /* iteration launch sets enqueued (>= max over RHS of iterations) */
     int sweep_bk;             /* sweep schedule that ran: z layers per workgroup */
-    int sweep_sync;           /* and wave coupling (1 LDS counters, 2 barriers) */
+    int sweep_sync;           /* and coupling (1 LDS counters, 2 barriers, 3 pipelined blocks) */
     double tune_ms;           /* device time spent timing candidate schedules in this call */
 } dct_stats;
 

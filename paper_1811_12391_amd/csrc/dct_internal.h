@@ -200,6 +200,12 @@ struct SweepArgs {
     const double *inflow;     // [G] or null
     int fixup;
     int sync;                 // 0: barrier per step, 1: LDS progress counters between waves
+    int pipe;                 // 1: all blocks of a sweep in one launch, block faces handed over
+                              //    through yface_p / zface_p as they are produced
+    void *yface_p;            // T [B*N][NBJ][nx*nz], every element the empty marker between launches
+    void *zface_p;            // T [B*N][NBK][nx*ny]
+    unsigned long long *hint; // [B*N][nblk] progress of each pipelined block: (launch tag << 32) | steps done
+    unsigned seq;             // host launch counter, part of the launch tag
     int *err;                 // set to non-zero when a bounded wait overflowed
 };
 
@@ -260,7 +266,7 @@ hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f64, 1 f32, 2 bf16
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);
-hipError_t launch_sweep(const SweepArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq);
 hipError_t launch_dose(const DoseArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_adj_ray(const AdjRayArgs &a, hipStream_t s);

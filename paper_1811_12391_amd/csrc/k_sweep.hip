@@ -129,6 +129,29 @@ __device__ inline void bst(rsrc_t r, unsigned off, double v)
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, off, 0, 0);
 }
 
+// Device-coherent loads (sc1: served by L2, never by the CU's L1), used for
+// block faces handed between workgroups inside one launch.
+template <typename T> __device__ inline T bld_dev(rsrc_t r, unsigned off);
+template <> __device__ inline float bld_dev<float>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 16));
+}
+template <> __device__ inline double bld_dev<double>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 16));
+}
+// Stores need no cache-policy bit: the CU's vector L1 is write-through, so a
+// plain store reaches the L2 that the consumer's sc1 load reads.
+__device__ inline void bst_dev(rsrc_t r, unsigned off, float v) { bst(r, off, v); }
+__device__ inline void bst_dev(rsrc_t r, unsigned off, double v) { bst(r, off, v); }
+// "Empty" marker of a handed-over face: all bits set, a NaN payload that the
+// arithmetic never produces (generated NaNs are the canonical quiet NaN).
+template <typename T> __device__ inline T face_empty();
+template <> __device__ inline float face_empty<float>() { return __builtin_bit_cast(float, 0xffffffffu); }
+template <> __device__ inline double face_empty<double>() { return __builtin_bit_cast(double, ~0ull); }
+__device__ inline bool is_empty(float v) { return __builtin_bit_cast(unsigned, v) == 0xffffffffu; }
+__device__ inline bool is_empty(double v) { return __builtin_bit_cast(unsigned long long, v) == ~0ull; }
+
 // One workgroup = one (source, direction, block).
 //
 // Wave coupling (SYNC = 1): instead of a workgroup barrier per step, wave w
@@ -148,6 +171,16 @@ __device__ inline void bst(rsrc_t r, unsigned off, double v)
 // only ever consumed by a neighbour that is active at the next step, which is
 // exactly when the lane itself was active.
 //
+// PIPE: every block of a sweep runs in the same launch.  The workgroup index
+// is mapped so that all blocks of one (source, direction) share an XCD (the
+// hardware deals workgroups to the 8 XCDs round robin, so indices congruent
+// mod 8 share one L2) and upstream blocks come first in dispatch order.  A
+// block face is handed over element by element: the producer stores the
+// value, the consumer waits (bounded) until the element is no longer the
+// empty marker, uses it and stores the marker back, so every face buffer is
+// empty again when the launch ends.  Consumers never block producers, so the
+// blocks form a pipeline along the sweep diagonal.
+//
 // MODE 0: forward sweep; 1: forward sweep that also records the fixup set of
 // every cell (kept for the adjoint); 2: the transposed sweep of the frozen-fixup
 // forward sweep (adjoint of the cell relations): cells visited in the reverse
@@ -156,7 +189,7 @@ __device__ inline void bst(rsrc_t r, unsigned off, double v)
 // and passes h_out = lambda:
 //   lambda = (s + sum_{a free} c_a h_a) / (sigma + sum_{a free} c_a),
 //   h_out,a = 2 lambda - h_a (free) or lambda (fixed).
-template <typename T, int PF, bool MULTI, int SYNC, int MODE>
+template <typename T, int PF, bool MULTI, int SYNC, int MODE, bool PIPE>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     constexpr bool ADJ = MODE == 2, KEEP = MODE == 1;
@@ -165,15 +198,35 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     __shared__ T zbuf[SYNC ? 16 : 2][SYNC ? ZR : 16][64];
     __shared__ int prog[16];
     __shared__ double red[3][16];
-    const int item = blockIdx.x;
+    const long nitems = (long)a.B * a.N;
+    int item, bj = 0, bk = 0;
+    if (PIPE) {
+        const int h = blockIdx.x, xcd = h & 7, slot = h >> 3;
+        const int qq = slot / a.nblk, blk = slot - qq * a.nblk;
+        item = qq * 8 + xcd;
+        if (item >= nitems) return;
+        // blk enumerates the blocks diagonal by diagonal (upstream first)
+        int rem = blk;
+        for (int d = 0; d < a.NBJ + a.NBK - 1; ++d) {
+            const int lo = max(0, d - (a.NBK - 1)), hi = min(d, a.NBJ - 1);
+            if (rem <= hi - lo) {
+                bj = lo + rem;
+                bk = d - bj;
+                break;
+            }
+            rem -= hi - lo + 1;
+        }
+    } else {
+        item = blockIdx.x;
+        bj = MULTI ? max(0, a.diag - (a.NBK - 1)) + (int)blockIdx.y : 0;
+        bk = MULTI ? a.diag - bj : 0;
+    }
     const int b = item / a.N;
     const int n = item - b * a.N;
     if (a.state[b].finished) return;
     const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const long C = a.C;
-    const int bj = MULTI ? max(0, a.diag - (a.NBK - 1)) + (int)blockIdx.y : 0;
-    const int bk = MULTI ? a.diag - bj : 0;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nwv = blockDim.x >> 6;
     const double ox = a.dirs[3 * n], oy = a.dirs[3 * n + 1], oz = a.dirs[3 * n + 2];
@@ -192,13 +245,32 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const rsrc_t rpsi = mk_rsrc((T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs + n) * C, C * TS);
     const rsrc_t rmask = mk_rsrc((ADJ || KEEP) && a.mask ? a.mask + (((long)b * a.G + g) * a.N + n) * C : nullptr, C);
     const rsrc_t rsg = mk_rsrc((const T *)a.sigc + ((long)cls * a.G + g) * C, C * TS);
-    // block faces, ping-pong by block parity so a block never reads a location
-    // that a block of the same launch writes
-    const long nitems = (long)a.B * a.N;
-    const rsrc_t ryi = mk_rsrc((const T *)a.yface + ((long)(bj & 1) * nitems + item) * nx * nz, (long)nx * nz * TS);
-    const rsrc_t ryo = mk_rsrc((T *)a.yface + ((long)((bj + 1) & 1) * nitems + item) * nx * nz, (long)nx * nz * TS);
-    const rsrc_t rzi = mk_rsrc((const T *)a.zface + ((long)(bk & 1) * nitems + item) * nx * ny, (long)nx * ny * TS);
-    const rsrc_t rzo = mk_rsrc((T *)a.zface + ((long)((bk + 1) & 1) * nitems + item) * nx * ny, (long)nx * ny * TS);
+    // block faces: with PIPE one slot per block boundary (entering face of
+    // block bj / bk); otherwise ping-pong by block parity so a block never
+    // reads a location that a block of the same launch writes
+    const long yslot_in = PIPE ? (long)item * a.NBJ + bj : (long)(bj & 1) * nitems + item;
+    const long yslot_out = PIPE ? (long)item * a.NBJ + bj + 1 : (long)((bj + 1) & 1) * nitems + item;
+    const long zslot_in = PIPE ? (long)item * a.NBK + bk : (long)(bk & 1) * nitems + item;
+    const long zslot_out = PIPE ? (long)item * a.NBK + bk + 1 : (long)((bk + 1) & 1) * nitems + item;
+    T *yfb = (T *)(PIPE ? a.yface_p : a.yface), *zfb = (T *)(PIPE ? a.zface_p : a.zface);
+    const rsrc_t ryi = mk_rsrc(yfb + yslot_in * nx * nz, (long)nx * nz * TS);
+    const rsrc_t ryo = mk_rsrc(yfb + yslot_out * nx * nz, (long)nx * nz * TS);
+    const rsrc_t rzi = mk_rsrc(zfb + zslot_in * nx * ny, (long)nx * ny * TS);
+    const rsrc_t rzo = mk_rsrc(zfb + zslot_out * nx * ny, (long)nx * ny * TS);
+    const bool yreader = PIPE && valid && l == 0 && bj > 0;   // lanes that take a handed-over face
+    const bool zreader = PIPE && valid && w == 0 && bk > 0;
+    // Pacing of pipelined blocks: the last wave of every block publishes its
+    // step count (tagged with the launch's group / iteration) after each group
+    // of PF steps; a downstream block holds back until its upstream blocks are
+    // far enough ahead that the face elements its prefetches read have been
+    // written.  The hint is advisory (relaxed, unordered with the face
+    // stores): correctness rests on the empty-marker check alone.
+    const unsigned tag = ((unsigned)(a.state[b].g * 65536 + a.state[b].it) ^ (a.seq * 0x9E3779B9u)) | 1u;
+    const rsrc_t rh = mk_rsrc(PIPE ? a.hint : nullptr, (long)nitems * a.nblk * 8);
+    const unsigned hoff_self = (unsigned)((item * a.nblk + bj * a.NBK + bk) * 8);
+    const unsigned hoff_z = bk > 0 ? (unsigned)((item * a.nblk + bj * a.NBK + bk - 1) * 8) : DCT_OOB;
+    const unsigned hoff_y = bj > 0 ? (unsigned)((item * a.nblk + (bj - 1) * a.NBK + bk) * 8) : DCT_OOB;
+    const bool hint_writer = PIPE && w == nw - 1 && l == 0;
     const int jpc = min(jp, ny - 1), kpc = min(kp, nz - 1);   // clamped for padded lanes/waves
     const T bc = a.inflow ? (T)a.inflow[g] : (T)0;
     const int fixup = a.fixup;
@@ -231,7 +303,30 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     T xo = bc, yo = 0, zo = 0;                              // x inflow of a row starts at the boundary value
     double lyv = 0.0, lzv = 0.0;
     int known_prev = 0, known_next = 0, spins = 0;   // wave-uniform
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(rh, 0, 0, 0)) u64v;
+    u64v hz = {0u, 0u}, hy = {0u, 0u};
     for (int tb = -PF; tb < NTp; tb += PF) {
+        if (PIPE && (bj > 0 || bk > 0)) {
+            // this group of steps prefetches up to step tb + 2 PF - 1; its face
+            // elements are written by upstream step + BK (z) or + 64 (y); an
+            // upstream block never reports more than its own padded step count
+            const int upz = ((nx + nl + a.BK - 2 + PF - 1) / PF) * PF;   // z upstream: same rows, full depth
+            const int upy = ((nx + 64 + nw - 2 + PF - 1) / PF) * PF;     // y upstream: 64 rows, same depth
+            const int needz = bk > 0 ? min(tb + 2 * PF + a.BK + 4, upz) : -(1 << 30);
+            const int needy = bj > 0 ? min(tb + 2 * PF + 64 + 4, upy) : -(1 << 30);
+            for (;;) {
+                const int pz = __builtin_amdgcn_readfirstlane(hz[1] == tag ? (int)hz[0] : -(1 << 30));
+                const int py = __builtin_amdgcn_readfirstlane(hy[1] == tag ? (int)hy[0] : -(1 << 30));
+                if ((pz >= needz && py >= needy) || spins >= DCT_SPIN_LIMIT) break;
+                __builtin_amdgcn_s_sleep(4);
+                ++spins;
+                hz = __builtin_amdgcn_raw_buffer_load_b64(rh, hoff_z, 0, 16);
+                hy = __builtin_amdgcn_raw_buffer_load_b64(rh, hoff_y, 0, 16);
+            }
+            // read ahead for the next group's check
+            hz = __builtin_amdgcn_raw_buffer_load_b64(rh, hoff_z, 0, 16);
+            hy = __builtin_amdgcn_raw_buffer_load_b64(rh, hoff_y, 0, 16);
+        }
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int t = tb + u;
@@ -244,6 +339,27 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             }
             const int ip = t - t0l;
             const bool act = valid && (unsigned)ip < (unsigned)nx;
+            if (PIPE) {
+                // a prefetched face element that was still empty is polled
+                // again (rare once the consumer trails its producer)
+                bool ywait = act && yreader && is_empty(yface_in);
+                bool zwait = act && zreader && is_empty(zface_in);
+                while (__builtin_amdgcn_ballot_w64(ywait || zwait) != 0 && spins < DCT_SPIN_LIMIT) {
+                    __builtin_amdgcn_s_sleep(2);
+                    ++spins;
+                    if (ywait) {
+                        yface_in = bld_dev<T>(ryi, (unsigned)(ip + nx * kp) * TS);
+                        ywait = is_empty(yface_in);
+                    }
+                    if (zwait) {
+                        zface_in = bld_dev<T>(rzi, (unsigned)(ip + nx * jp) * TS);
+                        zwait = is_empty(zface_in);
+                    }
+                }
+                // consumed: leave the element empty for the next launch
+                bst_dev(ryi, (act && yreader) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, face_empty<T>());
+                bst_dev(rzi, (act && zreader) ? (unsigned)(ip + nx * jp) * TS : DCT_OOB, face_empty<T>());
+            }
             // y inflow: lane l-1's outflow of the previous step; lane 0 takes the
             // boundary / block face value through the DPP "old" operand
             const T yin = dpp_shift_up_or<T>(yo, yface_in);
@@ -292,8 +408,13 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             bst(rpsi, act ? po * TS : DCT_OOB, c.pc);
             if (KEEP) __builtin_amdgcn_raw_buffer_store_b8((unsigned char)c.fixed, rmask, po, 0, 0);
             if (MULTI) {
-                bst(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
-                bst(rzo, (zwriter && act) ? (unsigned)(ip + nx * jp) * TS : DCT_OOB, c.zo);
+                if (PIPE) {
+                    bst_dev(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
+                    bst_dev(rzo, (zwriter && act) ? (unsigned)(ip + nx * jp) * TS : DCT_OOB, c.zo);
+                } else {
+                    bst(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
+                    bst(rzo, (zwriter && act) ? (unsigned)(ip + nx * jp) * TS : DCT_OOB, c.zo);
+                }
             }
             {
                 int rn = rc + dr;
@@ -311,8 +432,13 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
                 if (MULTI) {
                     const int ipc = inp ? tp - t0l : 0;
-                    yr[MULTI ? u : 0] = bld<T>(ryi, (unsigned)(ipc + nx * kpc) * TS);
-                    zr[MULTI ? u : 0] = bld<T>(rzi, (unsigned)(ipc + nx * jpc) * TS);
+                    if (PIPE) {
+                        yr[MULTI ? u : 0] = bld_dev<T>(ryi, (unsigned)(ipc + nx * kpc) * TS);
+                        zr[MULTI ? u : 0] = bld_dev<T>(rzi, (unsigned)(ipc + nx * jpc) * TS);
+                    } else {
+                        yr[MULTI ? u : 0] = bld<T>(ryi, (unsigned)(ipc + nx * kpc) * TS);
+                        zr[MULTI ? u : 0] = bld<T>(rzi, (unsigned)(ipc + nx * jpc) * TS);
+                    }
                 }
                 int rn = rp + dr;
                 rn = rn == wrap_at ? wrap_to : rn;
@@ -342,8 +468,12 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 __syncthreads();
             }
         }
+        if (PIPE) {
+            const u64v hv = {(unsigned)(tb + PF), tag};
+            __builtin_amdgcn_raw_buffer_store_b64(hv, rh, hint_writer ? hoff_self : DCT_OOB, 0, 0);
+        }
     }
-    if (SYNC && spins >= DCT_SPIN_LIMIT && l == 0) atomicOr(a.err, 1);
+    if ((SYNC || PIPE) && spins >= DCT_SPIN_LIMIT && l == 0) atomicOr(a.err, 1);
     // boundary outflow sums of this block (for the particle balance): the last
     // x outflow of every row, and the y / z outflows of the boundary rows
     double lx = valid ? (double)xo : 0.0;
@@ -367,26 +497,39 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     }
 }
 
-hipError_t launch_sweep(const SweepArgs &a, int is_f64, hipStream_t s)
+hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
 {
+    a.seq = seq;
     const int NBJ = a.NBJ, NBK = a.NBK;
-    int lo = max(0, a.diag - (NBK - 1));
-    int hi = min(a.diag, NBJ - 1);
-    dim3 grid((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
-    dim3 block(64 * a.BK);
     const bool multi = NBJ > 1 || NBK > 1;
+    const bool pipe = a.pipe && multi;
+    dim3 grid, block(64 * a.BK);
+    if (pipe) {
+        const long nitems = (long)a.B * a.N;
+        grid = dim3((unsigned)(8 * ((nitems + 7) / 8) * a.nblk));
+    } else {
+        int lo = max(0, a.diag - (NBK - 1));
+        int hi = min(a.diag, NBJ - 1);
+        grid = dim3((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
+    }
     const int mode = a.adjoint ? 2 : (a.mask ? 1 : 0);
-#define DCT_LAUNCH_SWEEP(T, PF, M, S, MD) hipLaunchKernelGGL((k_sweep<T, PF, M, S, MD>), grid, block, 0, s, a)
-#define DCT_LAUNCH_SWEEP_M(T, PF, M, S)                 \
-    do {                                                \
-        if (mode == 2) DCT_LAUNCH_SWEEP(T, PF, M, S, 2); \
-        else if (mode == 1) DCT_LAUNCH_SWEEP(T, PF, M, S, 1); \
-        else DCT_LAUNCH_SWEEP(T, PF, M, S, 0);          \
+#define DCT_LAUNCH_SWEEP(T, PF, M, S, MD, P) hipLaunchKernelGGL((k_sweep<T, PF, M, S, MD, P>), grid, block, 0, s, a)
+#define DCT_LAUNCH_SWEEP_M(T, PF, M, S, P)                   \
+    do {                                                     \
+        if (mode == 2) DCT_LAUNCH_SWEEP(T, PF, M, S, 2, P);   \
+        else if (mode == 1) DCT_LAUNCH_SWEEP(T, PF, M, S, 1, P); \
+        else DCT_LAUNCH_SWEEP(T, PF, M, S, 0, P);             \
     } while (0)
 #define DCT_LAUNCH_SWEEP_S(T, PF, M) \
-    do { if (a.sync) DCT_LAUNCH_SWEEP_M(T, PF, M, 1); else DCT_LAUNCH_SWEEP_M(T, PF, M, 0); } while (0)
-    if (is_f64) { if (multi) DCT_LAUNCH_SWEEP_S(double, 4, true); else DCT_LAUNCH_SWEEP_S(double, 8, false); }
-    else { if (multi) DCT_LAUNCH_SWEEP_S(float, 8, true); else DCT_LAUNCH_SWEEP_S(float, 8, false); }
+    do { if (a.sync) DCT_LAUNCH_SWEEP_M(T, PF, M, 1, false); else DCT_LAUNCH_SWEEP_M(T, PF, M, 0, false); } while (0)
+    if (pipe) {
+        if (is_f64) DCT_LAUNCH_SWEEP_M(double, 4, true, 1, true);
+        else DCT_LAUNCH_SWEEP_M(float, 8, true, 1, true);
+    } else if (is_f64) {
+        if (multi) DCT_LAUNCH_SWEEP_S(double, 4, true); else DCT_LAUNCH_SWEEP_S(double, 8, false);
+    } else {
+        if (multi) DCT_LAUNCH_SWEEP_S(float, 8, true); else DCT_LAUNCH_SWEEP_S(float, 8, false);
+    }
 #undef DCT_LAUNCH_SWEEP_S
 #undef DCT_LAUNCH_SWEEP_M
 #undef DCT_LAUNCH_SWEEP

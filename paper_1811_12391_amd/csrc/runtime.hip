@@ -73,6 +73,8 @@ struct dct_ctx {
     };
     std::vector<Tuned> tuned;
     int last_bk = 16, last_sync = 1;   // schedule of the last solve (reused by the adjoint)
+    bool pipe_clean = false;           // pipelined-block face buffers hold only the empty marker
+    unsigned sweep_seq = 0;            // counts sweep launches (part of the pipelined blocks' launch tag)
     hipStream_t own_stream = nullptr;  // capture stream when the context's stream is the null stream
 
     std::vector<hipEvent_t> evpool;
@@ -442,7 +444,7 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
     if (pl.NcP == 0) pl.NcP = 16;
     pl.NmP = 16 * ((Nm + 15) / 16);
     if (o.sweep_bk < 0 || o.sweep_bk > 16) return fail(ctx, DCT_EINVAL, "solve: sweep_bk must be in [0, 16]");
-    if (o.sweep_sync < 0 || o.sweep_sync > 2) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be 0, 1 or 2");
+    if (o.sweep_sync < 0 || o.sweep_sync > 3) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 3]");
     set_blocks(pl, o.sweep_bk > 0 ? o.sweep_bk : 16, ctx->ny, ctx->nz);
     return DCT_OK;
 }
@@ -521,6 +523,20 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // block-face buffers, two copies each (ping-pong by block parity)
     HC(dbuf(ctx, "yf", (size_t)2 * B * N * nx * nz * ts, &d_yf));
     HC(dbuf(ctx, "zf", (size_t)2 * B * N * nx * ny * ts, &d_zf));
+    // faces handed over inside a pipelined launch: one slot per block boundary
+    // (blocks of at least 2 z layers)
+    void *d_yfp = nullptr, *d_zfp = nullptr;
+    const size_t yfp_bytes = (size_t)B * N * pl.NBJ * nx * nz * ts;
+    const size_t zfp_bytes = (size_t)B * N * ((nz + 1) / 2) * nx * ny * ts;
+    void *d_hint = nullptr;
+    {
+        void *old_y = ctx->bufs["yfp"].p, *old_z = ctx->bufs["zfp"].p, *old_h = ctx->bufs["hint"].p;
+        HC(dbuf(ctx, "yfp", yfp_bytes, &d_yfp));
+        HC(dbuf(ctx, "zfp", zfp_bytes, &d_zfp));
+        HC(dbuf(ctx, "hint", (size_t)B * N * pl.NBJ * ((nz + 1) / 2) * 8, &d_hint));
+        if (d_yfp != old_y || d_zfp != old_z) ctx->pipe_clean = false;
+        if (d_hint != old_h) HC(hipMemsetAsync(d_hint, 0, (size_t)B * N * pl.NBJ * ((nz + 1) / 2) * 8, s));
+    }
     const size_t leak_max = (size_t)B * N * pl.NBJ * nz * 3 * 8;   // any block split (z layers >= 1)
     HC(dbuf(ctx, "leak", leak_max, &d_leak));
     HC(dbuf(ctx, "state", (size_t)B * sizeof(RhsState), &d_state));
@@ -730,6 +746,11 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     sw.inflow = (const double *)d_infl;
     sw.fixup = o.fixup;
     sw.sync = o.sweep_sync == 2 ? 0 : 1;
+    sw.pipe = 0;
+    sw.yface_p = d_yfp;
+    sw.zface_p = d_zfp;
+    sw.hint = (unsigned long long *)d_hint;
+    sw.seq = 0;
     sw.err = (int *)d_err;
 
     CombArgs cb;
@@ -762,26 +783,42 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         tr.nblk = pl.nblk;
     };
     auto sweep_all = [&]() -> hipError_t {
-        for (int d = 0; d < pl.ndiag; ++d) {
+        for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
             sw.diag = d;
-            hipError_t e = launch_sweep(sw, is64, s);
+            hipError_t e = launch_sweep(sw, is64, s, ctx->sweep_seq++);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };
 
     // ---------------- sweep schedule: given, cached, or timed now
+    // schedule = (z layers per workgroup, coupling): coupling 1 = LDS progress
+    // counters between the waves of a workgroup, 2 = one barrier per step,
+    // 3 = as 1 with every block of a sweep in one launch (pipelined blocks)
     double tune_ms = 0.0;
+    auto set_coupling = [&](int cpl) {
+        sw.sync = cpl != 2;
+        sw.pipe = cpl == 3;
+    };
+    auto pipe_ready = [&]() -> int {
+        // faces handed over inside a launch start out empty (all bits set)
+        if (!ctx->pipe_clean) {
+            HC(hipMemsetAsync(d_yfp, 0xff, yfp_bytes, s));
+            HC(hipMemsetAsync(d_zfp, 0xff, zfp_bytes, s));
+            ctx->pipe_clean = true;
+        }
+        return DCT_OK;
+    };
     {
-        int bk = o.sweep_bk > 0 ? o.sweep_bk : 16, sy = o.sweep_sync == 2 ? 0 : 1;
-        const bool free_bk = o.sweep_bk == 0, free_sync = o.sweep_sync == 0;
-        if (o.autotune && (free_bk || free_sync)) {
+        int bk = o.sweep_bk > 0 ? o.sweep_bk : 16, cpl = o.sweep_sync > 0 ? o.sweep_sync : 1;
+        const bool free_bk = o.sweep_bk == 0, free_cpl = o.sweep_sync == 0;
+        if (o.autotune && (free_bk || free_cpl)) {
             const dct_ctx::Tuned *hit = nullptr;
             for (const auto &t : ctx->tuned)
                 if (t.nx == nx && t.ny == ny && t.nz == nz && t.N == N && t.B == B && t.prec == o.precision) hit = &t;
             if (hit) {
                 if (free_bk) bk = hit->bk;
-                if (free_sync) sy = hit->sync;
+                if (free_cpl) cpl = hit->sync;
             } else {
                 // first iteration set up to the sweep: the transition sets up
                 // group 0 (the first real set then finds nothing pending) and
@@ -794,6 +831,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                     HC(hipEventCreate(&ev));
                     ctx->evpool.push_back(ev);
                 }
+                std::vector<std::pair<int, int>> cands;
                 std::vector<int> bks;
                 if (free_bk) {
                     for (int c : {16, 8, 4, 2}) {
@@ -803,33 +841,58 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 } else {
                     bks.push_back(std::min(bk, nz));
                 }
-                std::vector<int> sys = free_sync ? std::vector<int>{1, 0} : std::vector<int>{sy};
-                float best = 1e30f;
-                for (int cb : bks)
-                    for (int cs : sys) {
-                        apply_blocks(cb);
-                        sw.sync = cs;
-                        HC(sweep_all());   // warm-up
-                        HC(hipEventRecord(ctx->evpool[0], s));
-                        for (int r = 0; r < 3; ++r) HC(sweep_all());
-                        HC(hipEventRecord(ctx->evpool[1], s));
-                        HC(hipEventSynchronize(ctx->evpool[1]));
-                        float ms = 0.0f;
-                        HC(hipEventElapsedTime(&ms, ctx->evpool[0], ctx->evpool[1]));
-                        tune_ms += ms * 4.0 / 3.0;
-                        if (ms < best) {
-                            best = ms;
-                            bk = cb;
-                            sy = cs;
-                        }
+                for (int cb : bks) {
+                    const bool multi = (ny + 63) / 64 > 1 || (nz + cb - 1) / cb > 1;
+                    for (int cc : {1, 2, 3}) {
+                        if (!free_cpl && cc != cpl) continue;
+                        if (cc == 3 && (!multi || cb < 2)) continue;   // pipelining needs several blocks
+                        cands.push_back({cb, cc});
                     }
-                ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, bk, sy});
+                }
+                float best = 1e30f;
+                for (auto cand : cands) {
+                    apply_blocks(cand.first);
+                    set_coupling(cand.second);
+                    if (cand.second == 3) {
+                        int r = pipe_ready();
+                        if (r != DCT_OK) return r;
+                    }
+                    HC(sweep_all());   // warm-up
+                    HC(hipEventRecord(ctx->evpool[0], s));
+                    for (int r = 0; r < 3; ++r) HC(sweep_all());
+                    HC(hipEventRecord(ctx->evpool[1], s));
+                    HC(hipEventSynchronize(ctx->evpool[1]));
+                    int h_err = 0;
+                    HC(hipMemcpy(&h_err, d_err, 4, hipMemcpyDeviceToHost));
+                    if (h_err) {
+                        // a bounded wait gave up: drop this candidate, reset the
+                        // flag and the handed-over faces
+                        HC(hipMemsetAsync(d_err, 0, 4, s));
+                        ctx->pipe_clean = false;
+                        continue;
+                    }
+                    float ms = 0.0f;
+                    HC(hipEventElapsedTime(&ms, ctx->evpool[0], ctx->evpool[1]));
+                    tune_ms += ms * 4.0 / 3.0;
+                    if (ms < best) {
+                        best = ms;
+                        bk = cand.first;
+                        cpl = cand.second;
+                    }
+                }
+                if (best == 1e30f) return fail(ctx, DCT_EDEVICE, "solve: no sweep schedule completed during tuning");
+                ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, bk, cpl});
             }
         }
         apply_blocks(bk);
-        sw.sync = sy;
+        if (cpl == 3 && (pl.nblk == 1 || pl.BK < 2)) cpl = 1;   // one block (or 1-layer blocks): not pipelined
+        set_coupling(cpl);
+        if (cpl == 3) {
+            int r = pipe_ready();
+            if (r != DCT_OK) return r;
+        }
         ctx->last_bk = pl.BK;
-        ctx->last_sync = sy;
+        ctx->last_sync = cpl;
     }
 
     // upper bound of iteration sets: every group at its cap plus one transition each
@@ -842,7 +905,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         hipError_t e = launch_transition(tr, is64, es);
         if (e != hipSuccess) return e;
         if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
-        for (int d = 0; d < pl.ndiag; ++d) {
+        for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
             sw.diag = d;
             if (profile) {
                 while ((int)ctx->evpool.size() < 2 * (nprof + 1)) {
@@ -852,7 +915,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 if ((e = hipEventRecord(ctx->evpool[2 * nprof], es)) != hipSuccess) return e;
             }
-            if ((e = launch_sweep(sw, is64, es)) != hipSuccess) return e;
+            if ((e = launch_sweep(sw, is64, es, ctx->sweep_seq++)) != hipSuccess) return e;
             if (profile) {
                 if ((e = hipEventRecord(ctx->evpool[2 * nprof + 1], es)) != hipSuccess) return e;
                 ++nprof;
@@ -940,6 +1003,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(hipMemcpy(&h_err, d_err, 4, hipMemcpyDeviceToHost));
     if (h_err) {
         ctx->solved = false;
+        ctx->pipe_clean = false;
         return fail(ctx, DCT_EDEVICE, "solve: a sweep wave wait exceeded its bound (inter-wave synchronisation)");
     }
     int status = DCT_OK;
@@ -968,7 +1032,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         stats->sweep_launches = nprof;
         stats->iteration_sets = (int)sets;
         stats->sweep_bk = pl.BK;
-        stats->sweep_sync = sw.sync ? 1 : 2;
+        stats->sweep_sync = ctx->last_sync;
         stats->tune_ms = tune_ms;
     }
     ctx->solved = true;
@@ -1250,7 +1314,12 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     sw.state = (const RhsState *)B_("state");
     sw.inflow = nullptr;
     sw.fixup = 0;
-    sw.sync = ctx->last_sync;
+    sw.sync = ctx->last_sync != 2;
+    sw.pipe = ctx->last_sync == 3;
+    sw.yface_p = B_("yfp");
+    sw.zface_p = B_("zfp");
+    sw.hint = (unsigned long long *)B_("hint");
+    sw.seq = 0;
     sw.err = (int *)B_("err");
 
     CombArgs cb;
@@ -1281,9 +1350,9 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
         hipError_t e = launch_adj_transition(at, is64, s);
         if (e != hipSuccess) return e;
         if ((e = launch_mmap(ma, mode, s)) != hipSuccess) return e;
-        for (int d = 0; d < pl.ndiag; ++d) {
+        for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
             sw.diag = d;
-            if ((e = launch_sweep(sw, is64, s)) != hipSuccess) return e;
+            if ((e = launch_sweep(sw, is64, s, ctx->sweep_seq++)) != hipSuccess) return e;
         }
         if ((e = launch_dmap(ma, mode, s)) != hipSuccess) return e;
         return launch_combine(cb, is64, s);
@@ -1326,7 +1395,10 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     HC(hipEventSynchronize(ctx->ev_t1));
     int h_err = 0;
     HC(hipMemcpy(&h_err, B_("err"), 4, hipMemcpyDeviceToHost));
-    if (h_err) return fail(ctx, DCT_EDEVICE, "adjoint: a sweep wave wait exceeded its bound");
+    if (h_err) {
+        ctx->pipe_clean = false;
+        return fail(ctx, DCT_EDEVICE, "adjoint: a sweep wave wait exceeded its bound");
+    }
     if (unfinished != 0) return fail(ctx, DCT_ENOTCONV, "adjoint: iteration-set cap reached");
 
     std::vector<double> drho((size_t)B * C), dray(C), dose((size_t)B * C);

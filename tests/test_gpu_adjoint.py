@@ -197,3 +197,19 @@ def test_autograd_wrapper():
         assert rel(gw.grad.numpy() / 3.0, ref.d_group_w) < 1e-9
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("bk,sync", [(5, 3), (4, 2)])
+def test_adjoint_other_schedules(bk, sync):
+    """The adjoint sweeps reuse the forward solve's schedule (here pipelined
+    blocks, or barrier-coupled split blocks) and still match the oracle."""
+    prob, roi, fi, fa, ref = _oracle_adjoint("multiblock")
+    s = dctsn.Solver(prob)
+    try:
+        st = s.solve(precision="fp64", fixed_iters=fi, keep_adjoint=True, sweep_bk=bk, sweep_sync=sync)
+        assert (st.sweep_bk, st.sweep_sync) == (bk, sync)
+        a = s.adjoint(roi, fixed_iters=fa)
+    finally:
+        s.close()
+    assert rel(a.d_density, ref.d_density) < 1e-9
+    assert rel(a.d_group_w, ref.d_group_w) < 1e-9
