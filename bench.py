@@ -64,6 +64,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32,fp32_bf16map")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="configuration to time (the headline metric is quoted on c2; the others are for profiling)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched axial-scan and adjoint forms (reported beside the headline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -85,7 +89,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prob = I.make_problem("c2")
+    prob = I.make_problem(args.workload)
     C, G, N = prob.phantom.C, prob.G, prob.N
     solver = dctsn.Solver(prob, device=0, stream=ct_stream(stream))
     dose_dev = torch.empty(C, dtype=torch.float64, device="cuda")
@@ -164,9 +168,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp32_bf16map": "f32+bf16"}[best],
         "data": "synthetic",
-        "config": {"workload": "water cylinder d=35cm in air, 64x64x16 voxels @0.6cm, 1 point source 54cm "
-                               "(20x10 deg), 19 groups 10-120keV Kramers, S8 (80 dirs), P3, tol 1e-6",
-                   "voxels": C, "groups": G, "directions": N, "legendre_order": prob.L, "sources": 1,
+        "config": {"workload": WORKLOADS[args.workload],
+                   "voxels": C, "groups": G, "directions": N, "legendre_order": prob.L, "sources": prob.B,
                    "precision": best},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best),
@@ -174,13 +177,98 @@ def main():
                      "bytes_per_launch": bytes_per_solve / launches},
         "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()},
     }
+    if not args.no_forms:
+        solver.close()
+        solver = None
+        line["forms"] = other_forms(args)
     if not args.no_cpu_baseline:
         _log("[bench] timing the FP64 CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(prob)
-    solver.close()
+    if solver is not None:
+        solver.close()
     print(json.dumps(line), flush=True)
 
 
+def other_forms(args):
+    """The batched and differentiated forms of the solve, each against the
+    same form in FP64 on the GPU: the 36-source axial scan (FP32, autotuned,
+    graph replay) and the ROI-dose gradient on the 64x64x16 abdomen (FP32
+    forward + adjoint)."""
+    import numpy as np
+    import torch
+
+    from paper_1811_12391_amd import dctsn, inputs as I
+
+    out = {}
+    # axial scan: 36 right-hand sides in one solve
+    prob = I.make_problem("c4")
+    s = dctsn.Solver(prob)
+    try:
+        s.solve(precision="fp64", tol=prob.tol)
+        ref = s.dose(summed=True)
+        kw = dict(precision="fp32", tol=prob.tol, autotune=True, use_graph=True, chunk=8)
+        s.solve(**kw)
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = s.solve(**kw)
+        wall = (time.perf_counter() - t0) / reps
+        d = s.dose(summed=True)
+        upd = float(st.iters.sum()) * prob.phantom.C * prob.N
+        out["axial_scan_batched"] = {
+            "workload": "c2 cylinder, 36 sources every 10 deg on a 54 cm circle, 19 groups, S6 (48 dirs), P3",
+            "precision": "fp32", "ms_per_solve": 1e3 * wall, "updates_per_s": upd / wall,
+            "sweep_schedule": {"z_layers_per_workgroup": int(st.sweep_bk), "coupling": int(st.sweep_sync)},
+            "summed_dose_l2_rel_err_vs_fp64_gpu": float(np.linalg.norm(d - ref) / np.linalg.norm(ref)),
+        }
+        _log(f"[bench] axial scan (36 sources) fp32: {1e3 * wall:.1f} ms/solve, {upd / wall:.3e} updates/s")
+    finally:
+        s.close()
+    # ROI-dose gradient
+    prob = I.make_problem("c5")
+    ph = prob.phantom
+    roi = np.zeros((ph.nz, ph.ny, ph.nx))
+    roi[6:10, 27:37, 27:37] = 1.0 / 400.0
+    roi = roi.reshape(-1)
+    s = dctsn.Solver(prob)
+    try:
+        s.solve(precision="fp64", tol=prob.tol, keep_adjoint=True)
+        a64 = s.adjoint(roi, tol=prob.tol)
+        res = {}
+        for rep in range(2):
+            t0 = time.perf_counter()
+            st = s.solve(precision="fp32", tol=prob.tol, keep_adjoint=True, autotune=True)
+            t1 = time.perf_counter()
+            a32 = s.adjoint(roi, tol=prob.tol)
+            t2 = time.perf_counter()
+            res = {"forward_ms": 1e3 * (t1 - t0), "adjoint_ms": 1e3 * (t2 - t1)}
+        l2 = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+        out["roi_dose_gradient"] = {
+            "workload": "64x64x16 abdomen, 19 groups, S6, P3, mean dose in the centred 10x10x4 ROI",
+            "precision": "fp32", **res,
+            "d_density_l2_rel_err_vs_fp64_gpu": l2(a32.d_density, a64.d_density),
+            "d_group_w_l2_rel_err_vs_fp64_gpu": l2(a32.d_group_w, a64.d_group_w),
+            "roi_dose_rel_err_vs_fp64_gpu": abs(a32.R - a64.R) / abs(a64.R),
+        }
+        _log(f"[bench] ROI gradient fp32: forward {res['forward_ms']:.1f} ms, adjoint {res['adjoint_ms']:.1f} ms")
+    finally:
+        s.close()
+    return out
+
+
+WORKLOADS = {
+    "c1": "water cylinder d=35cm in air, 24x24x8 voxels @1.5cm, 1 point source 54cm (20x10 deg), 4 groups "
+          "10-120keV Kramers, S4 (24 dirs), P1, tol 1e-6",
+    "c2": "water cylinder d=35cm in air, 64x64x16 voxels @0.6cm, 1 point source 54cm (20x10 deg), 19 groups "
+          "10-120keV Kramers, S8 (80 dirs), P3, tol 1e-6",
+    "c3": "seeded abdomen phantom, 128x128x32 voxels @0.3cm, 1 point source 54cm (20x10 deg), 19 groups, "
+          "S8 (80 dirs), P3, tol 1e-6",
+    "c4": "water cylinder d=35cm in air, 64x64x16 voxels @0.6cm, 36 sources every 10 deg on a 54cm circle, "
+          "19 groups, S6 (48 dirs), P3, tol 1e-6",
+    "c5": "seeded abdomen phantom, 64x64x16 voxels @0.6cm, 1 point source 54cm, 19 groups, S6 (48 dirs), P3, "
+          "tol 1e-6",
+}
 COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c2_hbm_traffic.txt")
 SWEEP_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_sweep.hip")

@@ -193,8 +193,8 @@ struct SweepArgs {
     int reverse;              // groups run from G-1 down to 0 (adjoint machine)
     int adjoint;              // transposed sweep: reverse traversal, frozen masks, no fixup decisions
     const void *sigc;         // T [2][G][C]
-    void *yface;              // T [B*N][nx*nz]
-    void *zface;              // T [B*N][nx*ny]
+    void *yface;              // T [2][B*N][nx*nz]
+    void *zface;              // T [2][B*N][NBJ][(nx+63)*64] (diagonal strips)
     double *leak_part;        // [B][N][nblk][3]
     const RhsState *state;
     const double *inflow;     // [G] or null
@@ -203,7 +203,7 @@ struct SweepArgs {
     int pipe;                 // 1: all blocks of a sweep in one launch, block faces handed over
                               //    through yface_p / zface_p as they are produced
     void *yface_p;            // T [B*N][NBJ][nx*nz], every element the empty marker between launches
-    void *zface_p;            // T [B*N][NBK][nx*ny]
+    void *zface_p;            // T [B*N][NBK][NBJ][(nx+63)*64]
     unsigned long long *hint; // [B*N][nblk] progress of each pipelined block: (launch tag << 32) | steps done
     unsigned seq;             // host launch counter, part of the launch tag
     int *err;                 // set to non-zero when a bounded wait overflowed

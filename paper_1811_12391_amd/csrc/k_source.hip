@@ -46,16 +46,19 @@ __device__ inline double block_sum(double v, double *red)
     return t;   // valid on thread 0
 }
 
+// max that keeps a NaN (fmax would drop it and hide a non-finite change)
+__device__ inline double nan_max(double x, double y) { return (y > x || y != y) ? y : x; }
+
 __device__ inline double block_max(double v, double *red)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_down(v, o, 64));
     int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
     if (l == 0) red[w] = v;
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, red[i]);
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = nan_max(t, red[i]);
     return t;
 }
 
@@ -292,7 +295,12 @@ hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s)
 
 // LDS tile of one slab (z layer k, 16 consecutive y rows, all x) with an odd
 // row pitch so that the 16 lanes of a row segment hit distinct banks.
-template <typename T>
+//
+// E > 0: every thread holds E tile elements (16 nx <= 256 E) and issues all of
+// its global loads (both class halves, the external source, the previous
+// phi_00, material and density) before the first LDS phase, so the memory
+// latency is paid once per workgroup.  E = 0: generic loop for wide grids.
+template <typename T, int E>
 __global__ __launch_bounds__(256) void k_combine(CombArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -312,23 +320,89 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     const int j0 = (blockIdx.x % nslj) * 16;
     const int pitch = nx + 1;
     const int tile_n = 16 * nx;
-    const T *partA = (const T *)a.part + (long)b * Nm * C;
-    const T *partB = (const T *)a.part + ((long)a.B + b) * Nm * C;
-    T *QA = (T *)a.Qc + (long)b * Nm * C;
-    T *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
-    const T *ext = (const T *)a.ext + (long)b * Nm * C;
+    const int lm = blockIdx.z;
+    const int l = l_of(lm);
+    const T *partA = (const T *)a.part + ((long)b * Nm + lm) * C;
+    const T *partB = (const T *)a.part + (((long)a.B + b) * Nm + lm) * C;
+    T *QA = (T *)a.Qc + ((long)b * Nm + lm) * C;
+    T *QB = (T *)a.Qc + (((long)a.B + b) * Nm + lm) * C;
+    const T *ext = (const T *)a.ext + ((long)b * Nm + lm) * C;
     T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
     double dmax = 0.0, fmax_ = 0.0;
-    {
-        const int lm = blockIdx.z;
-        const int l = l_of(lm);
+    if (E > 0) {
+        constexpr int EE = E > 0 ? E : 1;
+        T va[EE], vb[EE], ve[EE], vo[EE];
+        double sc[EE];
+#pragma unroll
+        for (int e = 0; e < EE; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            // rotated-row order (class halves)
+            const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+            const bool okr = idx < tile_n && j < ny;
+            const long p = ((long)k * nx + (okr ? r : 0)) * ny + (okr ? j : 0);
+            va[e] = okr ? partA[p] : (T)0;
+            vb[e] = okr ? partB[p] : (T)0;
+            // natural order
+            const int jn = idx / nx, in = idx - jn * nx, jj = j0 + jn;
+            const bool okn = idx < tile_n && jj < ny;
+            const long v = okn ? in + (long)nx * (jj + (long)ny * k) : 0;
+            ve[e] = okn ? ext[v] : (T)0;
+            vo[e] = (okn && lm == 0) ? phib[v] : (T)0;
+            const int m = okn ? a.mat[v] : 0;
+            sc[e] = okn ? a.rho[v] * a.ss[(((long)m * (L + 1) + l) * G + g) * G + g] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < EE; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+            if (idx < tile_n && j < ny) tile[jl * pitch + rot_row(1, r, j % nx, nx)] = va[e];   // class A -> natural i
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EE; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+            if (idx < tile_n && j < ny) tile[jl * pitch + rot_row(0, r, j % nx, nx)] += vb[e];  // class B -> natural i
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EE; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int jn = idx / nx, in = idx - jn * nx, jj = j0 + jn;
+            if (idx < tile_n && jj < ny) {
+                const long v = in + (long)nx * (jj + (long)ny * k);
+                const T pn = tile[jn * pitch + in];
+                if (lm == 0) {
+                    const double dn = fabs((double)pn - (double)vo[e]);
+                    const double an = fabs((double)pn);
+                    dmax = (dn > dmax || dn != dn) ? dn : dmax;
+                    fmax_ = (an > fmax_ || an != an) ? an : fmax_;
+                }
+                phib[(long)lm * C + v] = pn;
+                tile[jn * pitch + in] = (T)((double)ve[e] + sc[e] * (double)pn);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EE; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+            if (idx < tile_n && j < ny) {
+                const int jm = j % nx;
+                const long p = ((long)k * nx + r) * ny + j;
+                QA[p] = tile[jl * pitch + rot_row(1, r, jm, nx)];
+                QB[p] = tile[jl * pitch + rot_row(0, r, jm, nx)];
+            }
+        }
+        __syncthreads();
+    } else {
         // class A half, rotated rows -> natural tile
         for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
             int r = idx >> 4, jl = idx & 15, j = j0 + jl;
             if (j < ny) {
                 int i = rot_row(1, r, j % nx, nx);          // inverse of (i + j) mod nx
                 long p = ((long)k * nx + r) * ny + j;
-                tile[jl * pitch + i] = partA[(long)lm * C + p];
+                tile[jl * pitch + i] = partA[p];
             }
         }
         __syncthreads();
@@ -337,7 +411,7 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             if (j < ny) {
                 int i = rot_row(0, r, j % nx, nx);          // inverse of (i - j) mod nx
                 long p = ((long)k * nx + r) * ny + j;
-                tile[jl * pitch + i] += partB[(long)lm * C + p];
+                tile[jl * pitch + i] += partB[p];
             }
         }
         __syncthreads();
@@ -357,7 +431,7 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
                 phib[(long)lm * C + v] = pn;
                 int m = a.mat[v];
                 double s = a.rho[v] * a.ss[(((long)m * (L + 1) + l) * G + g) * G + g];
-                tile[jl * pitch + i] = (T)((double)ext[(long)lm * C + v] + s * (double)pn);
+                tile[jl * pitch + i] = (T)((double)ext[v] + s * (double)pn);
             }
         }
         __syncthreads();
@@ -366,8 +440,8 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             if (j < ny) {
                 int jm = j % nx;
                 long p = ((long)k * nx + r) * ny + j;
-                QA[(long)lm * C + p] = tile[jl * pitch + rot_row(1, r, jm, nx)];
-                QB[(long)lm * C + p] = tile[jl * pitch + rot_row(0, r, jm, nx)];
+                QA[p] = tile[jl * pitch + rot_row(1, r, jm, nx)];
+                QB[p] = tile[jl * pitch + rot_row(0, r, jm, nx)];
             }
         }
         __syncthreads();
@@ -418,8 +492,11 @@ hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s)
     const int nslj = (a.geo.ny + 15) >> 4;
     dim3 grid((unsigned)(a.geo.nz * nslj), a.B, a.Nm);
     size_t shm = (size_t)16 * (a.geo.nx + 1) * (is_f64 ? 8 : 4);
-    if (is_f64) hipLaunchKernelGGL(k_combine<double>, grid, dim3(256), shm, s, a);
-    else hipLaunchKernelGGL(k_combine<float>, grid, dim3(256), shm, s, a);
+    const int per = (16 * a.geo.nx + 255) / 256;   // tile elements per thread
+#define DCT_LAUNCH_COMBINE(T)                                                                          do {                                                                                                   if (per <= 1) hipLaunchKernelGGL((k_combine<T, 1>), grid, dim3(256), shm, s, a);                  else if (per <= 2) hipLaunchKernelGGL((k_combine<T, 2>), grid, dim3(256), shm, s, a);             else if (per <= 4) hipLaunchKernelGGL((k_combine<T, 4>), grid, dim3(256), shm, s, a);             else if (per <= 8) hipLaunchKernelGGL((k_combine<T, 8>), grid, dim3(256), shm, s, a);             else hipLaunchKernelGGL((k_combine<T, 0>), grid, dim3(256), shm, s, a);                       } while (0)
+    if (is_f64) DCT_LAUNCH_COMBINE(double);
+    else DCT_LAUNCH_COMBINE(float);
+#undef DCT_LAUNCH_COMBINE
     return hipGetLastError();
 }
 

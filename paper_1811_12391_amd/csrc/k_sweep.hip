@@ -194,6 +194,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     constexpr bool ADJ = MODE == 2, KEEP = MODE == 1;
     constexpr int ZR = 4;                                   // z-face ring depth (SYNC = 1)
+    constexpr int FD = PIPE ? 2 : PF;                       // prefetch distance of block faces
     constexpr unsigned TS = sizeof(T);
     __shared__ T zbuf[SYNC ? 16 : 2][SYNC ? ZR : 16][64];
     __shared__ int prog[16];
@@ -255,10 +256,16 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     T *yfb = (T *)(PIPE ? a.yface_p : a.yface), *zfb = (T *)(PIPE ? a.zface_p : a.zface);
     const rsrc_t ryi = mk_rsrc(yfb + yslot_in * nx * nz, (long)nx * nz * TS);
     const rsrc_t ryo = mk_rsrc(yfb + yslot_out * nx * nz, (long)nx * nz * TS);
-    const rsrc_t rzi = mk_rsrc(zfb + zslot_in * nx * ny, (long)nx * ny * TS);
-    const rsrc_t rzo = mk_rsrc(zfb + zslot_out * nx * ny, (long)nx * ny * TS);
-    const bool yreader = PIPE && valid && l == 0 && bj > 0;   // lanes that take a handed-over face
-    const bool zreader = PIPE && valid && w == 0 && bk > 0;
+    // z faces are stored per y block along the wave diagonal: element
+    // (ip + l) * 64 + l for lane l, so the 64 lanes that hand over (or take)
+    // a face in one step touch 64 consecutive elements
+    const long ZS = (long)(nx + 63) * 64;
+    const rsrc_t rzi = mk_rsrc(zfb + (zslot_in * a.NBJ + bj) * ZS, ZS * TS);
+    const rsrc_t rzo = mk_rsrc(zfb + (zslot_out * a.NBJ + bj) * ZS, ZS * TS);
+    const bool ytaker = valid && l == 0 && bj > 0;            // lanes whose inflow is a block face
+    const bool ztaker = valid && w == 0 && bk > 0;
+    const bool yreader = PIPE && ytaker;                      // ... handed over inside the launch
+    const bool zreader = PIPE && ztaker;
     // Pacing of pipelined blocks: the last wave of every block publishes its
     // step count (tagged with the launch's group / iteration) after each group
     // of PF steps; a downstream block holds back until its upstream blocks are
@@ -271,7 +278,6 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const unsigned hoff_z = bk > 0 ? (unsigned)((item * a.nblk + bj * a.NBK + bk - 1) * 8) : DCT_OOB;
     const unsigned hoff_y = bj > 0 ? (unsigned)((item * a.nblk + (bj - 1) * a.NBK + bk) * 8) : DCT_OOB;
     const bool hint_writer = PIPE && w == nw - 1 && l == 0;
-    const int jpc = min(jp, ny - 1), kpc = min(kp, nz - 1);   // clamped for padded lanes/waves
     const T bc = a.inflow ? (T)a.inflow[g] : (T)0;
     const int fixup = a.fixup;
     const int NT = nx + nl + nw - 2;
@@ -299,21 +305,30 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         if (MULTI) yr[MULTI ? u : 0] = zr[MULTI ? u : 0] = (T)0;
         if (ADJ) fr[ADJ ? u : 0] = 0;
     }
-    int rp = rstart, rc = rstart;
+    // element offsets of the prefetch and the current cell: one rotated row
+    // (ny elements) per x step, wrapping inside the (k, rotated row) plane
+    const int dny = sx ? ny : -ny;
+    const int wrap_at_e = rowbase + wrap_at * ny, wrap_to_e = rowbase + wrap_to * ny;
+    int pe = rowbase + rstart * ny, ce = pe;
     T xo = bc, yo = 0, zo = 0;                              // x inflow of a row starts at the boundary value
-    double lyv = 0.0, lzv = 0.0;
+    // leakage: the y outflow of a lane is summed in T (at most nx terms per
+    // lane) and widened at the end; only the wave on the z boundary sums z
+    T lyv = 0;
+    double lzv = 0.0;
+    const bool zlast_wave = __builtin_amdgcn_readfirstlane(kp) == nz - 1;
     int known_prev = 0, known_next = 0, spins = 0;   // wave-uniform
     typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(rh, 0, 0, 0)) u64v;
     u64v hz = {0u, 0u}, hy = {0u, 0u};
     for (int tb = -PF; tb < NTp; tb += PF) {
         if (PIPE && (bj > 0 || bk > 0)) {
-            // this group of steps prefetches up to step tb + 2 PF - 1; its face
-            // elements are written by upstream step + BK (z) or + 64 (y); an
-            // upstream block never reports more than its own padded step count
+            // this group of steps loads faces up to step tb + PF - 1 + FD; the
+            // face of step s is written by upstream step s + BK - 1 (z) or
+            // s + 63 (y); an upstream block never reports more than its own
+            // padded step count
             const int upz = ((nx + nl + a.BK - 2 + PF - 1) / PF) * PF;   // z upstream: same rows, full depth
             const int upy = ((nx + 64 + nw - 2 + PF - 1) / PF) * PF;     // y upstream: 64 rows, same depth
-            const int needz = bk > 0 ? min(tb + 2 * PF + a.BK + 4, upz) : -(1 << 30);
-            const int needy = bj > 0 ? min(tb + 2 * PF + 64 + 4, upy) : -(1 << 30);
+            const int needz = bk > 0 ? min(tb + PF + FD + a.BK + 2, upz) : -(1 << 30);
+            const int needy = bj > 0 ? min(tb + PF + FD + 64 + 2, upy) : -(1 << 30);
             for (;;) {
                 const int pz = __builtin_amdgcn_readfirstlane(hz[1] == tag ? (int)hz[0] : -(1 << 30));
                 const int py = __builtin_amdgcn_readfirstlane(hy[1] == tag ? (int)hy[0] : -(1 << 30));
@@ -352,13 +367,13 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                         ywait = is_empty(yface_in);
                     }
                     if (zwait) {
-                        zface_in = bld_dev<T>(rzi, (unsigned)(ip + nx * jp) * TS);
+                        zface_in = bld_dev<T>(rzi, (unsigned)((ip + l) * 64 + l) * TS);
                         zwait = is_empty(zface_in);
                     }
                 }
                 // consumed: leave the element empty for the next launch
                 bst_dev(ryi, (act && yreader) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, face_empty<T>());
-                bst_dev(rzi, (act && zreader) ? (unsigned)(ip + nx * jp) * TS : DCT_OOB, face_empty<T>());
+                bst_dev(rzi, (act && zreader) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, face_empty<T>());
             }
             // y inflow: lane l-1's outflow of the previous step; lane 0 takes the
             // boundary / block face value through the DPP "old" operand
@@ -404,48 +419,55 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 if (fixup && act && __builtin_expect(fmin(c.xo, fmin(c.yo, c.zo)) < (T)0, 0))
                     c = dd_fixup<T>(qv, sv, cx, cy, cz, xin, yin, zin, c);
             }
-            const unsigned po = act ? (unsigned)(rowbase + rc * ny) : DCT_OOB;
+            const unsigned po = act ? (unsigned)ce : DCT_OOB;
             bst(rpsi, act ? po * TS : DCT_OOB, c.pc);
             if (KEEP) __builtin_amdgcn_raw_buffer_store_b8((unsigned char)c.fixed, rmask, po, 0, 0);
             if (MULTI) {
                 if (PIPE) {
                     bst_dev(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
-                    bst_dev(rzo, (zwriter && act) ? (unsigned)(ip + nx * jp) * TS : DCT_OOB, c.zo);
+                    bst_dev(rzo, (zwriter && act) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, c.zo);
                 } else {
                     bst(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
-                    bst(rzo, (zwriter && act) ? (unsigned)(ip + nx * jp) * TS : DCT_OOB, c.zo);
+                    bst(rzo, (zwriter && act) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, c.zo);
                 }
             }
             {
-                int rn = rc + dr;
-                rn = rn == wrap_at ? wrap_to : rn;
-                rc = act ? rn : rc;
+                int cn = ce + dny;
+                cn = cn == wrap_at_e ? wrap_to_e : cn;
+                ce = act ? cn : ce;
             }
             // prefetch step t + PF into the slots this step has just consumed
             // (issued after their last use so the new values need no copy)
             {
                 const int tp = t + PF;
-                const unsigned pp = (unsigned)(rowbase + rp * ny);
+                const unsigned pp = (unsigned)pe;
                 qr[u] = bld<T>(rq, pp * TS);
                 sr[u] = bld<T>(rsg, pp * TS);
                 if (ADJ) fr[ADJ ? u : 0] = __builtin_amdgcn_raw_buffer_load_b8(rmask, pp, 0, 0);
                 const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
                 if (MULTI) {
-                    const int ipc = inp ? tp - t0l : 0;
+                    // block faces of step t + FD (only the lanes that take a
+                    // block face load one) into the slot consumed at that step
+                    const int tf = t + FD;
+                    const bool inf = valid && (unsigned)(tf - t0l) < (unsigned)nx;
+                    const int ipn = tf - t0l;
+                    const unsigned yo_off = (inf && ytaker) ? (unsigned)(ipn + nx * kp) * TS : DCT_OOB;
+                    const unsigned zo_off = (inf && ztaker) ? (unsigned)((ipn + l) * 64 + l) * TS : DCT_OOB;
+                    const int fs = (u + FD) % PF;   // constant once the step loop is unrolled
                     if (PIPE) {
-                        yr[MULTI ? u : 0] = bld_dev<T>(ryi, (unsigned)(ipc + nx * kpc) * TS);
-                        zr[MULTI ? u : 0] = bld_dev<T>(rzi, (unsigned)(ipc + nx * jpc) * TS);
+                        yr[MULTI ? fs : 0] = bld_dev<T>(ryi, yo_off);
+                        zr[MULTI ? fs : 0] = bld_dev<T>(rzi, zo_off);
                     } else {
-                        yr[MULTI ? u : 0] = bld<T>(ryi, (unsigned)(ipc + nx * kpc) * TS);
-                        zr[MULTI ? u : 0] = bld<T>(rzi, (unsigned)(ipc + nx * jpc) * TS);
+                        yr[MULTI ? fs : 0] = bld<T>(ryi, yo_off);
+                        zr[MULTI ? fs : 0] = bld<T>(rzi, zo_off);
                     }
                 }
-                int rn = rp + dr;
-                rn = rn == wrap_at ? wrap_to : rn;
-                rp = inp ? rn : rp;
+                int pn = pe + dny;
+                pn = pn == wrap_at_e ? wrap_to_e : pn;
+                pe = inp ? pn : pe;
             }
-            lyv += act ? (double)c.yo : 0.0;
-            lzv += act ? (double)c.zo : 0.0;
+            lyv += act ? c.yo : (T)0;
+            if (zlast_wave) lzv += act ? (double)c.zo : 0.0;
             xo = act ? c.xo : xo;
             yo = c.yo;
             zo = c.zo;
@@ -467,17 +489,17 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 zbuf[t & 1][w][l] = zo;
                 __syncthreads();
             }
-        }
-        if (PIPE) {
-            const u64v hv = {(unsigned)(tb + PF), tag};
-            __builtin_amdgcn_raw_buffer_store_b64(hv, rh, hint_writer ? hoff_self : DCT_OOB, 0, 0);
+            if (PIPE && (u == PF - 1 || u == PF / 2 - 1)) {
+                const u64v hv = {(unsigned)(t + 1), tag};
+                __builtin_amdgcn_raw_buffer_store_b64(hv, rh, hint_writer ? hoff_self : DCT_OOB, 0, 0);
+            }
         }
     }
     if ((SYNC || PIPE) && spins >= DCT_SPIN_LIMIT && l == 0) atomicOr(a.err, 1);
     // boundary outflow sums of this block (for the particle balance): the last
     // x outflow of every row, and the y / z outflows of the boundary rows
     double lx = valid ? (double)xo : 0.0;
-    double ly = (valid && ylast) ? lyv : 0.0;
+    double ly = (valid && ylast) ? (double)lyv : 0.0;
     double lz = (valid && zlast) ? lzv : 0.0;
     for (int o = 32; o > 0; o >>= 1) {
         lx += __shfl_down(lx, o, 64);

@@ -522,12 +522,14 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(dbuf(ctx, "phi", (size_t)B * G * Nm * C * ts, &d_phi));
     // block-face buffers, two copies each (ping-pong by block parity)
     HC(dbuf(ctx, "yf", (size_t)2 * B * N * nx * nz * ts, &d_yf));
-    HC(dbuf(ctx, "zf", (size_t)2 * B * N * nx * ny * ts, &d_zf));
+    // z faces: per y block a diagonal strip of (nx + 63) x 64 elements
+    const size_t zstrip = (size_t)(nx + 63) * 64;
+    HC(dbuf(ctx, "zf", (size_t)2 * B * N * pl.NBJ * zstrip * ts, &d_zf));
     // faces handed over inside a pipelined launch: one slot per block boundary
     // (blocks of at least 2 z layers)
     void *d_yfp = nullptr, *d_zfp = nullptr;
     const size_t yfp_bytes = (size_t)B * N * pl.NBJ * nx * nz * ts;
-    const size_t zfp_bytes = (size_t)B * N * ((nz + 1) / 2) * nx * ny * ts;
+    const size_t zfp_bytes = (size_t)B * N * ((nz + 1) / 2) * pl.NBJ * zstrip * ts;
     void *d_hint = nullptr;
     {
         void *old_y = ctx->bufs["yfp"].p, *old_z = ctx->bufs["zfp"].p, *old_h = ctx->bufs["hint"].p;
