@@ -440,11 +440,15 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             // (issued after their last use so the new values need no copy)
             {
                 const int tp = t + PF;
-                const unsigned pp = (unsigned)pe;
-                qr[u] = bld<T>(rq, pp * TS);
-                sr[u] = bld<T>(rsg, pp * TS);
-                if (ADJ) fr[ADJ ? u : 0] = __builtin_amdgcn_raw_buffer_load_b8(rmask, pp, 0, 0);
                 const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
+                // idle lanes sit on their first or last row, away from the
+                // active ones: an out-of-range offset keeps their loads off
+                // the memory system (they return 0, never used)
+                const unsigned pp = inp ? (unsigned)pe : DCT_OOB;
+                const unsigned pb = inp ? (unsigned)pe * TS : DCT_OOB;
+                qr[u] = bld<T>(rq, pb);
+                sr[u] = bld<T>(rsg, pb);
+                if (ADJ) fr[ADJ ? u : 0] = __builtin_amdgcn_raw_buffer_load_b8(rmask, pp, 0, 0);
                 if (MULTI) {
                     // block faces of step t + FD (only the lanes that take a
                     // block face load one) into the slot consumed at that step
