@@ -84,6 +84,46 @@ __host__ __device__ inline void real_sh_cart(int L, R x, R y, R z, R *Y)
     }
 }
 
+// ---------------------------------------------------------------- buffer access
+// Raw buffer access through a descriptor (base, byte range): an offset at or
+// beyond the range makes a load return 0 and a store do nothing.  Idle lanes
+// pass DCT_OOB, so every lane issues the same memory instructions every step
+// and no memory access sits inside a branch (the compiler can then wait on
+// exactly the load a step consumes).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+#define DCT_OOB 0x80000000u
+__device__ inline rsrc_t mk_rsrc(const void *p, long bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, p ? (int)bytes : 0, 0x00020000);
+}
+template <typename T> __device__ inline T bld(rsrc_t r, unsigned off);
+template <> __device__ inline float bld<float>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ inline double bld<double>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline void bst(rsrc_t r, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ inline void bst(rsrc_t r, unsigned off, double v)
+{
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) u64v;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, off, 0, 0);
+}
+
+
+// Wait until this wave's own earlier memory operations (stores, atomics) have
+// completed.  The "last workgroup" counters below need only that: the counter
+// and the values it guards are all device atomics, performed in the order the
+// wave completes them, and everything else is read by later kernels, after the
+// kernel boundary.  (__threadfence() would also write back and invalidate the
+// whole L2 of the XCD, once per workgroup.)
+__device__ inline void wait_own_memory_ops() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // ---------------------------------------------------------------- device state
 // Per right-hand-side state of the device-driven group / iteration machine.
 struct RhsState {
@@ -144,7 +184,7 @@ struct TransArgs {
 
 struct CombArgs {
     Geo geo;
-    int G, L, Nm, B;
+    int G, L, Nm, B, M;
     const uint8_t *mat;
     const double *rho;
     const double *ss;

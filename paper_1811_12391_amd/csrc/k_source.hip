@@ -62,9 +62,12 @@ __device__ inline double block_max(double v, double *red)
     return t;
 }
 
-template <typename T>
+// LT: the P_N order as a compile-time constant, so that the harmonics of a
+// voxel's source direction stay in registers
+template <typename T, int LT>
 __global__ __launch_bounds__(256) void k_transition(TransArgs a)
 {
+    constexpr int NM = (LT + 1) * (LT + 1);
     __shared__ double red[8];
     const int b = blockIdx.y;
     RhsState *st = a.state + b;
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
     const long C = geo.C;
     const long v = (long)blockIdx.x * 256 + threadIdx.x;
     const bool inb = v < C;
-    const int G = a.G, L = a.L, Nm = a.Nm;
+    const int G = a.G, L = LT, Nm = NM;
     double Rp = 0.0, Pp = 0.0;
     T *phi_all = (T *)a.phi_all;
     if (inb) {
@@ -96,14 +99,15 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
             double d1 = geo.org[1] + (j + 0.5) * geo.dy - p[1];
             double d2 = geo.org[2] + (k + 0.5) * geo.dz - p[2];
             double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            double Y[DCT_MAXNM];
-            real_sh_cart<double>(L, d0 / r, d1 / r, d2 / r, Y);
+            double Y[NM];
+            real_sh_cart<double>(LT, d0 / r, d1 / r, d2 / r, Y);
             const long pA = cls_pos(0, i, j, k, geo.nx, geo.ny);
             const long pB = cls_pos(1, i, j, k, geo.nx, geo.ny);
             T *ext = (T *)a.ext + (long)b * Nm * C;
             T *QA = (T *)a.Qc + (long)b * Nm * C;
             T *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
-            for (int lm = 0; lm < Nm; ++lm) {
+#pragma unroll
+            for (int lm = 0; lm < NM; ++lm) {
                 const int l = l_of(lm);
                 const double *sl = a.ss + ((long)m * (L + 1) + l) * G * G;
                 double e = 0.0;
@@ -158,10 +162,10 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
                 atomicAdd(&a.bal[((long)b * G + g) * 3 + 0], a.inflow[g] * Pin);
             }
         }
-        __threadfence();
+        wait_own_memory_ops();
         unsigned prev = atomicAdd(&st->cnt_trans, 1u);
         if (prev == gridDim.x - 1) {
-            __threadfence();
+            wait_own_memory_ops();
             st->cnt_trans = 0;
             st->pending = 0;
             if (g >= G) {
@@ -179,14 +183,15 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
 // weights; then it builds the adjoint moment source of the next (higher)
 // group: the dose seed plus what every lower group took from it by
 // downscatter, and starts its iteration from lam = 0.
-template <typename T>
+template <typename T, int LT>
 __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
 {
+    constexpr int NM = (LT + 1) * (LT + 1);
     const int b = blockIdx.y;
     RhsState *st = a.state + b;
     if (!st->pending) return;
     const int gs = st->g;                          // position in the reversed group sequence
-    const int G = a.G, L = a.L, Nm = a.Nm, N = a.N;
+    const int G = a.G, L = LT, Nm = NM, N = a.N;
     const Geo &geo = a.geo;
     const long C = geo.C;
     const long v = (long)blockIdx.x * 256 + threadIdx.x;
@@ -201,8 +206,8 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
         double d1 = geo.org[1] + (j + 0.5) * geo.dy - p[1];
         double d2 = geo.org[2] + (k + 0.5) * geo.dz - p[2];
         double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        double Y[DCT_MAXNM];
-        real_sh_cart<double>(L, d0 / r, d1 / r, d2 / r, Y);
+        double Y[NM];
+        real_sh_cart<double>(LT, d0 / r, d1 / r, d2 / r, Y);
         const T *phi_all = (const T *)a.phi_all;
         T *lam_all = (T *)a.lam_all;
         if (gs > 0) {
@@ -218,7 +223,8 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
             }
             double drv = a.st[m * G + gp] * sbar;
             const T *lamg = lam_all + ((long)b * G + gp) * Nm * C;
-            for (int lm = 0; lm < Nm; ++lm) {
+#pragma unroll
+            for (int lm = 0; lm < NM; ++lm) {
                 const int l = l_of(lm);
                 const double *sl = a.ss + ((long)m * (L + 1) + l) * G * G;
                 const double lv = (double)lamg[(long)lm * C + v];
@@ -245,7 +251,8 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
             T *QA = (T *)a.Qc + (long)b * Nm * C;
             T *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
             const long pA = cls_pos(0, i, j, k, geo.nx, geo.ny), pB = cls_pos(1, i, j, k, geo.nx, geo.ny);
-            for (int lm = 0; lm < Nm; ++lm) {
+#pragma unroll
+            for (int lm = 0; lm < NM; ++lm) {
                 const int l = l_of(lm);
                 const double *sl = a.ss + ((long)m * (L + 1) + l) * G * G;
                 double e = lm == 0 ? a.roi[v] * a.kap[m * G + g] : 0.0;
@@ -263,10 +270,10 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        wait_own_memory_ops();
         unsigned prev = atomicAdd(&st->cnt_trans, 1u);
         if (prev == gridDim.x - 1) {
-            __threadfence();
+            wait_own_memory_ops();
             st->cnt_trans = 0;
             st->pending = 0;
             if (gs >= G) {
@@ -277,24 +284,37 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
     }
 }
 
+#define DCT_BY_ORDER(KER, T, L, ...)                                                        \
+    do {                                                                                     \
+        switch (L) {                                                                         \
+        case 0: hipLaunchKernelGGL((KER<T, 0>), __VA_ARGS__); break;                         \
+        case 1: hipLaunchKernelGGL((KER<T, 1>), __VA_ARGS__); break;                         \
+        case 2: hipLaunchKernelGGL((KER<T, 2>), __VA_ARGS__); break;                         \
+        case 3: hipLaunchKernelGGL((KER<T, 3>), __VA_ARGS__); break;                         \
+        case 4: hipLaunchKernelGGL((KER<T, 4>), __VA_ARGS__); break;                         \
+        default: hipLaunchKernelGGL((KER<T, 5>), __VA_ARGS__); break;                        \
+        }                                                                                    \
+    } while (0)
+
 hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t s)
 {
+    if (a.L < 0 || a.L > DCT_MAXL) return hipErrorInvalidValue;
     dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
-    if (is_f64) hipLaunchKernelGGL(k_adj_transition<double>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_adj_transition<float>, grid, dim3(256), 0, s, a);
+    if (is_f64) DCT_BY_ORDER(k_adj_transition, double, a.L, grid, dim3(256), 0, s, a);
+    else DCT_BY_ORDER(k_adj_transition, float, a.L, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s)
 {
     dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
-    if (is_f64) hipLaunchKernelGGL(k_transition<double>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_transition<float>, grid, dim3(256), 0, s, a);
+    if (a.L < 0 || a.L > DCT_MAXL) return hipErrorInvalidValue;
+    if (is_f64) DCT_BY_ORDER(k_transition, double, a.L, grid, dim3(256), 0, s, a);
+    else DCT_BY_ORDER(k_transition, float, a.L, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-// LDS tile of one slab (z layer k, 16 consecutive y rows, all x) with an odd
-// row pitch so that the 16 lanes of a row segment hit distinct banks.
+// LDS tile of one slab (z layer k, 16 consecutive y rows, all x).
 //
 // E > 0: every thread holds E tile elements (16 nx <= 256 E) and issues all of
 // its global loads (both class halves, the external source, the previous
@@ -312,15 +332,19 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     const int gseq = st->g;
     const int g = eff_group(gseq, a.G, a.reverse);
     const int nx = a.geo.nx, ny = a.geo.ny;
-    const unsigned nblocks_b = gridDim.x * gridDim.z;   // blocks of this RHS (slabs x moments)
     const long C = a.geo.C;
     const int G = a.G, Nm = a.Nm, L = a.L;
     const int nslj = (ny + 15) >> 4;
+    const int lm = blockIdx.z;
+    const int nslab = a.geo.nz * nslj;
+    const bool live = true;
     const int k = blockIdx.x / nslj;
     const int j0 = (blockIdx.x % nslj) * 16;
-    const int pitch = nx + 1;
+    // even pitch: row jl of the tile is read and written at i = r -+ jl, so
+    // the bank of element (jl, r -+ jl) is (pitch -+ 1) jl + r, distinct over
+    // the 16 rows when pitch -+ 1 are odd
+    const int pitch = (nx | 1) + 1;
     const int tile_n = 16 * nx;
-    const int lm = blockIdx.z;
     const int l = l_of(lm);
     const T *partA = (const T *)a.part + ((long)b * Nm + lm) * C;
     const T *partB = (const T *)a.part + (((long)a.B + b) * Nm + lm) * C;
@@ -331,25 +355,38 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     double dmax = 0.0, fmax_ = 0.0;
     if (E > 0) {
         constexpr int EE = E > 0 ? E : 1;
+        constexpr unsigned TS = sizeof(T);
+        // self-scatter moments of group g per material, for the next source
+        __shared__ double ssg[DCT_MAXMAT * (DCT_MAXL + 1)];
+        if ((int)threadIdx.x < a.M * (L + 1)) {
+            const int mm = threadIdx.x / (L + 1), ll = threadIdx.x - mm * (L + 1);
+            ssg[threadIdx.x] = a.ss[(((long)mm * (L + 1) + ll) * G + g) * G + g];
+        }
+        // every load is issued up front through descriptors; elements outside
+        // the tile use an out-of-range offset (no branch, no memory access)
+        const rsrc_t rA = mk_rsrc(partA, C * TS), rB = mk_rsrc(partB, C * TS);
+        const rsrc_t rE = mk_rsrc(ext, C * TS), rP = mk_rsrc(phib, C * TS);
+        const rsrc_t rM = mk_rsrc(a.mat, C), rR = mk_rsrc(a.rho, C * 8);
+        const rsrc_t rPo = mk_rsrc(phib + (long)lm * C, C * TS);
+        const rsrc_t rQA = mk_rsrc(QA, C * TS), rQB = mk_rsrc(QB, C * TS);
         T va[EE], vb[EE], ve[EE], vo[EE];
-        double sc[EE];
+        double rh[EE];
+        int mt[EE];
 #pragma unroll
         for (int e = 0; e < EE; ++e) {
             const int idx = threadIdx.x + 256 * e;
-            // rotated-row order (class halves)
             const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
             const bool okr = idx < tile_n && j < ny;
-            const long p = ((long)k * nx + (okr ? r : 0)) * ny + (okr ? j : 0);
-            va[e] = okr ? partA[p] : (T)0;
-            vb[e] = okr ? partB[p] : (T)0;
-            // natural order
+            const unsigned orot = okr ? (unsigned)(((long)k * nx + r) * ny + j) * TS : DCT_OOB;
+            va[e] = bld<T>(rA, orot);
+            vb[e] = bld<T>(rB, orot);
             const int jn = idx / nx, in = idx - jn * nx, jj = j0 + jn;
             const bool okn = idx < tile_n && jj < ny;
-            const long v = okn ? in + (long)nx * (jj + (long)ny * k) : 0;
-            ve[e] = okn ? ext[v] : (T)0;
-            vo[e] = (okn && lm == 0) ? phib[v] : (T)0;
-            const int m = okn ? a.mat[v] : 0;
-            sc[e] = okn ? a.rho[v] * a.ss[(((long)m * (L + 1) + l) * G + g) * G + g] : 0.0;
+            const unsigned v = okn ? (unsigned)(in + (long)nx * (jj + (long)ny * k)) : 0u;
+            ve[e] = bld<T>(rE, okn ? v * TS : DCT_OOB);
+            vo[e] = bld<T>(rP, (okn && lm == 0) ? v * TS : DCT_OOB);
+            mt[e] = __builtin_amdgcn_raw_buffer_load_b8(rM, okn ? v : DCT_OOB, 0, 0);
+            rh[e] = bld<double>(rR, okn ? v * 8 : DCT_OOB);
         }
 #pragma unroll
         for (int e = 0; e < EE; ++e) {
@@ -369,30 +406,31 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
         for (int e = 0; e < EE; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int jn = idx / nx, in = idx - jn * nx, jj = j0 + jn;
-            if (idx < tile_n && jj < ny) {
-                const long v = in + (long)nx * (jj + (long)ny * k);
-                const T pn = tile[jn * pitch + in];
-                if (lm == 0) {
-                    const double dn = fabs((double)pn - (double)vo[e]);
-                    const double an = fabs((double)pn);
-                    dmax = (dn > dmax || dn != dn) ? dn : dmax;
-                    fmax_ = (an > fmax_ || an != an) ? an : fmax_;
-                }
-                phib[(long)lm * C + v] = pn;
-                tile[jn * pitch + in] = (T)((double)ve[e] + sc[e] * (double)pn);
+            const bool okn = idx < tile_n && jj < ny;
+            const unsigned v = okn ? (unsigned)(in + (long)nx * (jj + (long)ny * k)) : 0u;
+            const int ti = okn ? jn * pitch + in : 0;
+            const T pn = tile[ti];
+            if (lm == 0 && okn) {
+                const double dn = fabs((double)pn - (double)vo[e]);
+                const double an = fabs((double)pn);
+                dmax = (dn > dmax || dn != dn) ? dn : dmax;
+                fmax_ = (an > fmax_ || an != an) ? an : fmax_;
             }
+            bst(rPo, okn ? v * TS : DCT_OOB, pn);
+            const double sc = rh[e] * ssg[mt[e] * (L + 1) + l];
+            if (okn) tile[ti] = (T)((double)ve[e] + sc * (double)pn);
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < EE; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
-            if (idx < tile_n && j < ny) {
-                const int jm = j % nx;
-                const long p = ((long)k * nx + r) * ny + j;
-                QA[p] = tile[jl * pitch + rot_row(1, r, jm, nx)];
-                QB[p] = tile[jl * pitch + rot_row(0, r, jm, nx)];
-            }
+            const bool okr = idx < tile_n && j < ny;
+            const int jm = okr ? j % nx : 0;
+            const unsigned orot = okr ? (unsigned)(((long)k * nx + r) * ny + j) * TS : DCT_OOB;
+            const int rr = okr ? r : 0, jr = okr ? jl : 0;
+            bst(rQA, orot, tile[jr * pitch + rot_row(1, rr, jm, nx)]);
+            bst(rQB, orot, tile[jr * pitch + rot_row(0, rr, jm, nx)]);
         }
         __syncthreads();
     } else {
@@ -446,17 +484,21 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
         }
         __syncthreads();
     }
-    double dm = block_max(dmax, red);
-    double fm = block_max(fmax_, red);
+    const unsigned nblocks_b = (unsigned)(nslab * Nm);   // live blocks of this RHS (slabs x moments)
+    double dm = 0.0, fm = 0.0;
+    if (lm == 0) {
+        dm = block_max(dmax, red);
+        fm = block_max(fmax_, red);
+    }
     if (threadIdx.x == 0) {
-        if (blockIdx.z == 0) {
+        if (lm == 0 && live) {
             atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
             atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
         }
-        __threadfence();
-        unsigned prev = atomicAdd(&st->cnt_combine, 1u);
-        if (prev == nblocks_b - 1) {
-            __threadfence();
+        wait_own_memory_ops();
+        unsigned prev = live ? atomicAdd(&st->cnt_combine, 1u) : 0u;
+        if (live && prev == nblocks_b - 1) {
+            wait_own_memory_ops();
             double num = __longlong_as_double((long long)atomicAdd(&st->eps_num, 0ull));
             double den = __longlong_as_double((long long)atomicAdd(&st->eps_den, 0ull));
             int it = st->it + 1;
@@ -491,7 +533,7 @@ hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s)
 {
     const int nslj = (a.geo.ny + 15) >> 4;
     dim3 grid((unsigned)(a.geo.nz * nslj), a.B, a.Nm);
-    size_t shm = (size_t)16 * (a.geo.nx + 1) * (is_f64 ? 8 : 4);
+    size_t shm = (size_t)16 * ((a.geo.nx | 1) + 1) * (is_f64 ? 8 : 4);
     const int per = (16 * a.geo.nx + 255) / 256;   // tile elements per thread
 #define DCT_LAUNCH_COMBINE(T)                                                                          do {                                                                                                   if (per <= 1) hipLaunchKernelGGL((k_combine<T, 1>), grid, dim3(256), shm, s, a);                  else if (per <= 2) hipLaunchKernelGGL((k_combine<T, 2>), grid, dim3(256), shm, s, a);             else if (per <= 4) hipLaunchKernelGGL((k_combine<T, 4>), grid, dim3(256), shm, s, a);             else if (per <= 8) hipLaunchKernelGGL((k_combine<T, 8>), grid, dim3(256), shm, s, a);             else hipLaunchKernelGGL((k_combine<T, 0>), grid, dim3(256), shm, s, a);                       } while (0)
     if (is_f64) DCT_LAUNCH_COMBINE(double);

@@ -99,36 +99,6 @@ __device__ inline void lds_st(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC
 
 #define DCT_SPIN_LIMIT (1 << 20)
 
-// Raw buffer access through a descriptor (base, byte range): an offset at or
-// beyond the range makes a load return 0 and a store do nothing.  Idle lanes
-// pass DCT_OOB, so every lane issues the same memory instructions every step
-// and no memory access sits inside a branch (the compiler can then wait on
-// exactly the load a step consumes).
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-#define DCT_OOB 0x80000000u
-__device__ inline rsrc_t mk_rsrc(const void *p, long bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, p ? (int)bytes : 0, 0x00020000);
-}
-template <typename T> __device__ inline T bld(rsrc_t r, unsigned off);
-template <> __device__ inline float bld<float>(rsrc_t r, unsigned off)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-template <> __device__ inline double bld<double>(rsrc_t r, unsigned off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ inline void bst(rsrc_t r, unsigned off, float v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
-}
-__device__ inline void bst(rsrc_t r, unsigned off, double v)
-{
-    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) u64v;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, off, 0, 0);
-}
-
 // Device-coherent loads (sc1: served by L2, never by the CU's L1), used for
 // block faces handed between workgroups inside one launch.
 template <typename T> __device__ inline T bld_dev(rsrc_t r, unsigned off);

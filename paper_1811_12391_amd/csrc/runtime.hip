@@ -413,8 +413,8 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
     pl.Nm = Nm;
     pl.prec = o.precision;
     pl.tsz = o.precision == DCT_FP64 ? 8 : 4;
-    if ((size_t)16 * (ctx->nx + 1) * pl.tsz > 65536)
-        return fail(ctx, DCT_EINVAL, "solve: nx too large for the 64 KiB combine tile (nx <= 511 in FP64, 1023 in FP32)");
+    if ((size_t)16 * ((ctx->nx | 1) + 1) * pl.tsz > 65536)
+        return fail(ctx, DCT_EINVAL, "solve: nx too large for the 64 KiB combine tile (nx <= 510 in FP64, 1022 in FP32)");
     // moment maps and the check that the quadrature integrates them: D M = I
     std::vector<double> Y((size_t)N * Nm);
     for (int n = 0; n < N; ++n)
@@ -761,6 +761,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     cb.L = L;
     cb.Nm = Nm;
     cb.B = B;
+    cb.M = M;
     cb.mat = (const uint8_t *)d_mat;
     cb.rho = (const double *)d_rho;
     cb.ss = (const double *)d_ss;
@@ -1330,6 +1331,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     cb.L = L;
     cb.Nm = Nm;
     cb.B = B;
+    cb.M = M;
     cb.mat = (const uint8_t *)B_("mat");
     cb.rho = (const double *)B_("rho");
     cb.ss = (const double *)B_("ss");
