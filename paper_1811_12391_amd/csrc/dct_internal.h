@@ -171,6 +171,7 @@ struct TransArgs {
     const double *phi_u;      // [B][G][C]
     const double *ext_iso;    // [G][C] or null
     const double *inflow;     // [G] or null
+    const int *band_lo;       // [G] lowest group that scatters into g in any material (or null)
     const double *dirs, *w;   // [N][3], [N]
     const double *leak_part;  // [B][N][nblk][3]
     int nblk;

@@ -106,28 +106,39 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
             T *ext = (T *)a.ext + (long)b * Nm * C;
             T *QA = (T *)a.Qc + (long)b * Nm * C;
             T *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
+            // every moment accumulates in the same order as before: first-
+            // collision terms g' = 0..g, the volume source, then downscatter
+            // g' = 0..g-1; each phi_u value is read once for all moments
+            double e[NM];
+#pragma unroll
+            for (int lm = 0; lm < NM; ++lm) e[lm] = 0.0;
+            // groups g' < band_lo[g] scatter into g in no material: they are
+            // skipped; inside the band every term is added (a zero transfer
+            // moment adds an exact zero), so the loads carry no branch
+            const double *sm = a.ss + (long)m * (L + 1) * G * G;
+            const int g0 = a.band_lo ? a.band_lo[g] : 0;
+            for (int gp = g0; gp <= g; ++gp) {
+                const double pu = rho * a.phi_u[((long)b * G + gp) * C + v];
+#pragma unroll
+                for (int lm = 0; lm < NM; ++lm) e[lm] += sm[((long)l_of(lm) * G + gp) * G + g] * pu * Y[lm];
+            }
+            if (a.ext_iso) e[0] += a.ext_iso[(long)g * C + v];
+            for (int gp = g0; gp < g; ++gp) {
+                const T *pa = phi_all + ((long)b * G + gp) * Nm * C + v;
+                T f[NM];
+#pragma unroll
+                for (int lm = 0; lm < NM; ++lm) f[lm] = pa[(long)lm * C];
+#pragma unroll
+                for (int lm = 0; lm < NM; ++lm) e[lm] += rho * sm[((long)l_of(lm) * G + gp) * G + g] * (double)f[lm];
+            }
 #pragma unroll
             for (int lm = 0; lm < NM; ++lm) {
-                const int l = l_of(lm);
-                const double *sl = a.ss + ((long)m * (L + 1) + l) * G * G;
-                double e = 0.0;
-                // first-collision source, groups g' <= g in order
-                for (int gp = 0; gp <= g; ++gp) {
-                    double s = sl[gp * G + g];
-                    if (s != 0.0) e += rho * s * a.phi_u[((long)b * G + gp) * C + v] * Y[lm];
-                }
-                if (lm == 0 && a.ext_iso) e += a.ext_iso[(long)g * C + v];
-                // downscatter from converged higher-energy groups, in order
-                for (int gp = 0; gp < g; ++gp) {
-                    double s = sl[gp * G + g];
-                    if (s != 0.0) e += rho * s * (double)phi_all[(((long)b * G + gp) * Nm + lm) * C + v];
-                }
-                T et = (T)e;
+                T et = (T)e[lm];
                 ext[(long)lm * C + v] = et;
                 phi_all[(((long)b * G + g) * Nm + lm) * C + v] = (T)0;
                 QA[(long)lm * C + pA] = et;
                 QB[(long)lm * C + pB] = et;
-                if (lm == 0) Pp = e;
+                if (lm == 0) Pp = e[0];
             }
         }
     }

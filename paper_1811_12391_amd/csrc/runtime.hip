@@ -503,6 +503,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(dbuf(ctx, "dirs", ctx->dirs.size() * 8, &d_dirs));
     HC(dbuf(ctx, "w", ctx->w.size() * 8, &d_w));
     HC(dbuf(ctx, "cdir", pl.cdir.size() * 4, &d_cdir));
+    void *d_band;
+    HC(dbuf(ctx, "band", (size_t)G * 4, &d_band));
     const size_t tabsz = (size_t)2 * pl.NcP * pl.NmP * (mode == 2 ? 2 : ts);
     HC(dbuf(ctx, "Mt", tabsz, &d_Mt));
     HC(dbuf(ctx, "Dt", tabsz, &d_Dt));
@@ -553,6 +555,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // ---------------- inputs: uploaded once, kept on the device until a set_* call
     if (ctx->dev_dirty || ctx->tab_prec != o.precision) {
         std::vector<unsigned char> Mt(tabsz, 0), Dt(tabsz, 0);
+        std::vector<int> band;   // host copy alive until the synchronisation below
         std::vector<double> Y(Nm);
         for (int c = 0; c < 2; ++c)
             for (int nl = 0; nl < pl.Nc[c]; ++nl) {
@@ -591,6 +594,20 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
             HC(hipMemcpyAsync(d_dirs, ctx->dirs.data(), ctx->dirs.size() * 8, hipMemcpyHostToDevice, s));
             HC(hipMemcpyAsync(d_w, ctx->w.data(), ctx->w.size() * 8, hipMemcpyHostToDevice, s));
             HC(hipMemcpyAsync(d_cdir, pl.cdir.data(), pl.cdir.size() * 4, hipMemcpyHostToDevice, s));
+            // lowest group that scatters into each group in some material and order
+            band.assign(G, 0);
+            for (int g = 0; g < G; ++g) {
+                int lo = g;
+                for (int gp = 0; gp < g && lo == g; ++gp)
+                    for (int m = 0; m < M && lo == g; ++m)
+                        for (int l = 0; l <= L; ++l)
+                            if (ctx->ss[(((size_t)m * (L + 1) + l) * G + gp) * G + g] != 0.0) {
+                                lo = gp;
+                                break;
+                            }
+                band[g] = lo;
+            }
+            HC(hipMemcpyAsync(d_band, band.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
             if (d_iso) HC(hipMemcpyAsync(d_iso, ctx->iso.data(), ctx->iso.size() * 8, hipMemcpyHostToDevice, s));
         }
         HC(hipStreamSynchronize(s));   // host tables must outlive the copies
@@ -684,6 +701,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     tr.phi_u = (const double *)d_phiu;
     tr.ext_iso = (const double *)d_iso;
     tr.inflow = (const double *)d_infl;
+    tr.band_lo = (const int *)d_band;
     tr.dirs = (const double *)d_dirs;
     tr.w = (const double *)d_w;
     tr.leak_part = (const double *)d_leak;
