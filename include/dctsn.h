@@ -76,7 +76,7 @@ typedef struct dct_opts {
                                  the fastest for this problem shape in the context */
     int sweep_bk;             /* z layers per sweep workgroup, 1..16 (0 = tuned or min(16, nz)) */
     int sweep_sync;           /* wave coupling: 1 = LDS progress counters between the waves of
-                                 a workgroup, 2 = one barrier per step, 3 = as 1 with all
+                                 a workgroup, 2 = one barrier per step, 3 = as 2 with all
                                  blocks of a sweep in one launch, handing block faces over
                                  as they are produced (needs >= 2 blocks of >= 2 z layers,
                                  otherwise runs as 1); 0 = tuned or 1 */

@@ -24,29 +24,27 @@
 
 namespace dct {
 
-// q / d for d > 0 (d >= sum of the face coefficients, never tiny): hardware
-// reciprocal refined by Newton-Raphson, then one residual correction of the
-// quotient (Markstein); FP64 keeps full precision, FP32 is within an ulp.
-__device__ inline double qdiv(double n, double d)
+// q / d for d > 0 (a normal number): hardware reciprocal refined by
+// Newton-Raphson (rcp_nr), then one residual correction of the quotient
+// (Markstein, qdiv_y); FP64 keeps full precision, FP32 is within an ulp.
+__device__ inline double rcp_nr(double d)
 {
     double y = __builtin_amdgcn_rcp(d);
     double e = fma(-d, y, 1.0);
     y = fma(y, e, y);
     e = fma(-d, y, 1.0);
-    y = fma(y, e, y);
-    double q = n * y;
-    double r = fma(-d, q, n);
+    return fma(y, e, y);
+}
+__device__ inline float rcp_nr(float d) { return __builtin_amdgcn_rcpf(d); }
+template <typename T> __device__ inline T qdiv_y(T n, T d, T y)
+{
+    T q = n * y;
+    T r = fma(-d, q, n);
     return fma(y, r, q);
 }
-__device__ inline float qdiv(float n, float d)
-{
-    float y = __builtin_amdgcn_rcpf(d);
-    float q = n * y;
-    float r = fmaf(-d, q, n);
-    return fmaf(y, r, q);
-}
+template <typename T> __device__ inline T qdiv(T n, T d) { return qdiv_y(n, d, rcp_nr(d)); }
 
-// Set-to-zero fixup of one cell (rare path): faces with a negative outflow are
+// Set-to-zero fixup of one cell: faces with a negative outflow are
 // closed (outflow 0, inflow weighted c_a / 2 in the balance) until no new
 // negative face appears.  Returns (psi_c, out_x, out_y, out_z) by value.
 template <typename T> struct Cell4 { T pc, xo, yo, zo; int fixed; };
@@ -66,7 +64,7 @@ __device__ __forceinline__ Cell4<T> dd_fixup(T qv, T sv, T cx, T cy, T cz, T xin
         if (fx) n2 += (T)0.5 * cx * xin; else { n2 += cx * xin; d2 += cx; }
         if (fy) n2 += (T)0.5 * cy * yin; else { n2 += cy * yin; d2 += cy; }
         if (fz) n2 += (T)0.5 * cz * zin; else { n2 += cz * zin; d2 += cz; }
-        c.pc = n2 / d2;
+        c.pc = qdiv(n2, d2);
         c.xo = fx ? (T)0 : c.pc + c.pc - xin;
         c.yo = fy ? (T)0 : c.pc + c.pc - yin;
         c.zo = fz ? (T)0 : c.pc + c.pc - zin;
@@ -149,7 +147,8 @@ __device__ inline bool is_empty(double v) { return __builtin_bit_cast(unsigned l
 // value, the consumer waits (bounded) until the element is no longer the
 // empty marker, uses it and stores the marker back, so every face buffer is
 // empty again when the launch ends.  Consumers never block producers, so the
-// blocks form a pipeline along the sweep diagonal.
+// blocks form a pipeline along the sweep diagonal.  Inside a workgroup the
+// waves of a pipelined block keep one barrier per step (SYNC = 0).
 //
 // MODE 0: forward sweep; 1: forward sweep that also records the fixup set of
 // every cell (kept for the adjoint); 2: the transposed sweep of the frozen-fixup
@@ -164,9 +163,12 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     constexpr bool ADJ = MODE == 2, KEEP = MODE == 1;
     constexpr int ZR = 4;                                   // z-face ring depth (SYNC = 1)
-    constexpr int FD = PIPE ? 2 : PF;                       // prefetch distance of block faces
+    constexpr int FD = PF;                                  // prefetch distance of block faces (as q, sigma)
     constexpr unsigned TS = sizeof(T);
-    __shared__ T zbuf[SYNC ? 16 : 2][SYNC ? ZR : 16][64];
+    // SYNC = 0 without block faces: row w + 1 holds wave w's z outflow and
+    // row 0 the boundary value, so every wave reads its z inflow from LDS
+    constexpr bool ZROW = !SYNC && !MULTI;
+    __shared__ T zbuf[SYNC ? 16 : 2][SYNC ? ZR : (ZROW ? 17 : 16)][64];
     __shared__ int prog[16];
     __shared__ double red[3][16];
     const long nitems = (long)a.B * a.N;
@@ -263,10 +265,16 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         if (threadIdx.x < 16) prog[threadIdx.x] = 0;
         __syncthreads();
     }
+    if (ZROW) {
+        if (w == 0) zbuf[0][0][l] = zbuf[1][0][l] = bc;
+        __syncthreads();
+    }
 
     // The loop starts PF steps early: those steps only issue the first
     // prefetches (every lane is idle), so the loop is entered with no load in
     // flight and the wait counts inside it are those of the steady state.
+    // Step t loads the operands of step t + PF - 1 into the ring slot that
+    // step t - 1 has just consumed.
     T qr[PF], sr[PF], yr[MULTI ? PF : 1], zr[MULTI ? PF : 1];
     int fr[ADJ ? PF : 1];
 #pragma unroll
@@ -275,11 +283,26 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         if (MULTI) yr[MULTI ? u : 0] = zr[MULTI ? u : 0] = (T)0;
         if (ADJ) fr[ADJ ? u : 0] = 0;
     }
-    // element offsets of the prefetch and the current cell: one rotated row
-    // (ny elements) per x step, wrapping inside the (k, rotated row) plane
+    // Element offsets: one rotated row (ny elements) per x step, wrapping
+    // inside the (k, rotated row) plane.  Lane l reaches x index t - l - w at
+    // step t and the rotation adds (or subtracts) its row j = j0 +- l, so the
+    // rotated row of step t is the same for every lane of a wave: the row
+    // part of the offset is a wave-uniform scalar (sre, for the prefetched
+    // step), the lane part a constant (rowbase).  The offsets a prefetch used
+    // are kept and reused by the stores of that step PF - 1 steps later.
     const int dny = sx ? ny : -ny;
-    const int wrap_at_e = rowbase + wrap_at * ny, wrap_to_e = rowbase + wrap_to * ny;
-    int pe = rowbase + rstart * ny, ce = pe;
+    const int wrap_at_r = wrap_at * ny, wrap_to_r = wrap_to * ny;
+    int sre = __builtin_amdgcn_readfirstlane((((rstart - dr * (t0l + 1)) % nx) + nx) % nx) * ny;   // step -1
+    const unsigned lane_b = (unsigned)rowbase * TS;
+    unsigned sbr[PF], ser[KEEP ? PF : 1];
+    bool actr[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        sbr[u] = DCT_OOB;
+        if (KEEP) ser[KEEP ? u : 0] = DCT_OOB;
+        actr[u] = false;
+    }
+    T ycar = bc;                                            // lane 0 keeps the boundary value
     T xo = bc, yo = 0, zo = 0;                              // x inflow of a row starts at the boundary value
     // leakage: the y outflow of a lane is summed in T (at most nx terms per
     // lane) and widened at the end; only the wave on the z boundary sums z
@@ -291,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     u64v hz = {0u, 0u}, hy = {0u, 0u};
     for (int tb = -PF; tb < NTp; tb += PF) {
         if (PIPE && (bj > 0 || bk > 0)) {
-            // this group of steps loads faces up to step tb + PF - 1 + FD; the
+            // this group of steps loads faces up to step tb + PF + FD - 2; the
             // face of step s is written by upstream step s + BK - 1 (z) or
             // s + 63 (y); an upstream block never reports more than its own
             // padded step count
@@ -314,6 +337,11 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         }
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
+            // Step order: the z inflow is requested first; the prefetch of a
+            // later step and everything that does not depend on the z inflow
+            // follow while it is in flight; a scheduling fence then keeps the
+            // short chain that does (cell update, fixup, z handoff) free of
+            // unrelated instructions, since a wave issues in program order.
             const int t = tb + u;
             const T qv = qr[u], sv = sr[u];
             const int fv = ADJ ? fr[ADJ ? u : 0] : 0;
@@ -323,7 +351,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 zface_in = (kp == 0) ? bc : zr[MULTI ? u : 0];
             }
             const int ip = t - t0l;
-            const bool act = valid && (unsigned)ip < (unsigned)nx;
+            const bool act = actr[u];                       // valid && 0 <= ip < nx
             if (PIPE) {
                 // a prefetched face element that was still empty is polled
                 // again (rare once the consumer trails its producer)
@@ -345,9 +373,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 bst_dev(ryi, (act && yreader) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, face_empty<T>());
                 bst_dev(rzi, (act && zreader) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, face_empty<T>());
             }
-            // y inflow: lane l-1's outflow of the previous step; lane 0 takes the
-            // boundary / block face value through the DPP "old" operand
-            const T yin = dpp_shift_up_or<T>(yo, yface_in);
+            // z inflow: wave w-1's outflow of the previous step
             T zin;
             if (SYNC) {
                 if (w > 0) {
@@ -365,69 +391,38 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 } else {
                     zin = zface_in;
                 }
+            } else if (ZROW) {
+                zin = zbuf[(t + 1) & 1][w][l];
             } else {
                 zin = (w > 0) ? zbuf[(t + 1) & 1][w > 0 ? w - 1 : 0][l] : zface_in;
             }
-            const T xin = xo;
-            Cell4<T> c;
-            if (ADJ) {
-                const bool ux = !(fv & 1), uy = !(fv & 2), uz = !(fv & 4);
-                const T ex = ux ? cx : (T)0, ey = uy ? cy : (T)0, ez = uz ? cz : (T)0;
-                const T num = qv + ex * xin + ey * yin + ez * zin;
-                c.pc = qdiv(num, sv + ex + ey + ez);
-                c.xo = ux ? c.pc + c.pc - xin : c.pc;
-                c.yo = uy ? c.pc + c.pc - yin : c.pc;
-                c.zo = uz ? c.pc + c.pc - zin : c.pc;
-                c.fixed = 0;
-            } else {
-                const T num = qv + cx * xin + cy * yin + cz * zin;
-                c.pc = qdiv(num, sv + csum);
-                c.xo = c.pc + c.pc - xin;
-                c.yo = c.pc + c.pc - yin;
-                c.zo = c.pc + c.pc - zin;
-                c.fixed = 0;
-                if (fixup && act && __builtin_expect(fmin(c.xo, fmin(c.yo, c.zo)) < (T)0, 0))
-                    c = dd_fixup<T>(qv, sv, cx, cy, cz, xin, yin, zin, c);
-            }
-            const unsigned po = act ? (unsigned)ce : DCT_OOB;
-            bst(rpsi, act ? po * TS : DCT_OOB, c.pc);
-            if (KEEP) __builtin_amdgcn_raw_buffer_store_b8((unsigned char)c.fixed, rmask, po, 0, 0);
-            if (MULTI) {
-                if (PIPE) {
-                    bst_dev(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
-                    bst_dev(rzo, (zwriter && act) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, c.zo);
-                } else {
-                    bst(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
-                    bst(rzo, (zwriter && act) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, c.zo);
-                }
-            }
+            __builtin_amdgcn_sched_barrier(0);
+            // prefetch step t + PF - 1 into the slot that step t - 1 consumed
             {
-                int cn = ce + dny;
-                cn = cn == wrap_at_e ? wrap_to_e : cn;
-                ce = act ? cn : ce;
-            }
-            // prefetch step t + PF into the slots this step has just consumed
-            // (issued after their last use so the new values need no copy)
-            {
-                const int tp = t + PF;
+                const int tp = t + PF - 1;
+                const int ps = (u + PF - 1) % PF;           // constant once the step loop is unrolled
                 const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
                 // idle lanes sit on their first or last row, away from the
                 // active ones: an out-of-range offset keeps their loads off
                 // the memory system (they return 0, never used)
-                const unsigned pp = inp ? (unsigned)pe : DCT_OOB;
-                const unsigned pb = inp ? (unsigned)pe * TS : DCT_OOB;
-                qr[u] = bld<T>(rq, pb);
-                sr[u] = bld<T>(rsg, pb);
-                if (ADJ) fr[ADJ ? u : 0] = __builtin_amdgcn_raw_buffer_load_b8(rmask, pp, 0, 0);
+                const unsigned pp = inp ? (unsigned)(rowbase + sre) : DCT_OOB;
+                const unsigned pb = inp ? lane_b + (unsigned)sre * TS : DCT_OOB;
+                sbr[ps] = pb;
+                actr[ps] = inp;
+                if (KEEP) ser[KEEP ? ps : 0] = pp;
+                qr[ps] = bld<T>(rq, pb);
+                sr[ps] = bld<T>(rsg, pb);
+                if (ADJ) fr[ADJ ? ps : 0] = __builtin_amdgcn_raw_buffer_load_b8(rmask, pp, 0, 0);
                 if (MULTI) {
-                    // block faces of step t + FD (only the lanes that take a
-                    // block face load one) into the slot consumed at that step
-                    const int tf = t + FD;
+                    // block faces of step t + FD - 1 (only the lanes that take
+                    // a block face load one) into the slot consumed at that
+                    // step PF steps earlier
+                    const int tf = t + FD - 1;
                     const bool inf = valid && (unsigned)(tf - t0l) < (unsigned)nx;
                     const int ipn = tf - t0l;
                     const unsigned yo_off = (inf && ytaker) ? (unsigned)(ipn + nx * kp) * TS : DCT_OOB;
                     const unsigned zo_off = (inf && ztaker) ? (unsigned)((ipn + l) * 64 + l) * TS : DCT_OOB;
-                    const int fs = (u + FD) % PF;   // constant once the step loop is unrolled
+                    const int fs = (u + FD - 1) % PF;
                     if (PIPE) {
                         yr[MULTI ? fs : 0] = bld_dev<T>(ryi, yo_off);
                         zr[MULTI ? fs : 0] = bld_dev<T>(rzi, zo_off);
@@ -436,15 +431,52 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                         zr[MULTI ? fs : 0] = bld<T>(rzi, zo_off);
                     }
                 }
-                int pn = pe + dny;
-                pn = pn == wrap_at_e ? wrap_to_e : pn;
-                pe = inp ? pn : pe;
+                sre += dny;
+                sre = sre == wrap_at_r ? wrap_to_r : sre;
             }
-            lyv += act ? c.yo : (T)0;
-            if (zlast_wave) lzv += act ? (double)c.zo : 0.0;
-            xo = act ? c.xo : xo;
-            yo = c.yo;
-            zo = c.zo;
+            // y inflow: lane l-1's outflow of the previous step; lane 0 takes the
+            // boundary / block face value through the DPP "old" operand
+            T yin;
+            if (MULTI) {
+                yin = dpp_shift_up_or<T>(yo, yface_in);
+            } else {
+                ycar = dpp_shift_up_or<T>(yo, ycar);
+                yin = ycar;
+            }
+            const T xin = xo;
+            // Everything except the z term: psi_c = a + b zin with
+            // a = (q + cx xin + cy yin) / d and b = cz / d (the reciprocal of
+            // d refined once, so the quotient is within a few ulp).
+            T a0, b0;
+            if (ADJ) {
+                const bool ux = !(fv & 1), uy = !(fv & 2), uz = !(fv & 4);
+                const T ex = ux ? cx : (T)0, ey = uy ? cy : (T)0, ez = uz ? cz : (T)0;
+                const T y0 = rcp_nr(sv + ex + ey + ez);
+                a0 = (qv + ex * xin + ey * yin) * y0;
+                b0 = ez * y0;
+            } else {
+                const T y0 = rcp_nr(sv + csum);
+                a0 = (qv + cx * xin + cy * yin) * y0;
+                b0 = cz * y0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            Cell4<T> c;
+            c.pc = fma(b0, zin, a0);
+            if (ADJ) {
+                const bool ux = !(fv & 1), uy = !(fv & 2), uz = !(fv & 4);
+                c.xo = ux ? c.pc + c.pc - xin : c.pc;
+                c.yo = uy ? c.pc + c.pc - yin : c.pc;
+                c.zo = uz ? c.pc + c.pc - zin : c.pc;
+                c.fixed = 0;
+            } else {
+                c.xo = c.pc + c.pc - xin;
+                c.yo = c.pc + c.pc - yin;
+                c.zo = c.pc + c.pc - zin;
+                c.fixed = 0;
+                if (fixup && act && fmin(c.xo, fmin(c.yo, c.zo)) < (T)0)
+                    c = dd_fixup<T>(qv, sv, cx, cy, cz, xin, yin, zin, c);
+            }
+            // z handoff first (the next step of wave w+1 waits on it)
             if (SYNC) {
                 if (w + 1 < nwv) {
                     const int need = t - ZR + 2;                // successor must have read slot t - ZR
@@ -456,13 +488,30 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                         }
                     }
                 }
-                zbuf[w][t & (ZR - 1)][l] = zo;
+                zbuf[w][t & (ZR - 1)][l] = c.zo;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
                 if (l == 0) lds_st(&prog[w], t + 1);
             } else {
-                zbuf[t & 1][w][l] = zo;
-                __syncthreads();
+                zbuf[t & 1][ZROW ? w + 1 : w][l] = c.zo;
             }
+            __builtin_amdgcn_sched_barrier(0);
+            bst(rpsi, sbr[u], c.pc);
+            if (KEEP) __builtin_amdgcn_raw_buffer_store_b8((unsigned char)c.fixed, rmask, ser[KEEP ? u : 0], 0, 0);
+            if (MULTI) {
+                if (PIPE) {
+                    bst_dev(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
+                    bst_dev(rzo, (zwriter && act) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, c.zo);
+                } else {
+                    bst(ryo, (ywriter && act) ? (unsigned)(ip + nx * kp) * TS : DCT_OOB, c.yo);
+                    bst(rzo, (zwriter && act) ? (unsigned)((ip + l) * 64 + l) * TS : DCT_OOB, c.zo);
+                }
+            }
+            lyv += act ? c.yo : (T)0;
+            if (zlast_wave) lzv += act ? (double)c.zo : 0.0;
+            xo = act ? c.xo : xo;
+            yo = c.yo;
+            zo = c.zo;
+            if (!SYNC) __syncthreads();
             if (PIPE && (u == PF - 1 || u == PF / 2 - 1)) {
                 const u64v hv = {(unsigned)(t + 1), tag};
                 __builtin_amdgcn_raw_buffer_store_b64(hv, rh, hint_writer ? hoff_self : DCT_OOB, 0, 0);
@@ -519,8 +568,9 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
 #define DCT_LAUNCH_SWEEP_S(T, PF, M) \
     do { if (a.sync) DCT_LAUNCH_SWEEP_M(T, PF, M, 1, false); else DCT_LAUNCH_SWEEP_M(T, PF, M, 0, false); } while (0)
     if (pipe) {
-        if (is_f64) DCT_LAUNCH_SWEEP_M(double, 4, true, 1, true);
-        else DCT_LAUNCH_SWEEP_M(float, 8, true, 1, true);
+        // pipelined blocks keep one barrier per step inside the workgroup
+        if (is_f64) DCT_LAUNCH_SWEEP_M(double, 4, true, 0, true);
+        else DCT_LAUNCH_SWEEP_M(float, 8, true, 0, true);
     } else if (is_f64) {
         if (multi) DCT_LAUNCH_SWEEP_S(double, 4, true); else DCT_LAUNCH_SWEEP_S(double, 8, false);
     } else {

@@ -815,7 +815,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // ---------------- sweep schedule: given, cached, or timed now
     // schedule = (z layers per workgroup, coupling): coupling 1 = LDS progress
     // counters between the waves of a workgroup, 2 = one barrier per step,
-    // 3 = as 1 with every block of a sweep in one launch (pipelined blocks)
+    // 3 = as 2 with every block of a sweep in one launch (pipelined blocks)
     double tune_ms = 0.0;
     auto set_coupling = [&](int cpl) {
         sw.sync = cpl != 2;
