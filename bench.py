@@ -32,17 +32,18 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, groups=4):
-    """FP64 oracle on the first `groups` groups of the same workload (groups
-    only couple downward, so this is exactly the first part of the full
-    solve), all host threads it is given."""
+def cpu_baseline(prob, groups=None):
+    """FP64 oracle on the first `groups` groups of the same workload (all of
+    them by default; groups only couple downward, so a prefix is exactly the
+    first part of the full solve), all host threads it is given."""
     import numpy as np
 
     import oracle
     from paper_1811_12391_amd import inputs as I
 
     xs = prob.xs
-    sub = I.XSTables(edges=xs.edges[: groups + 1], sigma_t=xs.sigma_t[:, :groups].copy(),
+    groups = prob.G if groups is None else groups
+    sub = xs if groups == prob.G else I.XSTables(edges=xs.edges[: groups + 1], sigma_t=xs.sigma_t[:, :groups].copy(),
                      sigma_s=xs.sigma_s[:, :, :groups, :groups].copy(), kerma=xs.kerma[:, :groups].copy(),
                      cutoff=xs.cutoff[:, :groups].copy(), names=xs.names, Z=xs.Z)
     threads = oracle.default_threads()
@@ -53,8 +54,10 @@ def cpu_baseline(prob, groups=4):
     dt = time.perf_counter() - t0
     upd = float(r.iters.sum()) * prob.phantom.C * prob.N
     return {"value": upd / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {groups} of {prob.G} groups of the same solve ({int(r.iters.sum())} source "
-                      f"iterations, {dt:.1f} s wall, FP64 C oracle, OpenMP over directions/voxels)"}
+            "sample": (f"the whole solve, all {prob.G} groups" if groups == prob.G else
+                       f"first {groups} of {prob.G} groups of the same solve")
+                      + f" ({int(r.iters.sum())} source iterations, {dt:.1f} s wall, FP64 C oracle, "
+                        f"OpenMP over directions/voxels)"}
 
 
 def main():
@@ -122,7 +125,8 @@ def main():
             "fixed_iters": fixed is not None,
             "iteration_sets": int(stats[-1].iteration_sets),
             "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
-                               "wave_coupling": {1: "lds_counters", 2: "barrier"}[int(stats[-1].sweep_sync)]},
+                               "wave_coupling": {1: "lds_counters", 2: "barrier",
+                                                  3: "pipelined_blocks"}[int(stats[-1].sweep_sync)]},
             "dose": dose,
         }
         _log(f"[bench] {tag}: {res['ms_per_step']:.2f} ms/solve wall, {res['device_ms_per_solve']:.2f} ms device, "
