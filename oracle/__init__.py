@@ -86,6 +86,13 @@ def _declare(L):
                             ct.c_double, ct.c_int, _i, ct.c_int, _d, ct.c_int,
                             _d, _d, _d, _i, _d, _d, _l])
     L.orc_solve.restype = ct.c_int
+    L.orc_solve_sup.argtypes = ([ct.c_int] * 3 + [ct.c_double] * 3 + [_d, _u8, _d,
+                                ct.c_int, ct.c_int, ct.c_int, _d, _d, _d,
+                                ct.c_int, _d, _d,
+                                ct.c_int, ct.c_int, _d, _d, ct.c_double, ct.c_double, _d, _d,
+                                ct.c_double, ct.c_int, _i, ct.c_int, _d, ct.c_int,
+                                _d, _d, _d, _i, _d, _d, _l])
+    L.orc_solve_sup.restype = ct.c_int
 
 
 def _p(a, t=_d):
@@ -260,9 +267,12 @@ class OracleResult:
 
 def solve(ph, xs, dirs, w, L, pos, axis, fan_deg, cone_deg, group_w, *, ext_iso=None, tol=1e-6,
           max_iter=1000, fixed_iters=None, fixup=True, test_inflow=None, threads=None,
-          B_subset=None) -> OracleResult:
+          B_subset=None, superpose=1) -> OracleResult:
     """Full FP64 solve; ``xs`` needs sigma_t [M][G], sigma_s [M][L+1][G][G]
-    (only l <= L used), kerma [M][G]."""
+    (only l <= L used), kerma [M][G].  With ``superpose`` = S > 1 every S
+    consecutive sources form one right-hand side (one collided solve of
+    their summed first-collision source; the outputs are per right-hand
+    side, phi_u summed over its sources)."""
     G = xs.sigma_t.shape[1]
     M = xs.sigma_t.shape[0]
     st = _f64(xs.sigma_t)
@@ -272,14 +282,18 @@ def solve(ph, xs, dirs, w, L, pos, axis, fan_deg, cone_deg, group_w, *, ext_iso=
     N = dirs.shape[0]
     pos, axis = _f64(pos).reshape(-1, 3), _f64(axis).reshape(-1, 3)
     B = pos.shape[0]
+    S = int(superpose)
+    if S < 1 or B % S:
+        raise ValueError(f"superpose={S} must divide the number of sources {B}")
+    R = B // S
     C = ph.C
     Nm = (L + 1) ** 2
-    phi_u = np.zeros((B, G, C))
-    phi = np.zeros((B, G, Nm, C))
-    dose = np.zeros((B, C))
-    iters = np.zeros((B, G), dtype=np.int32)
-    eps = np.zeros((B, G))
-    bal = np.zeros((B, G, 3))
+    phi_u = np.zeros((R, G, C))
+    phi = np.zeros((R, G, Nm, C))
+    dose = np.zeros((R, C))
+    iters = np.zeros((R, G), dtype=np.int32)
+    eps = np.zeros((R, G))
+    bal = np.zeros((R, G, 3))
     nfix = ct.c_long(0)
     fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, dtype=np.int32)
     ei = None if ext_iso is None else _f64(ext_iso).reshape(G, C)
@@ -288,9 +302,9 @@ def solve(ph, xs, dirs, w, L, pos, axis, fan_deg, cone_deg, group_w, *, ext_iso=
     rho = _f64(ph.density)
     org = _f64(ph.origin)
     gw = _f64(group_w)
-    rc = lib().orc_solve(ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, _p(org), _p(mat, _u8), _p(rho),
+    rc = lib().orc_solve_sup(ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, _p(org), _p(mat, _u8), _p(rho),
                          G, M, L, _p(st), _p(ss), _p(ka), N, _p(dirs), _p(w),
-                         B, _p(pos), _p(axis), float(fan_deg), float(cone_deg), _p(gw), _p(ei),
+                         B, S, _p(pos), _p(axis), float(fan_deg), float(cone_deg), _p(gw), _p(ei),
                          float(tol), int(max_iter), _p(fi, _i), int(fixup), _p(ti),
                          threads or default_threads(),
                          _p(phi_u), _p(phi), _p(dose), _p(iters, _i), _p(eps), _p(bal), ct.byref(nfix))

@@ -471,11 +471,13 @@ static double ss_at(const Prob *P, int m, int l, int gf, int gt)
     return P->ss[(((size_t)m * (P->L + 1) + l) * P->G + gf) * P->G + gt];
 }
 
-/* Forward solve of one right-hand side.  pu = its uncollided flux [G][C].
- * Outputs phi[G][Nm][C], dose[C], iters[G], eps[G], bal[G][3].  When
- * psi_store / mask_store are given, the cell fluxes [G][N][C] and fixed-face
- * sets of the final sweep of every group are kept (for the adjoint). */
-static int forward_rhs(const Prob *P, const double *p, const double *pu, const double *ext_iso,
+/* Forward solve of one right-hand side.  ext = its first-collision source
+ * [G][Nm][C] (owned by the call: downscatter is added to it in place), pu =
+ * its uncollided flux [G][C].  Outputs phi[G][Nm][C], dose[C], iters[G],
+ * eps[G], bal[G][3].  When psi_store / mask_store are given, the cell fluxes
+ * [G][N][C] and fixed-face sets of the final sweep of every group are kept
+ * (for the adjoint). */
+static int forward_rhs(const Prob *P, double *ext, const double *pu,
                        double tol, int max_iter, const int *fixed_iters, int fixup, const double *test_inflow,
                        int nthreads, double *phi, double *dose, int *iters, double *eps, double *bal,
                        long *nfix_total, double *psi_store, uint8_t *mask_store)
@@ -484,7 +486,6 @@ static int forward_rhs(const Prob *P, const double *p, const double *pu, const d
     const size_t C = (size_t)P->nx * P->ny * P->nz;
     const double V = P->dx * P->dy * P->dz;
     const double Ax = P->dy * P->dz, Ay = P->dx * P->dz, Az = P->dx * P->dy;
-    double *ext = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
     double *Q = (double *)malloc(sizeof(double) * (size_t)Nm * C);
     double *q = (double *)malloc(sizeof(double) * (size_t)N * C);
     double *ps = (double *)malloc(sizeof(double) * (size_t)N * C);
@@ -494,9 +495,7 @@ static int forward_rhs(const Prob *P, const double *p, const double *pu, const d
     double *leak = (double *)malloc(sizeof(double) * 3 * N);
     double *inflow = (double *)malloc(sizeof(double) * N);
     uint8_t *mask = (uint8_t *)malloc((size_t)N * C);
-    if (!ext || !Q || !q || !ps || !cur || !nxt || !sigt || !leak || !inflow || !mask) return -4;
-    orc_first_collision(P->nx, P->ny, P->nz, P->dx, P->dy, P->dz, P->org, P->mat, P->rho, G, L, P->ss, p, pu,
-                        ext_iso, nthreads, ext);
+    if (!Q || !q || !ps || !cur || !nxt || !sigt || !leak || !inflow || !mask) return -4;
     for (int g = 0; g < G; ++g) {
         double bc = test_inflow ? test_inflow[g] : 0.0;
         for (int n = 0; n < N; ++n) inflow[n] = bc;
@@ -585,7 +584,7 @@ static int forward_rhs(const Prob *P, const double *p, const double *pu, const d
             dose[v] += k0 * (pu[(size_t)g * C + v] + cur[v]);
         }
     }
-    free(ext); free(Q); free(q); free(ps); free(cur); free(nxt); free(sigt); free(leak); free(inflow); free(mask);
+    free(Q); free(q); free(ps); free(cur); free(nxt); free(sigt); free(leak); free(inflow); free(mask);
     return 0;
 }
 
@@ -613,6 +612,63 @@ static void free_prob(Prob *P)
     free((void *)P->Dmap);
 }
 
+/* Superposed sources (the CT-scan form of Sec. III-C: several cone beams in
+ * one simulation): the B sources form B / S right-hand sides of S consecutive
+ * sources each.  The transport problem is linear in its source, so one
+ * collided solve per right-hand side takes the sum of its sources'
+ * first-collision sources, and its dose adds the sum of their uncollided
+ * fluxes.  S = 1 solves every source on its own.  Outputs per right-hand
+ * side: phi_u [B/S][G][C] (summed), phi, dose, iters, eps, bal. */
+int orc_solve_sup(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+                  const uint8_t *mat, const double *rho,
+                  int G, int M, int L, const double *st, const double *ss, const double *kap,
+                  int N, const double *dirs, const double *w,
+                  int B, int S, const double *pos, const double *axis, double fan_deg, double cone_deg,
+                  const double *gw, const double *ext_iso,
+                  double tol, int max_iter, const int *fixed_iters, int fixup,
+                  const double *test_inflow, int nthreads,
+                  double *phi_u, double *phi, double *dose, int *iters, double *eps, double *bal,
+                  long *nfix_out)
+{
+    if (S < 1 || B % S != 0) return -1;
+    size_t C = (size_t)nx * ny * nz;
+    int lof[289];
+    Prob P;
+    make_prob(&P, nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, L, st, ss, kap, N, dirs, w, lof);
+    const int Nm = P.Nm, R = B / S;
+    double *pu_src = (double *)malloc(sizeof(double) * (size_t)B * G * C);
+    double *ext = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
+    double *ext1 = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
+    if (!pu_src || !ext || !ext1) return -4;
+    orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg, cone_deg, gw, nthreads,
+                   pu_src);
+    long nfix = 0;
+    int rc = 0;
+    for (int r = 0; r < R && rc == 0; ++r) {
+        double *pu = phi_u + (size_t)r * G * C;
+        memset(pu, 0, sizeof(double) * (size_t)G * C);
+        memset(ext, 0, sizeof(double) * (size_t)G * Nm * C);
+        for (int k = 0; k < S; ++k) {
+            const int b = r * S + k;
+            const double *pb = pu_src + (size_t)b * G * C;
+            /* the volumetric source belongs to the problem, not to a beam: once per right-hand side */
+            orc_first_collision(nx, ny, nz, dx, dy, dz, org, mat, rho, G, L, ss, pos + 3 * b, pb,
+                                k == 0 ? ext_iso : NULL, nthreads, ext1);
+            for (size_t i = 0; i < (size_t)G * Nm * C; ++i) ext[i] += ext1[i];
+            for (size_t i = 0; i < (size_t)G * C; ++i) pu[i] += pb[i];
+        }
+        rc = forward_rhs(&P, ext, pu, tol, max_iter, fixed_iters, fixup, test_inflow, nthreads,
+                         phi + (size_t)r * G * Nm * C, dose + (size_t)r * C, iters + r * G, eps + r * G,
+                         bal + (size_t)r * G * 3, &nfix, NULL, NULL);
+    }
+    if (nfix_out) *nfix_out = nfix;
+    free(pu_src);
+    free(ext);
+    free(ext1);
+    free_prob(&P);
+    return rc;
+}
+
 int orc_solve(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
               const uint8_t *mat, const double *rho,
               int G, int M, int L, const double *st, const double *ss, const double *kap,
@@ -624,21 +680,9 @@ int orc_solve(int nx, int ny, int nz, double dx, double dy, double dz, const dou
               double *phi_u, double *phi, double *dose, int *iters, double *eps, double *bal,
               long *nfix_out)
 {
-    size_t C = (size_t)nx * ny * nz;
-    int lof[289];
-    Prob P;
-    make_prob(&P, nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, L, st, ss, kap, N, dirs, w, lof);
-    orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg, cone_deg, gw, nthreads,
-                   phi_u);
-    long nfix = 0;
-    int rc = 0;
-    for (int b = 0; b < B && rc == 0; ++b)
-        rc = forward_rhs(&P, pos + 3 * b, phi_u + (size_t)b * G * C, ext_iso, tol, max_iter, fixed_iters, fixup,
-                         test_inflow, nthreads, phi + (size_t)b * G * P.Nm * C, dose + (size_t)b * C, iters + b * G,
-                         eps + b * G, bal + (size_t)b * G * 3, &nfix, NULL, NULL);
-    if (nfix_out) *nfix_out = nfix;
-    free_prob(&P);
-    return rc;
+    return orc_solve_sup(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, L, st, ss, kap, N, dirs, w, B, 1, pos, axis,
+                         fan_deg, cone_deg, gw, ext_iso, tol, max_iter, fixed_iters, fixup, test_inflow, nthreads,
+                         phi_u, phi, dose, iters, eps, bal, nfix_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -697,6 +741,7 @@ int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, const d
     double *nxt = (double *)malloc(sizeof(double) * (size_t)Nm * C);
     double *sigt = (double *)malloc(sizeof(double) * C);
     double *pbu = (double *)malloc(sizeof(double) * (size_t)G * C);
+    double *ext = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
     long nfix = 0;
     double R = 0.0;
     memset(d_rho, 0, sizeof(double) * C);
@@ -704,7 +749,8 @@ int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, const d
     for (int b = 0; b < B; ++b) {
         const double *p = pos + 3 * b;
         const double *pu = phi_u + (size_t)b * G * C;
-        forward_rhs(&P, p, pu, NULL, tol, max_iter, fixed_iters, fixup, NULL, nthreads, phi, dose, it_f, eps_f, bal,
+        orc_first_collision(nx, ny, nz, dx, dy, dz, org, mat, rho, G, L, ss, p, pu, NULL, nthreads, ext);
+        forward_rhs(&P, ext, pu, tol, max_iter, fixed_iters, fixup, NULL, nthreads, phi, dose, it_f, eps_f, bal,
                     &nfix, psi, mask);
         for (size_t v = 0; v < C; ++v) R += roi[v] * dose[v];
         /* direct weights of the dose on both fluence parts */
@@ -816,7 +862,7 @@ int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, const d
     }
     if (R_out) *R_out = R;
     free(phi_u); free(unit); free(ones); free(phi); free(psi); free(mask); free(dose); free(it_f); free(eps_f);
-    free(bal); free(lam); free(pb); free(mu); free(sdir); free(lc); free(cur); free(nxt); free(sigt); free(pbu);
+    free(bal); free(lam); free(pb); free(mu); free(sdir); free(lc); free(cur); free(nxt); free(sigt); free(pbu); free(ext);
     free_prob(&P);
     return 0;
 }

@@ -486,7 +486,9 @@ class Problem:
 def make_problem(name: str) -> Problem:
     """The five workloads (water cylinder and abdomen phantoms) plus small
     ragged test cases.  'c1'..'c5' follow the configurations used for the
-    measurements; 'tiny*' are a few-second oracle sizes."""
+    measurements; 'ct16' is the superposed CT-scan form; 'tiny*' are
+    few-second oracle sizes."""
+    fan, cone = 20.0, 10.0          # beam window (full angles, degrees)
     if name == "c1":
         ph = cylinder_phantom(24, 24, 8, 1.5)
         G, S, L, pos, axis, prec = 4, 4, 1, *top_source(), "fp64"
@@ -502,6 +504,16 @@ def make_problem(name: str) -> Problem:
     elif name == "c5":
         ph = abdomen_phantom(64, 64, 16, 0.6)
         G, S, L, pos, axis, prec = 19, 6, 3, *top_source(), "fp32"
+    elif name == "ct16":
+        # CT-scan form: 16 cone beams of 30 degrees evenly on the 54 cm circle
+        # around the c2 cylinder, meant to be superposed into one collided solve
+        ph = cylinder_phantom(64, 64, 16, 0.6)
+        G, S, L, (pos, axis), prec = 19, 6, 3, ring_sources(16, 22.5), "fp32"
+        fan = cone = 30.0
+    elif name == "tiny_ct":
+        ph = cylinder_phantom(13, 11, 5, 3.0)
+        G, S, L, (pos, axis), prec = 3, 4, 1, ring_sources(4, 90.0), "fp64"
+        fan = cone = 30.0
     elif name == "tiny":
         # ragged: not a multiple of any tile, several groups, P1
         ph = cylinder_phantom(13, 11, 5, 3.0)
@@ -514,4 +526,4 @@ def make_problem(name: str) -> Problem:
     xs = xs_tables(ph.material_names, G, L)
     dirs, w = lq_quadrature(S)
     gw = kramers_weights(xs.edges)
-    return Problem(name, ph, xs, dirs, w, L, pos, axis, 20.0, 10.0, gw, precision=prec)
+    return Problem(name, ph, xs, dirs, w, L, pos, axis, fan, cone, gw, precision=prec)

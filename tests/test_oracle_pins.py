@@ -450,3 +450,62 @@ def test_threads_bitwise(oracle_mod):
     a = oracle_mod.solve_problem(prob, threads=1)
     b = oracle_mod.solve_problem(prob, threads=4)
     assert np.array_equal(a.dose, b.dose) and np.array_equal(a.phi, b.phi)
+
+
+def _with_sources(prob, pos, axis):
+    return I.Problem(prob.name, prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, pos, axis,
+                     prob.fan_deg, prob.cone_deg, prob.group_w)
+
+
+def test_superposition_doubling_exact(oracle_mod):
+    """Two copies of one source superposed into one right-hand side give
+    exactly twice the single-source solve: every input of the collided solve
+    is doubled (an exact operation in binary floating point), the stopping
+    rule and the set-to-zero fixup depend only on ratios and signs, so every
+    result bit scales (fixup on, convergence-driven iteration counts)."""
+    prob = I.make_problem("tiny")
+    one = oracle_mod.solve_problem(prob)
+    two = oracle_mod.solve_problem(_with_sources(prob, np.repeat(prob.src_pos, 2, 0), np.repeat(prob.src_axis, 2, 0)),
+                                   superpose=2)
+    assert two.dose.shape == one.dose.shape
+    assert np.array_equal(two.iters, one.iters)
+    assert np.array_equal(two.dose, 2.0 * one.dose)
+    assert np.array_equal(two.phi, 2.0 * one.phi)
+    assert np.array_equal(two.phi_u, 2.0 * one.phi_u)
+
+
+def test_superposition_linear_in_sources(oracle_mod):
+    """Without the fixup the collided solve is linear, so the superposed
+    four-beam solve equals the sum of the four separate solves (same fixed
+    iteration counts), and its uncollided flux is the sum of theirs."""
+    prob = I.make_problem("tiny_ct")
+    fi = [5] * prob.G
+    sep = oracle_mod.solve_problem(prob, fixed_iters=fi, fixup=False)
+    sup = oracle_mod.solve_problem(prob, fixed_iters=fi, fixup=False, superpose=4)
+    assert sup.dose.shape == (1, prob.phantom.C)
+    ref = sep.dose.sum(axis=0)
+    assert np.allclose(sup.dose[0], ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    assert np.allclose(sup.phi_u[0], sep.phi_u.sum(axis=0), rtol=1e-15, atol=0)
+    # two right-hand sides of two beams each: pairs of the separate solves
+    sup2 = oracle_mod.solve_problem(prob, fixed_iters=fi, fixup=False, superpose=2)
+    for r in range(2):
+        ref = sep.dose[2 * r] + sep.dose[2 * r + 1]
+        assert np.allclose(sup2.dose[r], ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+def test_superposition_fixup_nonlinear_but_close(oracle_mod):
+    """With the set-to-zero fixup the solve is no longer exactly linear, but
+    the superposed dose stays close to the sum of the separate doses (the
+    fixup only acts where DD outflows turn negative)."""
+    prob = I.make_problem("tiny_ct")
+    sep = oracle_mod.solve_problem(prob)
+    sup = oracle_mod.solve_problem(prob, superpose=4)
+    ref = sep.dose.sum(axis=0)
+    err = np.linalg.norm(sup.dose[0] - ref) / np.linalg.norm(ref)
+    assert err < 1e-2
+
+
+def test_superpose_rejects_uneven_groups(oracle_mod):
+    prob = I.make_problem("tiny_ct")
+    with pytest.raises(ValueError):
+        oracle_mod.solve_problem(prob, superpose=3)
