@@ -194,10 +194,11 @@ def main():
 
 
 def other_forms(args):
-    """The batched and differentiated forms of the solve, each against the
-    same form in FP64 on the GPU: the 36-source axial scan (FP32, autotuned,
-    graph replay) and the ROI-dose gradient on the 64x64x16 abdomen (FP32
-    forward + adjoint)."""
+    """The batched, superposed and differentiated forms of the solve, each
+    against the same form in FP64 on the GPU: the 36-source axial scan (FP32,
+    autotuned, graph replay), the 16-beam CT scan superposed into one
+    collided solve (FP32 at the FP64 solve's iteration counts), and the
+    ROI-dose gradient on the 64x64x16 abdomen (FP32 forward + adjoint)."""
     import numpy as np
     import torch
 
@@ -229,6 +230,46 @@ def other_forms(args):
         _log(f"[bench] axial scan (36 sources) fp32: {1e3 * wall:.1f} ms/solve, {upd / wall:.3e} updates/s")
     finally:
         s.close()
+    # CT scan as 16 concurrent cone beams superposed into one collided solve,
+    # beside one beam alone and the 16 beams as separate right-hand sides
+    prob = I.make_problem("ct16")
+    one = I.Problem("ct16_one", prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos[:1],
+                    prob.src_axis[:1], prob.fan_deg, prob.cone_deg, prob.group_w)
+    reps = max(1, min(args.steps, 3))
+
+    def timed(p, **kw):
+        s = dctsn.Solver(p)
+        try:
+            s.solve(**kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st = s.solve(**kw)
+            wall = (time.perf_counter() - t0) / reps
+            return wall, st, s.dose(summed=True)
+        finally:
+            s.close()
+
+    base = dict(autotune=True, use_graph=True, chunk=8)
+    _, st64, ref = timed(prob, precision="fp64", tol=prob.tol, superpose=16, **base)
+    # FP32 stalls at a few 1e-6 in the highest groups of this form (set-to-zero
+    # decisions that flip between iterations), so it runs the FP64 counts
+    fi = st64.iters[0].astype(np.int32)
+    w_sup, st, d = timed(prob, precision="fp32", fixed_iters=fi, superpose=16, **base)
+    w_one, st1, _ = timed(one, precision="fp32", fixed_iters=fi, **base)
+    w_sep, _, d_sep = timed(prob, precision="fp32", fixed_iters=fi, **base)
+    upd = float(st.iters.sum()) * prob.phantom.C * prob.N
+    out["ct_scan_superposed"] = {
+        "workload": "c2 cylinder, 16 cone beams of 30 x 30 deg every 22.5 deg on a 54 cm circle, superposed "
+                    "into one collided solve, 19 groups, S6 (48 dirs), P3",
+        "precision": "fp32", "fixed_iters_from_fp64": fi.tolist(), "ms_per_solve": 1e3 * w_sup,
+        "updates_per_s": upd / w_sup, "one_beam_ms_per_solve": 1e3 * w_one,
+        "sixteen_separate_rhs_ms_per_solve": 1e3 * w_sep,
+        "dose_l2_rel_err_vs_fp64_gpu": float(np.linalg.norm(d - ref) / np.linalg.norm(ref)),
+        "superposed_vs_separate_dose_l2_rel_diff": float(np.linalg.norm(d - d_sep) / np.linalg.norm(d_sep)),
+    }
+    _log(f"[bench] CT scan, 16 beams superposed fp32: {1e3 * w_sup:.1f} ms/solve (one beam {1e3 * w_one:.1f} ms, "
+         f"16 separate {1e3 * w_sep:.1f} ms)")
     # ROI-dose gradient
     prob = I.make_problem("c5")
     ph = prob.phantom

@@ -80,10 +80,18 @@ typedef struct dct_opts {
                                  blocks of a sweep in one launch, handing block faces over
                                  as they are produced (needs >= 2 blocks of >= 2 z layers,
                                  otherwise runs as 1); 0 = tuned or 1 */
+    int superpose;            /* sources per right-hand side S (0 or 1: one each).  With
+                                 S > 1 the B sources of dct_set_source form B / S right-hand
+                                 sides of S consecutive sources; each is solved once with
+                                 the summed first-collision source of its beams and its dose
+                                 adds their uncollided fluences (a CT scan as concurrent
+                                 beams in one simulation, Sec. III-C).  Every [B] below then
+                                 counts right-hand sides.  EINVAL if S does not divide B or
+                                 if keep_adjoint is set with S > 1. */
 } dct_opts;
 
 typedef struct dct_stats {
-    /* caller-owned arrays, each may be NULL */
+    /* caller-owned arrays, each may be NULL ([B] = right-hand sides) */
     int *iters;               /* [B][G] iterations taken */
     double *eps;              /* [B][G] final relative change */
     double *balance;          /* [B][G][3] production, removal, leakage of the final sweep */
@@ -166,10 +174,13 @@ int dct_set_volume_source(dct_ctx *ctx, const double *S);
  * ENUMERIC on NaN/Inf, ESTATE if an input is missing or inputs conflict. */
 int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats);
 
-/* Results of the last solve into caller-allocated HOST buffers.
- *   dose[B][C] (summed = 0) or dose[C] (summed = 1: sum over sources), keV/g
- *     per source photon;
- *   phi_u[B][G][C] uncollided scalar fluence (may be NULL);
+/* Results of the last solve into caller-allocated HOST buffers ([B] counts
+ * the right-hand sides of that solve: sources, or groups of superposed
+ * sources).
+ *   dose[B][C] (summed = 0) or dose[C] (summed = 1: sum over right-hand
+ *     sides), keV/g per source photon;
+ *   phi_u[B][G][C] uncollided scalar fluence (summed over superposed sources;
+ *     may be NULL);
  *   phi_c[B][G][C] collided scalar fluence phi_00 (may be NULL).
  * ESTATE before a successful solve. */
 int dct_dose(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c);
@@ -196,7 +207,7 @@ int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R
                 double *d_group_w, dct_stats *stats);
 
 /* All collided flux moments of the last solve into a host buffer
- * phi[B][G][Nm][C] (FP64 whatever the precision). */
+ * phi[B][G][Nm][C] (B right-hand sides; FP64 whatever the precision). */
 int dct_moments(dct_ctx *ctx, double *phi);
 
 #ifdef __cplusplus

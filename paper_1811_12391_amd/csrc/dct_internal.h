@@ -163,12 +163,13 @@ struct TraceArgs {
 struct TransArgs {
     Geo geo;
     int G, M, L, Nm, N, B;
+    int S;                    // sources per right-hand side (superposed beams)
     double V;
     const uint8_t *mat;
     const double *rho;
     const double *st, *ss;    // [M][G], [M][L+1][G][G]
-    const double *pos;        // [B][3]
-    const double *phi_u;      // [B][G][C]
+    const double *pos;        // [B*S][3]
+    const double *phi_u;      // [B*S][G][C]
     const double *ext_iso;    // [G][C] or null
     const double *inflow;     // [G] or null
     const int *band_lo;       // [G] lowest group that scatters into g in any material (or null)
@@ -289,13 +290,14 @@ struct AdjRayArgs {
 struct DoseArgs {
     long C;
     int G, B, Nm;
+    int S;                    // sources per right-hand side (superposed beams)
     const uint8_t *mat;
     const double *kap;        // [M][G]
-    const double *phi_u;      // [B][G][C]
+    const double *phi_u;      // [B*S][G][C]
     const void *phi_all;      // T [B][G][Nm][C]
     double *dose;             // [B][C]
     double *phi_c;            // [B][G][C] or null
-    double *phi_u_out;        // [B][G][C] or null
+    double *phi_u_out;        // [B][G][C] (summed over each right-hand side's sources) or null
     int summed;               // 1: dose[C] = sum_b
 };
 

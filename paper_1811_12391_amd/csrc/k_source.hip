@@ -94,16 +94,10 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
             const int i = (int)(v % geo.nx);
             const int j = (int)((v / geo.nx) % geo.ny);
             const int k = (int)(v / ((long)geo.nx * geo.ny));
-            const double *p = a.pos + 3 * b;
-            double d0 = geo.org[0] + (i + 0.5) * geo.dx - p[0];
-            double d1 = geo.org[1] + (j + 0.5) * geo.dy - p[1];
-            double d2 = geo.org[2] + (k + 0.5) * geo.dz - p[2];
-            double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            double Y[NM];
-            real_sh_cart<double>(LT, d0 / r, d1 / r, d2 / r, Y);
             T *ext = (T *)a.ext + (long)b * Nm * C;   // the first source of the group (k_qinit lays it out for the sweep)
             // every moment accumulates in the same order as before: first-
-            // collision terms g' = 0..g, the volume source, then downscatter
+            // collision terms g' = 0..g (per superposed source, each source's
+            // sum added in turn), the volume source, then downscatter
             // g' = 0..g-1; each phi_u value is read once for all moments
             double e[NM];
 #pragma unroll
@@ -113,10 +107,27 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
             // moment adds an exact zero), so the loads carry no branch
             const double *sm = a.ss + (long)m * (L + 1) * G * G;
             const int g0 = a.band_lo ? a.band_lo[g] : 0;
-            for (int gp = g0; gp <= g; ++gp) {
-                const double pu = rho * a.phi_u[((long)b * G + gp) * C + v];
+            for (int ks = 0; ks < a.S; ++ks) {
+                // the uncollided flux of source ks is a delta in angle along
+                // the direction from the source to the voxel centre
+                const long src = (long)b * a.S + ks;
+                const double *p = a.pos + 3 * src;
+                double d0 = geo.org[0] + (i + 0.5) * geo.dx - p[0];
+                double d1 = geo.org[1] + (j + 0.5) * geo.dy - p[1];
+                double d2 = geo.org[2] + (k + 0.5) * geo.dz - p[2];
+                double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                double Y[NM];
+                real_sh_cart<double>(LT, d0 / r, d1 / r, d2 / r, Y);
+                double es[NM];
 #pragma unroll
-                for (int lm = 0; lm < NM; ++lm) e[lm] += sm[((long)l_of(lm) * G + gp) * G + g] * pu * Y[lm];
+                for (int lm = 0; lm < NM; ++lm) es[lm] = 0.0;
+                for (int gp = g0; gp <= g; ++gp) {
+                    const double pu = rho * a.phi_u[(src * G + gp) * C + v];
+#pragma unroll
+                    for (int lm = 0; lm < NM; ++lm) es[lm] += sm[((long)l_of(lm) * G + gp) * G + g] * pu * Y[lm];
+                }
+#pragma unroll
+                for (int lm = 0; lm < NM; ++lm) e[lm] += es[lm];
             }
             if (a.ext_iso) e[0] += a.ext_iso[(long)g * C + v];
             for (int gp = g0; gp < g; ++gp) {

@@ -271,7 +271,8 @@ hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, cons
 }
 
 // Dose tally (Sec. II-A: collision kerma as absorbed dose):
-// dose_b(v) = sum_g kappa_g[m_v] (phi_u,g(v) + phi_00,g(v)), summed in group order.
+// dose_b(v) = sum_g kappa_g[m_v] (phi_u,g(v) + phi_00,g(v)), summed in group order;
+// phi_u of a right-hand side is the sum of its S superposed sources' fluxes.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dose(DoseArgs a)
 {
@@ -283,7 +284,8 @@ __global__ __launch_bounds__(256) void k_dose(DoseArgs a)
     for (int b = 0; b < a.B; ++b) {
         double dsum = 0.0;
         for (int g = 0; g < a.G; ++g) {
-            double pu = a.phi_u[((long)b * a.G + g) * a.C + v];
+            double pu = 0.0;
+            for (int k = 0; k < a.S; ++k) pu += a.phi_u[(((long)b * a.S + k) * a.G + g) * a.C + v];
             double pc = (double)pa[(((long)b * a.G + g) * a.Nm) * a.C + v];
             dsum += a.kap[m * a.G + g] * (pu + pc);
             if (a.phi_c) a.phi_c[((long)b * a.G + g) * a.C + v] = pc;

@@ -65,6 +65,7 @@ struct dct_ctx {
     bool solved = false;
     int solved_prec = 0;
     int solved_Nm = 0;
+    int solved_S = 1;           // sources per right-hand side of the last solve
     bool kept = false;          // the last solve kept per-group fluxes and fixup sets
 
     // sweep schedules chosen by the autotuner, per problem shape
@@ -445,6 +446,10 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
     pl.NmP = 16 * ((Nm + 15) / 16);
     if (o.sweep_bk < 0 || o.sweep_bk > 16) return fail(ctx, DCT_EINVAL, "solve: sweep_bk must be in [0, 16]");
     if (o.sweep_sync < 0 || o.sweep_sync > 3) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 3]");
+    if (o.superpose < 0 || (o.superpose > 1 && ctx->B % o.superpose != 0))
+        return fail(ctx, DCT_EINVAL, "solve: superpose must divide the number of sources (" + std::to_string(ctx->B) + ")");
+    if (o.superpose > 1 && o.keep_adjoint)
+        return fail(ctx, DCT_EINVAL, "solve: keep_adjoint is not supported with superposed sources");
     set_blocks(pl, o.sweep_bk > 0 ? o.sweep_bk : 16, ctx->ny, ctx->nz);
     return DCT_OK;
 }
@@ -480,7 +485,9 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     ctx->solved = false;
     HC(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz, G = ctx->G, M = ctx->M, L = ctx->L, N = ctx->N, B = ctx->B;
+    const int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz, G = ctx->G, M = ctx->M, L = ctx->L, N = ctx->N;
+    // right-hand sides: one per source, or groups of S superposed sources
+    const int nsrc = ctx->B, S = o.superpose > 1 ? o.superpose : 1, B = nsrc / S;
     const long C = (long)nx * ny * nz;
     const int Nm = pl.Nm;
     const size_t ts = pl.tsz;
@@ -511,7 +518,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     if (!ctx->iso.empty()) HC(dbuf(ctx, "iso", ctx->iso.size() * 8, &d_iso));
     if (o.test_inflow) HC(dbuf(ctx, "infl", (size_t)G * 8, &d_infl));
     if (o.fixed_iters) HC(dbuf(ctx, "fixed", (size_t)G * 4, &d_fixed));
-    HC(dbuf(ctx, "phiu", (size_t)B * G * C * 8, &d_phiu));
+    HC(dbuf(ctx, "phiu", (size_t)nsrc * G * C * 8, &d_phiu));
     HC(dbuf(ctx, "sigc", (size_t)2 * G * C * ts, &d_sigc));
     HC(dbuf(ctx, "ext", (size_t)B * Nm * C * ts, &d_ext));
     HC(dbuf(ctx, "Qc", (size_t)2 * B * Nm * C * ts, &d_Qc));
@@ -674,7 +681,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         ta.st = (const double *)d_st;
         ta.G = G;
         ta.M = M;
-        ta.B = B;
+        ta.B = nsrc;
         ta.pos = (const double *)d_pos;
         ta.axis = (const double *)d_axis;
         ta.half_fan = ctx->fan * DCT_PI / 360.0;
@@ -692,6 +699,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     tr.Nm = Nm;
     tr.N = N;
     tr.B = B;
+    tr.S = S;
     tr.V = ctx->dx * ctx->dy * ctx->dz;
     tr.mat = (const uint8_t *)d_mat;
     tr.rho = (const double *)d_rho;
@@ -1005,6 +1013,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     da.C = C;
     da.G = G;
     da.B = B;
+    da.S = S;
     da.Nm = Nm;
     da.mat = (const uint8_t *)d_mat;
     da.kap = (const double *)d_kap;
@@ -1061,6 +1070,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     ctx->solved = true;
     ctx->solved_prec = o.precision;
     ctx->solved_Nm = Nm;
+    ctx->solved_S = S;
     ctx->kept = keep;
     if (unfinished != 0) {
         ctx->solved = false;
@@ -1080,7 +1090,7 @@ static int dose_common(dct_ctx *ctx, double *dose, int summed, double *phi_u, do
     HC(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const long C = (long)ctx->nx * ctx->ny * ctx->nz;
-    const int B = ctx->B, G = ctx->G;
+    const int B = ctx->B / ctx->solved_S, G = ctx->G;
     double *o_dose = dose, *o_pu = phi_u, *o_pc = phi_c;
     if (!dev) {
         void *t;
@@ -1098,6 +1108,7 @@ static int dose_common(dct_ctx *ctx, double *dose, int summed, double *phi_u, do
     da.C = C;
     da.G = G;
     da.B = B;
+    da.S = ctx->solved_S;
     da.Nm = ctx->solved_Nm;
     da.mat = (const uint8_t *)ctx->bufs["mat"].p;
     da.kap = (const double *)ctx->bufs["kap"].p;
@@ -1135,7 +1146,7 @@ extern "C" int dct_moments(dct_ctx *ctx, double *phi)
     if (!phi) return fail(ctx, DCT_EINVAL, "moments: NULL output");
     HC(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const long n = (long)ctx->B * ctx->G * ctx->solved_Nm * ctx->nx * ctx->ny * ctx->nz;
+    const long n = (long)(ctx->B / ctx->solved_S) * ctx->G * ctx->solved_Nm * ctx->nx * ctx->ny * ctx->nz;
     void *t;
     HC(dbuf(ctx, "o_mom", (size_t)n * 8, &t));
     HC(launch_moments_out(ctx->bufs["phi"].p, n, (double *)t, ctx->solved_prec == DCT_FP64, s));

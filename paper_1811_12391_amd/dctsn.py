@@ -39,7 +39,7 @@ class dct_opts(ct.Structure):
                 ("fixed_iters", ct.POINTER(ct.c_int)), ("fixup", ct.c_int),
                 ("test_inflow", ct.POINTER(ct.c_double)), ("chunk", ct.c_int), ("use_graph", ct.c_int),
                 ("profile", ct.c_int), ("keep_adjoint", ct.c_int), ("autotune", ct.c_int),
-                ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int)]
+                ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int), ("superpose", ct.c_int)]
 
 
 class dct_stats(ct.Structure):
@@ -168,7 +168,9 @@ class SolveStats:
 
 def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=None, fixup=True,
           test_inflow=None, chunk=0, use_graph=False, profile=False, keep_adjoint=False, autotune=False,
-          sweep_bk=0, sweep_sync=0, allow_notconv=False) -> SolveStats:
+          sweep_bk=0, sweep_sync=0, superpose=1, allow_notconv=False) -> SolveStats:
+    """B = number of sources; with superpose = S > 1 the per-right-hand-side
+    outputs have B // S rows."""
     o = dct_opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.tol = tol
@@ -185,6 +187,11 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     o.autotune = int(autotune)
     o.sweep_bk = int(sweep_bk)
     o.sweep_sync = int(sweep_sync)
+    o.superpose = int(superpose)
+    S = max(1, int(superpose))
+    if B % S:
+        raise ValueError(f"superpose={S} must divide the number of sources {B}")
+    B = B // S
     iters = np.zeros((B, G), dtype=np.int32)
     eps = np.zeros((B, G))
     bal = np.zeros((B, G, 3))
@@ -262,12 +269,15 @@ class Solver:
         set_xs(self.h, xs.G, xs.edges, xs.M, prob.L, xs.sigma_t, xs.sigma_s[:, : prob.L + 1], xs.kerma)
         set_quadrature(self.h, prob.N, prob.dirs, prob.weights)
         set_source(self.h, prob.B, prob.src_pos, prob.src_axis, prob.fan_deg, prob.cone_deg, prob.group_w)
+        self.rhs = prob.B                 # right-hand sides of the last solve
 
     def solve(self, **kw) -> SolveStats:
-        return solve(self.h, self.prob.B, self.prob.G, **kw)
+        st = solve(self.h, self.prob.B, self.prob.G, **kw)
+        self.rhs = self.prob.B // max(1, int(kw.get("superpose", 1)))
+        return st
 
     def dose(self, **kw):
-        return dose(self.h, self.prob.B, self.prob.G, self.prob.phantom.C, **kw)
+        return dose(self.h, self.rhs, self.prob.G, self.prob.phantom.C, **kw)
 
     def adjoint(self, roi, **kw) -> AdjointResult:
         return adjoint(self.h, self.prob.B, self.prob.G, self.prob.phantom.C, roi, **kw)
@@ -282,7 +292,7 @@ class Solver:
         set_source(self.h, p.B, p.src_pos, p.src_axis, p.fan_deg, p.cone_deg, group_w)
 
     def moments(self):
-        return moments(self.h, self.prob.B, self.prob.G, (self.prob.L + 1) ** 2, self.prob.phantom.C)
+        return moments(self.h, self.rhs, self.prob.G, (self.prob.L + 1) ** 2, self.prob.phantom.C)
 
     def close(self):
         if self.h is not None:
