@@ -43,37 +43,65 @@ __device__ inline short to_bf16(float f)
     return (short)(u >> 16);
 }
 
+// One class's map table [rows][cols] into LDS with row stride ST, and its
+// class-local -> global direction slots.  The loads of a round are issued
+// together (clamped indices, guarded LDS stores), the slot load first.
+template <typename T>
+__device__ inline void stage_table(T *tab, int ST, const T *src, int rows, int cols, int *cds, const int *cdsrc,
+                                   int nc)
+{
+    const int n = rows * cols;
+    const int c0 = cdsrc[min((int)threadIdx.x, max(nc - 1, 0))];
+    for (int i0 = threadIdx.x; i0 < n; i0 += 1024) {
+        T v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = src[min(i0 + 256 * k, n - 1)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + 256 * k;
+            if (i < n) tab[(i / cols) * ST + i % cols] = v[k];
+        }
+    }
+    if ((int)threadIdx.x < nc) cds[threadIdx.x] = c0;
+    for (int i = threadIdx.x + 256; i < nc; i += 256) cds[i] = cdsrc[i];
+}
+
 // ---------------------------------------------------------------- M map
+// Operands are loaded unconditionally and all at once (no load sits behind a
+// branch, so none waits for the previous one): padded moments (lm >= Nm) read
+// a real row whose table column is zero, positions past the grid read the
+// last position and are never stored.  The class's table and direction
+// slots are staged in LDS (row stride NmP + 1 against bank conflicts).
 template <typename T, int NS>
 __global__ __launch_bounds__(256) void k_mmap(MapArgs a)
 {
     typedef typename acc4<T>::type A4;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
-    if (a.state[b].finished) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
-    const int Nm = a.Nm;
+    const long pc = inb ? p : C - 1;
+    const int Nm = a.Nm, Nc = a.Nc[c], NmP = a.NmP, ST = a.NmP + 1;
     const T *Q = (const T *)a.Qc + ((long)c * a.B + b) * Nm * C;
     T bq[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        int lm = 4 * s + kr;
-        bq[s] = (inb && lm < Nm) ? Q[(long)lm * C + p] : (T)0;
-    }
-    const T *Mt = (const T *)a.Mtab + (long)c * a.NcP * a.NmP;
-    const int Nc = a.Nc[c];
-    const int *cd = a.cdir + c * a.N;
+    for (int s = 0; s < NS; ++s) bq[s] = Q[(long)min(4 * s + kr, Nm - 1) * C + pc];
+    T *tab = (T *)smem_map;                              // [NcP][NmP + 1]
+    int *cds = (int *)(tab + (long)a.NcP * ST);
+    stage_table(tab, ST, (const T *)a.Mtab + (long)c * a.NcP * NmP, a.NcP, NmP, cds, a.cdir + c * a.N, Nc);
+    __syncthreads();
+    if (a.state[b].finished) return;
     T *q = (T *)a.q + (long)b * a.N * C;
     for (int rb = 0; rb * 16 < Nc; ++rb) {
         A4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < NS; ++s) acc = mfma_k4(Mt[(rb * 16 + col) * a.NmP + 4 * s + kr], bq[s], acc);
+        for (int s = 0; s < NS; ++s) acc = mfma_k4(tab[(rb * 16 + col) * ST + 4 * s + kr], bq[s], acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int nl = rb * 16 + out_row<T>(kr, r);
-            if (nl < Nc && inb) q[(long)cd[nl] * C + p] = acc[r];
+            if (nl < Nc && inb) q[(long)cds[nl] * C + p] = acc[r];
         }
     }
 }
@@ -117,35 +145,53 @@ __global__ __launch_bounds__(256) void k_mmap_bf16(MapArgs a)
 }
 
 // ---------------------------------------------------------------- D map
-template <typename T>
+// As the M map: the class's table and direction slots in LDS, the psi
+// operands of up to KC K-steps loaded at once (clamped, unconditional; the
+// table columns of padded directions are zero), NRB 16-row blocks of
+// moments accumulated together so psi is read once.
+template <typename T, int NRB>
 __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
 {
     typedef typename acc4<T>::type A4;
+    constexpr int KC = 16;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
-    if (a.state[b].finished) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
-    const int Nm = a.Nm, Nc = a.Nc[c];
-    const int *cd = a.cdir + c * a.N;
+    const long pc = inb ? p : C - 1;
+    const int Nm = a.Nm, Nc = a.Nc[c], NcP = a.NcP, ST = a.NcP + 1;
+    T *tab = (T *)smem_map;                              // [NmP][NcP + 1]
+    int *cds = (int *)(tab + (long)a.NmP * ST);
+    stage_table(tab, ST, (const T *)a.Dtab + (long)c * a.NmP * NcP, a.NmP, NcP, cds, a.cdir + c * a.N, Nc);
+    __syncthreads();
+    if (a.state[b].finished) return;
     const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const T *psi = (const T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
-    const T *Dt = (const T *)a.Dtab + (long)c * a.NmP * a.NcP;
     T *part = (T *)a.part + ((long)c * a.B + b) * Nm * C;
-    for (int rb = 0; rb * 16 < Nm; ++rb) {
-        A4 acc = {0, 0, 0, 0};
-        for (int s = 0; 4 * s < Nc; ++s) {
-            int nl = 4 * s + kr;
-            T bv = (inb && nl < Nc) ? psi[(long)cd[nl] * C + p] : (T)0;
-            acc = mfma_k4(Dt[(rb * 16 + col) * a.NcP + 4 * s + kr], bv, acc);
-        }
+    A4 acc[NRB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) acc[rb] = A4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < Nc; k0 += 4 * KC) {
+        T bv[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) bv[u] = psi[(long)cds[min(k0 + 4 * u + kr, Nc - 1)] * C + pc];
+#pragma unroll
+        for (int u = 0; u < KC; ++u)
+            if (k0 + 4 * u < Nc) {
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb)
+                    acc[rb] = mfma_k4(tab[(rb * 16 + col) * ST + k0 + 4 * u + kr], bv[u], acc[rb]);
+            }
+    }
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int lm = rb * 16 + out_row<T>(kr, r);
-            if (lm < Nm && inb) part[(long)lm * C + p] = acc[r];
+            if (lm < Nm && inb) part[(long)lm * C + p] = acc[rb][r];
         }
-    }
 }
 
 __global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
@@ -182,21 +228,40 @@ __global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
     }
 }
 
+// LDS of the FP map kernels: the class's table (padded row stride) and its
+// direction slots
+template <typename T> static size_t map_lds(const MapArgs &a, bool mmap)
+{
+    const size_t rows = mmap ? a.NcP : a.NmP, st = (mmap ? a.NmP : a.NcP) + 1;
+    return rows * st * sizeof(T) + (size_t)a.N * 4;
+}
+
 template <typename T>
 static void dispatch_mmap(const MapArgs &a, dim3 grid, hipStream_t s)
 {
     int NS = (a.Nm + 3) / 4;
+    const size_t shm = map_lds<T>(a, true);
     switch (NS) {
-    case 1: hipLaunchKernelGGL((k_mmap<T, 1>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_mmap<T, 2>), grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_mmap<T, 3>), grid, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_mmap<T, 4>), grid, dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_mmap<T, 5>), grid, dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_mmap<T, 6>), grid, dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_mmap<T, 7>), grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_mmap<T, 8>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_mmap<T, 9>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_mmap<T, 1>), grid, dim3(256), shm, s, a); break;
+    case 2: hipLaunchKernelGGL((k_mmap<T, 2>), grid, dim3(256), shm, s, a); break;
+    case 3: hipLaunchKernelGGL((k_mmap<T, 3>), grid, dim3(256), shm, s, a); break;
+    case 4: hipLaunchKernelGGL((k_mmap<T, 4>), grid, dim3(256), shm, s, a); break;
+    case 5: hipLaunchKernelGGL((k_mmap<T, 5>), grid, dim3(256), shm, s, a); break;
+    case 6: hipLaunchKernelGGL((k_mmap<T, 6>), grid, dim3(256), shm, s, a); break;
+    case 7: hipLaunchKernelGGL((k_mmap<T, 7>), grid, dim3(256), shm, s, a); break;
+    case 8: hipLaunchKernelGGL((k_mmap<T, 8>), grid, dim3(256), shm, s, a); break;
+    default: hipLaunchKernelGGL((k_mmap<T, 9>), grid, dim3(256), shm, s, a); break;
     }
+}
+
+template <typename T>
+static void dispatch_dmap(const MapArgs &a, dim3 grid, hipStream_t s)
+{
+    const size_t shm = map_lds<T>(a, false);
+    const int nrb = (a.Nm + 15) / 16;
+    if (nrb == 1) hipLaunchKernelGGL((k_dmap<T, 1>), grid, dim3(256), shm, s, a);
+    else if (nrb == 2) hipLaunchKernelGGL((k_dmap<T, 2>), grid, dim3(256), shm, s, a);
+    else hipLaunchKernelGGL((k_dmap<T, 3>), grid, dim3(256), shm, s, a);
 }
 
 hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s)
@@ -216,8 +281,8 @@ hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s)
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s)
 {
     dim3 grid((unsigned)((a.C + 63) / 64), 2, a.B);
-    if (mode == 0) hipLaunchKernelGGL(k_dmap<double>, grid, dim3(256), 0, s, a);
-    else if (mode == 1) hipLaunchKernelGGL(k_dmap<float>, grid, dim3(256), 0, s, a);
+    if (mode == 0) dispatch_dmap<double>(a, grid, s);
+    else if (mode == 1) dispatch_dmap<float>(a, grid, s);
     else hipLaunchKernelGGL(k_dmap_bf16, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -444,6 +444,13 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
     pl.NcP = 16 * ((std::max(pl.Nc[0], pl.Nc[1]) + 15) / 16);
     if (pl.NcP == 0) pl.NcP = 16;
     pl.NmP = 16 * ((Nm + 15) / 16);
+    {
+        // the map kernels stage one class's table (padded rows) and its direction slots in LDS
+        const size_t lm = (size_t)pl.NcP * (pl.NmP + 1) * pl.tsz, ld = (size_t)pl.NmP * (pl.NcP + 1) * pl.tsz;
+        if (std::max(lm, ld) + (size_t)N * 4 > 65536)
+            return fail(ctx, DCT_EINVAL, "solve: too many directions per octant class for the moment-map tables (" +
+                                             std::to_string(std::max(pl.Nc[0], pl.Nc[1])) + ")");
+    }
     if (o.sweep_bk < 0 || o.sweep_bk > 16) return fail(ctx, DCT_EINVAL, "solve: sweep_bk must be in [0, 16]");
     if (o.sweep_sync < 0 || o.sweep_sync > 3) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 3]");
     if (o.superpose < 0 || (o.superpose > 1 && ctx->B % o.superpose != 0))
