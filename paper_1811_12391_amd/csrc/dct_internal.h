@@ -202,6 +202,7 @@ struct CombArgs {
     int max_iter;
     int nblocks_per_b;
     int reverse;              // groups run from G-1 down to 0
+    unsigned *cnt_mom;        // [B][Nm][32] per-moment completion counters, one per 128-byte line
 };
 
 struct MapArgs {

@@ -78,6 +78,7 @@ __global__ __launch_bounds__(256) void k_mmap(MapArgs a)
     typedef typename acc4<T>::type A4;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
+    if (a.state[b].finished) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
@@ -92,7 +93,6 @@ __global__ __launch_bounds__(256) void k_mmap(MapArgs a)
     int *cds = (int *)(tab + (long)a.NcP * ST);
     stage_table(tab, ST, (const T *)a.Mtab + (long)c * a.NcP * NmP, a.NcP, NmP, cds, a.cdir + c * a.N, Nc);
     __syncthreads();
-    if (a.state[b].finished) return;
     T *q = (T *)a.q + (long)b * a.N * C;
     for (int rb = 0; rb * 16 < Nc; ++rb) {
         A4 acc = {0, 0, 0, 0};
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
     constexpr int KC = 16;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
+    if (a.state[b].finished) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
@@ -166,7 +167,6 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
     int *cds = (int *)(tab + (long)a.NmP * ST);
     stage_table(tab, ST, (const T *)a.Dtab + (long)c * a.NmP * NcP, a.NmP, NcP, cds, a.cdir + c * a.N, Nc);
     __syncthreads();
-    if (a.state[b].finished) return;
     const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const T *psi = (const T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
     T *part = (T *)a.part + ((long)c * a.B + b) * Nm * C;

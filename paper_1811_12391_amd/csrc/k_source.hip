@@ -496,7 +496,6 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
         }
         __syncthreads();
     }
-    const unsigned nblocks_b = (unsigned)(nslab * Nm);   // live blocks of this RHS (slabs x moments)
     double dm = 0.0, fm = 0.0;
     if (lm == 0) {
         dm = block_max(dmax, red);
@@ -508,8 +507,19 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
         }
         wait_own_memory_ops();
-        unsigned prev = live ? atomicAdd(&st->cnt_combine, 1u) : 0u;
-        if (live && prev == nblocks_b - 1) {
+        // two-level completion count: the slabs of one moment on that
+        // moment's counter (its own cache line), the last of them on the
+        // right-hand side's counter, so no counter takes an atomic from every
+        // workgroup; the last block of the last moment closes the iteration
+        unsigned *cm = a.cnt_mom + ((long)b * Nm + lm) * 32;
+        const unsigned prev1 = live ? atomicAdd(cm, 1u) : 0u;
+        unsigned prev = 0u;
+        if (live && prev1 == (unsigned)nslab - 1) {
+            atomicExch(cm, 0u);
+            wait_own_memory_ops();
+            prev = atomicAdd(&st->cnt_combine, 1u) + 1u;
+        }
+        if (prev == (unsigned)Nm) {
             wait_own_memory_ops();
             double num = __longlong_as_double((long long)atomicAdd(&st->eps_num, 0ull));
             double den = __longlong_as_double((long long)atomicAdd(&st->eps_den, 0ull));

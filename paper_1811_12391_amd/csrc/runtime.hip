@@ -558,6 +558,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     const size_t leak_max = (size_t)B * N * pl.NBJ * nz * 3 * 8;   // any block split (z layers >= 1)
     HC(dbuf(ctx, "leak", leak_max, &d_leak));
     HC(dbuf(ctx, "state", (size_t)B * sizeof(RhsState), &d_state));
+    void *d_ccnt;
+    HC(dbuf(ctx, "ccnt", (size_t)B * DCT_MAXNM * 128, &d_ccnt));
     HC(dbuf(ctx, "bal", (size_t)B * G * 3 * 8, &d_bal));
     HC(dbuf(ctx, "iters", (size_t)B * G * 4, &d_iters));
     HC(dbuf(ctx, "eps", (size_t)B * G * 8, &d_eps));
@@ -667,6 +669,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(hipMemsetAsync(d_eps, 0, (size_t)B * G * 8, s));
     HC(hipMemsetAsync(d_leak, 0, leak_max, s));
     HC(hipMemsetAsync(d_err, 0, 4, s));
+    HC(hipMemsetAsync(d_ccnt, 0, (size_t)B * DCT_MAXNM * 128, s));
 
     Geo geo;
     geo.nx = nx;
@@ -805,6 +808,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     cb.state = (RhsState *)d_state;
     cb.iters = (int *)d_iters;
     cb.eps = (double *)d_eps;
+    cb.cnt_mom = (unsigned *)d_ccnt;
     cb.fixed_iters = (const int *)d_fixed;
     cb.tol = o.tol;
     cb.max_iter = o.max_iter;
@@ -1261,6 +1265,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     HC(hipMemsetAsync(d_ait, 0, (size_t)B * G * 4, s));
     HC(hipMemsetAsync(d_aeps, 0, (size_t)B * G * 8, s));
     HC(hipMemsetAsync(B_("err"), 0, 4, s));
+    HC(hipMemsetAsync(B_("ccnt"), 0, (size_t)B * DCT_MAXNM * 128, s));
     HC(launch_adj_init(C, G, B, (const uint8_t *)B_("mat"), (const double *)B_("kap"), (const double *)d_roi,
                        (double *)d_pbu, s));
     HC(hipStreamSynchronize(s));   // host tables must outlive the copies
@@ -1380,6 +1385,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     cb.state = (RhsState *)B_("state");
     cb.iters = (int *)d_ait;
     cb.eps = (double *)d_aeps;
+    cb.cnt_mom = (unsigned *)B_("ccnt");
     cb.fixed_iters = o.fixed_iters ? (const int *)d_fix : nullptr;
     cb.tol = o.tol;
     cb.max_iter = o.max_iter;
