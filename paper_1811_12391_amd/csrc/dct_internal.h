@@ -124,6 +124,27 @@ __device__ inline void bst(rsrc_t r, unsigned off, double v)
 // whole L2 of the XCD, once per workgroup.)
 __device__ inline void wait_own_memory_ops() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Two-level "last workgroup" detection over the nblk workgroups of one
+// right-hand side: workgroup i counts on sub-counter i / 32 (one 128-byte
+// line each: sub[(i / 32) * 32]), the last of each group of 32 on `top`, so
+// no counter takes an atomic from every workgroup.  True in exactly one
+// workgroup, after the device atomics of every workgroup (issued before its
+// call) are complete; the counters are left at zero.  One thread calls it.
+__device__ inline bool last_block(unsigned *sub, unsigned *top, unsigned i, unsigned nblk)
+{
+    wait_own_memory_ops();
+    const unsigned grp = i >> 5, ngrp = (nblk + 31) >> 5;
+    const unsigned in_grp = nblk - (grp << 5) < 32u ? nblk - (grp << 5) : 32u;
+    unsigned *c = sub + grp * 32;
+    if (atomicAdd(c, 1u) != in_grp - 1) return false;
+    atomicExch(c, 0u);
+    wait_own_memory_ops();
+    if (atomicAdd(top, 1u) != ngrp - 1) return false;
+    atomicExch(top, 0u);
+    wait_own_memory_ops();
+    return true;
+}
+
 // ---------------------------------------------------------------- device state
 // Per right-hand-side state of the device-driven group / iteration machine.
 struct RhsState {
@@ -182,6 +203,9 @@ struct TransArgs {
     RhsState *state;
     double *bal;              // [B][G][3]
     int *n_unfinished;
+    unsigned *cnt_sub;        // [B][nsub][32] completion sub-counters (zero between launches)
+    int nsub;                 // ceil(workgroups per right-hand side / 32)
+    double *part_bal;         // [B][workgroups][2] per-workgroup removal and production sums
 };
 
 struct CombArgs {
@@ -272,6 +296,8 @@ struct AdjTransArgs {
     double *drho;             // [B][C]
     RhsState *state;
     int *n_unfinished;
+    unsigned *cnt_sub;        // [B][nsub][32] completion sub-counters (zero between launches)
+    int nsub;
 };
 
 struct AdjRayArgs {

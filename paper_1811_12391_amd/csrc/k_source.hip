@@ -149,45 +149,59 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
     }
     double Rs = block_sum(Rp, red);
     double Ps = block_sum(Pp, red);
+    // per-workgroup sums through device atomics (no contention: one slot
+    // each); the last workgroup closes the finished group's balance and
+    // opens the next one, summing in a fixed order
+    __shared__ int last;
     if (threadIdx.x == 0) {
-        if (g > 0) atomicAdd(&a.bal[((long)b * G + g - 1) * 3 + 1], Rs * a.V);
-        if (g < G) atomicAdd(&a.bal[((long)b * G + g) * 3 + 0], Ps * a.V);
-        if (blockIdx.x == 0) {
-            const double Ax = geo.dy * geo.dz, Ay = geo.dx * geo.dz, Az = geo.dx * geo.dy;
-            if (g > 0) {
-                double Lk = 0.0;
-                for (int n = 0; n < a.N; ++n) {
-                    double lx = 0, ly = 0, lz = 0;
-                    for (int q = 0; q < a.nblk; ++q) {
-                        const double *lp = a.leak_part + (((long)b * a.N + n) * a.nblk + q) * 3;
-                        lx += lp[0];
-                        ly += lp[1];
-                        lz += lp[2];
-                    }
-                    Lk += a.w[n] * (fabs(a.dirs[3 * n]) * Ax * lx + fabs(a.dirs[3 * n + 1]) * Ay * ly +
-                                    fabs(a.dirs[3 * n + 2]) * Az * lz);
-                }
-                a.bal[((long)b * G + g - 1) * 3 + 2] = Lk;
+        unsigned long long *pb = (unsigned long long *)a.part_bal + ((long)b * gridDim.x + blockIdx.x) * 2;
+        atomicExch(pb, (unsigned long long)__double_as_longlong(Rs));
+        atomicExch(pb + 1, (unsigned long long)__double_as_longlong(Ps));
+        last = last_block(a.cnt_sub + (long)b * a.nsub * 32, &st->cnt_trans, blockIdx.x, gridDim.x);
+    }
+    __syncthreads();
+    if (!last) return;
+    double r = 0.0, pr = 0.0, lk = 0.0, pin = 0.0;
+    for (unsigned q = threadIdx.x; q < gridDim.x; q += blockDim.x) {
+        const unsigned long long *pq = (const unsigned long long *)a.part_bal + ((long)b * gridDim.x + q) * 2;
+        r += __longlong_as_double((long long)__hip_atomic_load(pq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        pr += __longlong_as_double((long long)__hip_atomic_load(pq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    const double Ax = geo.dy * geo.dz, Ay = geo.dx * geo.dz, Az = geo.dx * geo.dy;
+    for (int n = threadIdx.x; n < a.N; n += blockDim.x) {
+        const double wx = a.w[n] * fabs(a.dirs[3 * n]) * Ax, wy = a.w[n] * fabs(a.dirs[3 * n + 1]) * Ay,
+                     wz = a.w[n] * fabs(a.dirs[3 * n + 2]) * Az;
+        if (g > 0) {
+            // leakage of the finished group: boundary outflows of its final sweep
+            double lx = 0, ly = 0, lz = 0;
+            for (int q = 0; q < a.nblk; ++q) {
+                const double *lp = a.leak_part + (((long)b * a.N + n) * a.nblk + q) * 3;
+                lx += lp[0];
+                ly += lp[1];
+                lz += lp[2];
             }
-            if (g < G && a.inflow && a.inflow[g] != 0.0) {
-                double Pin = 0.0;
-                for (int n = 0; n < a.N; ++n)
-                    Pin += a.w[n] * (fabs(a.dirs[3 * n]) * Ax * geo.ny * geo.nz +
-                                     fabs(a.dirs[3 * n + 1]) * Ay * geo.nx * geo.nz +
-                                     fabs(a.dirs[3 * n + 2]) * Az * geo.nx * geo.ny);
-                atomicAdd(&a.bal[((long)b * G + g) * 3 + 0], a.inflow[g] * Pin);
-            }
+            lk += wx * lx + wy * ly + wz * lz;
         }
-        wait_own_memory_ops();
-        unsigned prev = atomicAdd(&st->cnt_trans, 1u);
-        if (prev == gridDim.x - 1) {
-            wait_own_memory_ops();
-            st->cnt_trans = 0;
-            st->pending = 0;
-            if (g >= G) {
-                st->finished = 1;
-                atomicSub(a.n_unfinished, 1);
-            }
+        // boundary inflow production of the next group (isotropic inflow)
+        pin += wx * geo.ny * geo.nz + wy * geo.nx * geo.nz + wz * geo.nx * geo.ny;
+    }
+    r = block_sum(r, red);
+    pr = block_sum(pr, red);
+    lk = block_sum(lk, red);
+    pin = block_sum(pin, red);
+    if (threadIdx.x == 0) {
+        if (g > 0) {
+            a.bal[((long)b * G + g - 1) * 3 + 1] = r * a.V;
+            a.bal[((long)b * G + g - 1) * 3 + 2] = lk;
+        }
+        if (g < G) {
+            const double fin = (a.inflow && a.inflow[g] != 0.0) ? a.inflow[g] * pin : 0.0;
+            a.bal[((long)b * G + g) * 3 + 0] = pr * a.V + fin;
+        }
+        st->pending = 0;
+        if (g >= G) {
+            st->finished = 1;
+            atomicSub(a.n_unfinished, 1);
         }
     }
 }
@@ -282,11 +296,7 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        wait_own_memory_ops();
-        unsigned prev = atomicAdd(&st->cnt_trans, 1u);
-        if (prev == gridDim.x - 1) {
-            wait_own_memory_ops();
-            st->cnt_trans = 0;
+        if (last_block(a.cnt_sub + (long)b * a.nsub * 32, &st->cnt_trans, blockIdx.x, gridDim.x)) {
             st->pending = 0;
             if (gs >= G) {
                 st->finished = 1;

@@ -560,6 +560,11 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(dbuf(ctx, "state", (size_t)B * sizeof(RhsState), &d_state));
     void *d_ccnt;
     HC(dbuf(ctx, "ccnt", (size_t)B * DCT_MAXNM * 128, &d_ccnt));
+    // transition kernels: completion sub-counters and per-workgroup balance sums
+    const int tr_blocks = (int)((C + 255) / 256), tr_nsub = (tr_blocks + 31) / 32;
+    void *d_tsub, *d_pbal;
+    HC(dbuf(ctx, "tsub", (size_t)B * tr_nsub * 128, &d_tsub));
+    HC(dbuf(ctx, "pbal", (size_t)B * tr_blocks * 16, &d_pbal));
     HC(dbuf(ctx, "bal", (size_t)B * G * 3 * 8, &d_bal));
     HC(dbuf(ctx, "iters", (size_t)B * G * 4, &d_iters));
     HC(dbuf(ctx, "eps", (size_t)B * G * 8, &d_eps));
@@ -670,6 +675,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(hipMemsetAsync(d_leak, 0, leak_max, s));
     HC(hipMemsetAsync(d_err, 0, 4, s));
     HC(hipMemsetAsync(d_ccnt, 0, (size_t)B * DCT_MAXNM * 128, s));
+    HC(hipMemsetAsync(d_tsub, 0, (size_t)B * tr_nsub * 128, s));
 
     Geo geo;
     geo.nx = nx;
@@ -730,6 +736,9 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     tr.state = (RhsState *)d_state;
     tr.bal = (double *)d_bal;
     tr.n_unfinished = (int *)d_unf;
+    tr.cnt_sub = (unsigned *)d_tsub;
+    tr.nsub = tr_nsub;
+    tr.part_bal = (double *)d_pbal;
 
     MapArgs ma;
     ma.C = C;
@@ -1266,6 +1275,8 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     HC(hipMemsetAsync(d_aeps, 0, (size_t)B * G * 8, s));
     HC(hipMemsetAsync(B_("err"), 0, 4, s));
     HC(hipMemsetAsync(B_("ccnt"), 0, (size_t)B * DCT_MAXNM * 128, s));
+    const int tr_nsub = (int)(((C + 255) / 256 + 31) / 32);
+    HC(hipMemsetAsync(B_("tsub"), 0, (size_t)B * tr_nsub * 128, s));
     HC(launch_adj_init(C, G, B, (const uint8_t *)B_("mat"), (const double *)B_("kap"), (const double *)d_roi,
                        (double *)d_pbu, s));
     HC(hipStreamSynchronize(s));   // host tables must outlive the copies
@@ -1307,6 +1318,8 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     at.drho = (double *)d_drho;
     at.state = (RhsState *)B_("state");
     at.n_unfinished = (int *)B_("unf");
+    at.cnt_sub = (unsigned *)B_("tsub");
+    at.nsub = tr_nsub;
 
     MapArgs ma;
     ma.C = C;
