@@ -189,6 +189,21 @@ int dct_dose(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_
  * context's stream (asynchronous). */
 int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c);
 
+/* Fluence-to-dose conversion of the last solve (Sec. III-A: group-wise
+ * fluence-to-effective-dose factors interpolated linearly from a table, the
+ * dose in air neglected; the paper's table, ICRP 116, is an input here).
+ *   n >= 1 table points, energy_keV[n] strictly increasing, factor[n] dose per
+ *     unit fluence (e.g. pSv cm^2);
+ *   group factor h_g = the table at the group's mid energy (E_g + E_g+1) / 2,
+ *     linear between points, the end value beyond either end (needs the
+ *     group edges given to dct_set_xs);
+ *   zero_material[M] (nonzero: voxels of that material get 0) or NULL;
+ *   out[B][C] (summed = 0) or out[C] (summed = 1) HOST buffer:
+ *     out_b(v) = sum_g h_g (phi_u,g(v) + phi_00,g(v)).
+ * ESTATE before a solve or without group edges; EINVAL on a bad table. */
+int dct_effective_dose(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
+                       const uint8_t *zero_material, double *out, int summed);
+
 /* Gradient of the response R = sum_b sum_v roi[v] dose_b(v) with respect to
  * every voxel density and every source group weight, by the adjoint of the
  * discretised solve at the converged state of the last dct_solve (which must

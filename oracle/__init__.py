@@ -316,3 +316,22 @@ def solve(ph, xs, dirs, w, L, pos, axis, fan_deg, cone_deg, group_w, *, ext_iso=
 def solve_problem(prob, **kw) -> OracleResult:
     return solve(prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos, prob.src_axis,
                  prob.fan_deg, prob.cone_deg, prob.group_w, **kw)
+
+
+def effective_dose(res, phantom, edges_keV, energy_keV, factor, zero_material=None, summed=False):
+    """Fluence-to-dose conversion (Sec. III-A, dose comparison paragraph):
+    group-wise conversion factors taken from a table by linear interpolation
+    at each group's mid energy (the end value beyond either end of the
+    table), applied to the total (uncollided + collided) scalar fluence of
+    every group; voxels of flagged materials (air) get zero dose.  ``res`` is
+    an OracleResult; group g = 0 is the highest energy (edges descending)."""
+    edges = np.asarray(edges_keV, dtype=np.float64)
+    mid = 0.5 * (edges[:-1] + edges[1:])
+    h = np.interp(mid, np.asarray(energy_keV, dtype=np.float64), np.asarray(factor, dtype=np.float64))
+    total = res.phi_u + res.phi[:, :, 0]                     # [B][G][C]
+    out = np.zeros((total.shape[0], total.shape[2]))
+    for g in range(total.shape[1]):                          # group order, as the dose tally
+        out += h[g] * total[:, g]
+    if zero_material is not None:
+        out[:, np.asarray(zero_material, dtype=bool)[phantom.material]] = 0.0
+    return out.sum(axis=0) if summed else out

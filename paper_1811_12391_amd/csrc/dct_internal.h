@@ -326,6 +326,8 @@ struct DoseArgs {
     double *phi_c;            // [B][G][C] or null
     double *phi_u_out;        // [B][G][C] (summed over each right-hand side's sources) or null
     int summed;               // 1: dose[C] = sum_b
+    const double *hg;         // [G] fluence-to-dose factor per group in place of kerma, or null
+    const uint8_t *zero_mat;  // [M] nonzero: dose 0 in that material (fluences still written), or null
 };
 
 // ---------------------------------------------------------------- launchers

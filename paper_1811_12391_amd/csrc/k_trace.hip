@@ -270,7 +270,9 @@ hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, cons
     return hipGetLastError();
 }
 
-// Dose tally (Sec. II-A: collision kerma as absorbed dose):
+// Dose tally (Sec. II-A: collision kerma as absorbed dose; or, with per-group
+// factors hg, a fluence-to-dose conversion such as effective dose, Sec. III-A,
+// with the dose of flagged materials such as air neglected):
 // dose_b(v) = sum_g kappa_g[m_v] (phi_u,g(v) + phi_00,g(v)), summed in group order;
 // phi_u of a right-hand side is the sum of its S superposed sources' fluxes.
 template <typename T>
@@ -280,6 +282,7 @@ __global__ __launch_bounds__(256) void k_dose(DoseArgs a)
     if (v >= a.C) return;
     const T *pa = (const T *)a.phi_all;
     int m = a.mat[v];
+    const bool zero = a.zero_mat && a.zero_mat[m];
     double tot = 0.0;
     for (int b = 0; b < a.B; ++b) {
         double dsum = 0.0;
@@ -287,10 +290,11 @@ __global__ __launch_bounds__(256) void k_dose(DoseArgs a)
             double pu = 0.0;
             for (int k = 0; k < a.S; ++k) pu += a.phi_u[(((long)b * a.S + k) * a.G + g) * a.C + v];
             double pc = (double)pa[(((long)b * a.G + g) * a.Nm) * a.C + v];
-            dsum += a.kap[m * a.G + g] * (pu + pc);
+            dsum += (a.hg ? a.hg[g] : a.kap[m * a.G + g]) * (pu + pc);
             if (a.phi_c) a.phi_c[((long)b * a.G + g) * a.C + v] = pc;
             if (a.phi_u_out) a.phi_u_out[((long)b * a.G + g) * a.C + v] = pu;
         }
+        if (zero) dsum = 0.0;
         if (a.summed) tot += dsum;
         else a.dose[(long)b * a.C + v] = dsum;
     }

@@ -52,6 +52,7 @@ struct dct_ctx {
     std::vector<double> rho;
     int G = 0, M = 0, L = 0;
     std::vector<double> st, ss, kap;
+    std::vector<double> edges;  // group edges (keV, descending) when given
     int N = 0;
     std::vector<double> dirs, w;
     int B = 0;
@@ -265,6 +266,8 @@ int dct_set_xs(dct_ctx *ctx, int G, const double *edges_keV, int M, int L, const
     ctx->st.assign(sigma_t, sigma_t + (size_t)M * G);
     ctx->ss.assign(sigma_s, sigma_s + nss);
     ctx->kap.assign(kerma, kerma + (size_t)M * G);
+    if (edges_keV) ctx->edges.assign(edges_keV, edges_keV + G + 1);
+    else ctx->edges.clear();
     ctx->G = G;
     ctx->M = M;
     ctx->L = L;
@@ -1043,6 +1046,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     da.phi_c = nullptr;
     da.phi_u_out = nullptr;
     da.summed = 0;
+    da.hg = nullptr;
+    da.zero_mat = nullptr;
     HC(launch_dose(da, is64, s));
     HC(hipEventRecord(ctx->ev_t1, s));
     HC(hipEventSynchronize(ctx->ev_t1));
@@ -1101,7 +1106,10 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     return status;
 }
 
-static int dose_common(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c, bool dev)
+// hg: per-group fluence-to-dose factors (host, [G]) in place of the kerma
+// factors, or null; zmat: per-material flags (host, [M]), nonzero = dose 0
+static int dose_common(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c, bool dev,
+                       const double *hg = nullptr, const uint8_t *zmat = nullptr)
 {
     if (!ctx) return DCT_EINVAL;
     ctx->err.clear();
@@ -1138,7 +1146,22 @@ static int dose_common(dct_ctx *ctx, double *dose, int summed, double *phi_u, do
     da.phi_c = o_pc;
     da.phi_u_out = o_pu;
     da.summed = o_dose ? summed : 0;
+    da.hg = nullptr;
+    da.zero_mat = nullptr;
+    if (hg) {
+        void *t;
+        HC(dbuf(ctx, "o_hg", (size_t)G * 8, &t));
+        HC(hipMemcpyAsync(t, hg, (size_t)G * 8, hipMemcpyHostToDevice, s));
+        da.hg = (const double *)t;
+    }
+    if (zmat) {
+        void *t;
+        HC(dbuf(ctx, "o_zmat", (size_t)ctx->M, &t));
+        HC(hipMemcpyAsync(t, zmat, (size_t)ctx->M, hipMemcpyHostToDevice, s));
+        da.zero_mat = (const uint8_t *)t;
+    }
     HC(launch_dose(da, ctx->solved_prec == DCT_FP64, s));
+    if ((hg || zmat) && dev) HC(hipStreamSynchronize(s));   // the host tables are the caller's
     if (!dev) {
         if (dose) HC(hipMemcpyAsync(dose, o_dose, (size_t)(summed ? 1 : B) * C * 8, hipMemcpyDeviceToHost, s));
         if (phi_u) HC(hipMemcpyAsync(phi_u, o_pu, (size_t)B * G * C * 8, hipMemcpyDeviceToHost, s));
@@ -1156,6 +1179,39 @@ extern "C" int dct_dose(dct_ctx *ctx, double *dose, int summed, double *phi_u, d
 extern "C" int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *phi_c)
 {
     return dose_common(ctx, dose, summed, phi_u, phi_c, true);
+}
+
+extern "C" int dct_effective_dose(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
+                                  const uint8_t *zero_material, double *out, int summed)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!ctx->solved) return fail(ctx, DCT_ESTATE, "effective_dose: no valid solve since the last set_* call");
+    if ((int)ctx->edges.size() != ctx->G + 1)
+        return fail(ctx, DCT_ESTATE, "effective_dose: the group edges were not given to dct_set_xs");
+    if (n < 1 || !energy_keV || !factor || !out) return fail(ctx, DCT_EINVAL, "effective_dose: empty table or NULL");
+    if (!finite_all(energy_keV, n) || !finite_all(factor, n))
+        return fail(ctx, DCT_EINVAL, "effective_dose: non-finite table entry");
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(energy_keV[i] < energy_keV[i + 1]))
+            return fail(ctx, DCT_EINVAL, "effective_dose: table energies must be strictly increasing");
+    // group factor: the table at the group's mid energy, linear between
+    // points, the end value beyond either end
+    std::vector<double> hg(ctx->G);
+    for (int g = 0; g < ctx->G; ++g) {
+        const double e = 0.5 * (ctx->edges[g] + ctx->edges[g + 1]);
+        double h;
+        if (e <= energy_keV[0]) h = factor[0];
+        else if (e >= energy_keV[n - 1]) h = factor[n - 1];
+        else {
+            int i = 0;
+            while (energy_keV[i + 1] < e) ++i;
+            const double t = (e - energy_keV[i]) / (energy_keV[i + 1] - energy_keV[i]);
+            h = factor[i] + t * (factor[i + 1] - factor[i]);
+        }
+        hg[g] = h;
+    }
+    return dose_common(ctx, out, summed, nullptr, nullptr, false, hg.data(), zero_material);
 }
 
 extern "C" int dct_moments(dct_ctx *ctx, double *phi)

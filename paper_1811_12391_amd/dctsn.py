@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "DCT_OK", -1: "DCT_EINVAL", -2: "DCT_ESTATE", -3: "DCT_EDEVIC
 # every symbol include/dctsn.h declares
 EXPORTS = ["dct_create", "dct_destroy", "dct_last_error", "dct_set_geometry", "dct_set_xs",
            "dct_set_quadrature", "dct_set_source", "dct_set_volume_source", "dct_solve", "dct_dose",
-           "dct_dose_dev", "dct_adjoint", "dct_moments"]
+           "dct_dose_dev", "dct_effective_dose", "dct_adjoint", "dct_moments"]
 
 
 class DctError(RuntimeError):
@@ -79,6 +79,7 @@ def lib():
         L.dct_dose_dev.argtypes = [_vp, _vp, ct.c_int, _vp, _vp]
         L.dct_adjoint.argtypes = [_vp, _d, ct.POINTER(dct_opts), _d, _d, _d, ct.POINTER(dct_stats)]
         L.dct_moments.argtypes = [_vp, _d]
+        L.dct_effective_dose.argtypes = [_vp, ct.c_int, _d, _d, _u8, _d, ct.c_int]
         for n in EXPORTS:
             if n != "dct_last_error":
                 getattr(L, n).restype = ct.c_int
@@ -213,6 +214,19 @@ def dose(h, B, G, C, *, summed=False, want_phi=False):
     return (out, pu, pc) if want_phi else out
 
 
+def effective_dose(h, B, C, energy_keV, factor, *, zero_material=None, summed=False):
+    """Fluence-to-dose conversion of the last solve: per-group factors from a
+    table (linear in energy at each group's mid energy, flat beyond the
+    ends), zero in the flagged materials; B = right-hand sides."""
+    e, f = _f64(energy_keV).reshape(-1), _f64(factor).reshape(-1)
+    if e.size != f.size:
+        raise ValueError("energy and factor tables differ in length")
+    z = None if zero_material is None else np.ascontiguousarray(zero_material, dtype=np.uint8)
+    out = np.zeros(C if summed else (B, C))
+    _chk(h, lib().dct_effective_dose(h, int(e.size), _p(e), _p(f), _p(z, _u8), _p(out), int(summed)))
+    return out
+
+
 def dose_dev(h, dose_t, summed=False, phi_u_t=None, phi_c_t=None):
     """Write results into device tensors (float64 torch tensors on the context's device)."""
     return _chk(h, lib().dct_dose_dev(h, _dev_ptr(dose_t), int(summed), _dev_ptr(phi_u_t), _dev_ptr(phi_c_t)))
@@ -278,6 +292,9 @@ class Solver:
 
     def dose(self, **kw):
         return dose(self.h, self.rhs, self.prob.G, self.prob.phantom.C, **kw)
+
+    def effective_dose(self, energy_keV, factor, **kw):
+        return effective_dose(self.h, self.rhs, self.prob.phantom.C, energy_keV, factor, **kw)
 
     def adjoint(self, roi, **kw) -> AdjointResult:
         return adjoint(self.h, self.prob.B, self.prob.G, self.prob.phantom.C, roi, **kw)

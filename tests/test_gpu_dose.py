@@ -1,0 +1,80 @@
+"""GPU fluence-to-dose conversion (group factors interpolated from a table,
+air neglected: the effective-dose form of Sec. III-A) against the oracle's
+conversion of its own FP64 solve."""
+import numpy as np
+import pytest
+
+from paper_1811_12391_amd import dctsn, inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dctsn.lib()
+    yield
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _table(seed=3):
+    # seven points from 20 to 100 keV: the groups above 100 keV take the end value
+    rng = np.random.default_rng(seed)
+    E = np.linspace(20.0, 100.0, 7)
+    return E, rng.uniform(0.5, 4.0, E.size)
+
+
+@pytest.mark.parametrize("name,S,summed", [("tiny_abd", 1, False), ("tiny_ct", 4, False), ("tiny_ct", 2, True)])
+def test_effective_dose_fp64_matches_oracle(name, S, summed):
+    import oracle
+
+    prob = I.make_problem(name)
+    ph = prob.phantom
+    ref0 = oracle.solve_problem(prob, tol=1e-10, superpose=S)
+    fi = ref0.iters.max(0)
+    ref = oracle.solve_problem(prob, fixed_iters=fi, superpose=S)
+    E, f = _table()
+    zm = np.zeros(len(ph.material_names), dtype=np.uint8)
+    zm[ph.material_names.index("air")] = 1
+    want = oracle.effective_dose(ref, ph, prob.xs.edges, E, f, zero_material=zm, summed=summed)
+    s = dctsn.Solver(prob)
+    try:
+        s.solve(precision="fp64", fixed_iters=fi, superpose=S)
+        got = s.effective_dose(E, f, zero_material=zm, summed=summed)
+        plain = s.effective_dose(E, f, summed=summed)
+    finally:
+        s.close()
+    assert got.shape == want.shape
+    assert rel(got, want) < 1e-9
+    air = ph.material == ph.material_names.index("air")
+    sel = (Ellipsis, air)
+    assert np.all(got[sel] == 0.0) and np.any(plain[sel] != 0.0)
+
+
+def test_effective_dose_errors():
+    prob = I.make_problem("tiny")
+    s = dctsn.Solver(prob)
+    try:
+        E, f = _table()
+        with pytest.raises(dctsn.DctError) as e:
+            s.effective_dose(E, f)
+        assert e.value.code == dctsn.DCT_ESTATE          # no solve yet
+        s.solve(precision="fp64")
+        with pytest.raises(dctsn.DctError) as e:
+            s.effective_dose(E[::-1], f)
+        assert e.value.code == dctsn.DCT_EINVAL          # energies not increasing
+        xs = prob.xs
+        dctsn.set_xs(s.h, xs.G, None, xs.M, prob.L, xs.sigma_t, xs.sigma_s[:, : prob.L + 1], xs.kerma)
+        s.solve(precision="fp64")
+        with pytest.raises(dctsn.DctError) as e:
+            s.effective_dose(E, f)
+        assert e.value.code == dctsn.DCT_ESTATE          # no group edges
+    finally:
+        s.close()

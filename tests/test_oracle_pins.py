@@ -509,3 +509,54 @@ def test_superpose_rejects_uneven_groups(oracle_mod):
     prob = I.make_problem("tiny_ct")
     with pytest.raises(ValueError):
         oracle_mod.solve_problem(prob, superpose=3)
+
+
+@pytest.fixture(scope="module")
+def _tiny_solved(oracle_mod):
+    prob = I.make_problem("tiny")
+    return prob, oracle_mod.solve_problem(prob)
+
+
+def test_effective_dose_constant_table_is_total_fluence(oracle_mod, _tiny_solved):
+    """A flat conversion table gives c times the total scalar fluence."""
+    prob, r = _tiny_solved
+    d = oracle_mod.effective_dose(r, prob.phantom, prob.xs.edges, [10.0, 200.0], [2.5, 2.5])
+    tot = (r.phi_u + r.phi[:, :, 0]).sum(axis=1)
+    assert np.allclose(d, 2.5 * tot, rtol=1e-14, atol=0)
+
+
+def test_effective_dose_linear_table_exact_at_mid_energies(oracle_mod, _tiny_solved):
+    """A table linear in energy is reproduced exactly at the group mid energies
+    (group 0 is the highest energy: its factor is the largest)."""
+    prob, r = _tiny_solved
+    a, b = 0.3, 0.02
+    E = np.array([5.0, 40.0, 90.0, 150.0])
+    d = oracle_mod.effective_dose(r, prob.phantom, prob.xs.edges, E, a + b * E)
+    ed = prob.xs.edges
+    mid = [(ed[g] + ed[g + 1]) / 2 for g in range(prob.G)]
+    assert mid[0] > mid[-1]
+    ref = sum((a + b * mid[g]) * (r.phi_u[:, g] + r.phi[:, g, 0]) for g in range(prob.G))
+    assert np.allclose(d, ref, rtol=1e-13, atol=0)
+
+
+def test_effective_dose_flat_beyond_table_and_air_neglected(oracle_mod, _tiny_solved):
+    prob, r = _tiny_solved
+    ph = prob.phantom
+    # a one-interval table inside the lowest group: every group takes an end value
+    lo = float(prob.xs.edges[-1])
+    E, f = [lo + 1.0, lo + 2.0], [1.0, 3.0]
+    d = oracle_mod.effective_dose(r, ph, prob.xs.edges, E, f)
+    mid_low = (prob.xs.edges[-2] + prob.xs.edges[-1]) / 2
+    h = np.array([3.0 if (prob.xs.edges[g] + prob.xs.edges[g + 1]) / 2 >= lo + 2.0 else
+                  (1.0 if (prob.xs.edges[g] + prob.xs.edges[g + 1]) / 2 <= lo + 1.0 else np.nan)
+                  for g in range(prob.G)])
+    assert mid_low > lo + 2.0 and not np.isnan(h).any()
+    ref = sum(h[g] * (r.phi_u[:, g] + r.phi[:, g, 0]) for g in range(prob.G))
+    assert np.allclose(d, ref, rtol=1e-14, atol=0)
+    air = ph.material_names.index("air")
+    zm = np.zeros(len(ph.material_names), dtype=np.uint8)
+    zm[air] = 1
+    dz = oracle_mod.effective_dose(r, ph, prob.xs.edges, E, f, zero_material=zm)
+    is_air = ph.material == air
+    assert is_air.any() and (~is_air).any()
+    assert np.all(dz[:, is_air] == 0.0) and np.array_equal(dz[:, ~is_air], d[:, ~is_air])
