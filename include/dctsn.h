@@ -145,7 +145,7 @@ int dct_set_xs(dct_ctx *ctx, int G, const double *edges_keV, int M, int L, const
  * ESTATE at solve time if the P_N order L exceeds what the set integrates
  * (checked as D M = I to 1e-10 on the moment maps); EINVAL at solve time if
  * one class of octants (same sign of Omega_x Omega_y) holds more directions
- * than the moment-map tables fit in 64 KiB of LDS (about 300 at P5 in FP64,
+ * than the moment-map tables fit in 64 KiB of LDS (about 160 at P5 in FP64;
  * S16 = 144 per class fits). */
 int dct_set_quadrature(dct_ctx *ctx, int n, const double *dirs, const double *w);
 
