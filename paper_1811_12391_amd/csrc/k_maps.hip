@@ -109,37 +109,42 @@ __global__ __launch_bounds__(256) void k_mmap(MapArgs a)
 template <int NS16>
 __global__ __launch_bounds__(256) void k_mmap_bf16(MapArgs a)
 {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
     if (a.state[b].finished) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
-    const int Nm = a.Nm;
+    const long pc = inb ? p : C - 1;
+    const int Nm = a.Nm, Nc = a.Nc[c], NmP = a.NmP, ST = a.NmP + 4;   // 8-byte aligned rows
     const float *Q = (const float *)a.Qc + ((long)c * a.B + b) * Nm * C;
+    float fq[NS16][4];
+#pragma unroll
+    for (int s = 0; s < NS16; ++s)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) fq[s][e] = Q[(long)min(16 * s + 4 * kr + e, Nm - 1) * C + pc];
+    short *tab = (short *)smem_map;                      // [NcP][NmP + 4]
+    int *cds = (int *)(tab + (long)a.NcP * ST);
+    stage_table(tab, ST, (const short *)a.Mtab + (long)c * a.NcP * NmP, a.NcP, NmP, cds, a.cdir + c * a.N, Nc);
+    __syncthreads();
     s4_t bq[NS16];
 #pragma unroll
     for (int s = 0; s < NS16; ++s)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int lm = 16 * s + 4 * kr + e;
-            bq[s][e] = to_bf16((inb && lm < Nm) ? Q[(long)lm * C + p] : 0.0f);
-        }
-    const short *Mt = (const short *)a.Mtab + (long)c * a.NcP * a.NmP;
-    const int Nc = a.Nc[c];
-    const int *cd = a.cdir + c * a.N;
+        for (int e = 0; e < 4; ++e) bq[s][e] = to_bf16(fq[s][e]);
     float *q = (float *)a.q + (long)b * a.N * C;
     for (int rb = 0; rb * 16 < Nc; ++rb) {
         f4_t acc = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < NS16; ++s) {
-            s4_t av = *(const s4_t *)(Mt + (rb * 16 + col) * a.NmP + 16 * s + 4 * kr);
+            s4_t av = *(const s4_t *)(tab + (rb * 16 + col) * ST + 16 * s + 4 * kr);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bq[s], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int nl = rb * 16 + 4 * kr + r;
-            if (nl < Nc && inb) q[(long)cd[nl] * C + p] = acc[r];
+            if (nl < Nc && inb) q[(long)cds[nl] * C + p] = acc[r];
         }
     }
 }
@@ -196,36 +201,53 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
 
 __global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
 {
+    constexpr int KC = 4;                                // K-steps of 16 directions per load round
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
     if (a.state[b].finished) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
-    const int Nm = a.Nm, Nc = a.Nc[c];
-    const int *cd = a.cdir + c * a.N;
+    const long pc = inb ? p : C - 1;
+    const int Nm = a.Nm, Nc = a.Nc[c], NcP = a.NcP, ST = a.NcP + 4;
+    short *tab = (short *)smem_map;                      // [NmP][NcP + 4]
+    int *cds = (int *)(tab + (long)a.NmP * ST);
+    stage_table(tab, ST, (const short *)a.Dtab + (long)c * a.NmP * NcP, a.NmP, NcP, cds, a.cdir + c * a.N, Nc);
+    __syncthreads();
     const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const float *psi = (const float *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
-    const short *Dt = (const short *)a.Dtab + (long)c * a.NmP * a.NcP;
     float *part = (float *)a.part + ((long)c * a.B + b) * Nm * C;
-    for (int rb = 0; rb * 16 < Nm; ++rb) {
-        f4_t acc = {0, 0, 0, 0};
-        for (int s = 0; 16 * s < Nc; ++s) {
-            s4_t bv;
+    f4_t acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    const int nrb = (Nm + 15) / 16;
+    for (int k0 = 0; k0 < Nc; k0 += 16 * KC) {
+        float fv[KC][4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int nl = 16 * s + 4 * kr + e;
-                bv[e] = to_bf16((inb && nl < Nc) ? psi[(long)cd[nl] * C + p] : 0.0f);
+        for (int u = 0; u < KC; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                fv[u][e] = psi[(long)cds[min(k0 + 16 * u + 4 * kr + e, Nc - 1)] * C + pc];
+#pragma unroll
+        for (int u = 0; u < KC; ++u)
+            if (k0 + 16 * u < Nc) {
+                s4_t bv;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) bv[e] = to_bf16(fv[u][e]);
+#pragma unroll
+                for (int rb = 0; rb < 3; ++rb)
+                    if (rb < nrb) {
+                        s4_t av = *(const s4_t *)(tab + (rb * 16 + col) * ST + k0 + 16 * u + 4 * kr);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[rb], 0, 0, 0);
+                    }
             }
-            s4_t av = *(const s4_t *)(Dt + (rb * 16 + col) * a.NcP + 16 * s + 4 * kr);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 3; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int lm = rb * 16 + 4 * kr + r;
-            if (lm < Nm && inb) part[(long)lm * C + p] = acc[r];
+            if (rb < nrb && lm < Nm && inb) part[(long)lm * C + p] = acc[rb][r];
         }
-    }
 }
 
 // LDS of the FP map kernels: the class's table (padded row stride) and its
@@ -271,9 +293,10 @@ hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s)
     else if (mode == 1) dispatch_mmap<float>(a, grid, s);
     else {
         int NS16 = (a.Nm + 15) / 16;
-        if (NS16 == 1) hipLaunchKernelGGL(k_mmap_bf16<1>, grid, dim3(256), 0, s, a);
-        else if (NS16 == 2) hipLaunchKernelGGL(k_mmap_bf16<2>, grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(k_mmap_bf16<3>, grid, dim3(256), 0, s, a);
+        const size_t shm = (size_t)a.NcP * (a.NmP + 4) * 2 + (size_t)a.N * 4;
+        if (NS16 == 1) hipLaunchKernelGGL(k_mmap_bf16<1>, grid, dim3(256), shm, s, a);
+        else if (NS16 == 2) hipLaunchKernelGGL(k_mmap_bf16<2>, grid, dim3(256), shm, s, a);
+        else hipLaunchKernelGGL(k_mmap_bf16<3>, grid, dim3(256), shm, s, a);
     }
     return hipGetLastError();
 }
@@ -283,7 +306,7 @@ hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s)
     dim3 grid((unsigned)((a.C + 63) / 64), 2, a.B);
     if (mode == 0) dispatch_dmap<double>(a, grid, s);
     else if (mode == 1) dispatch_dmap<float>(a, grid, s);
-    else hipLaunchKernelGGL(k_dmap_bf16, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_dmap_bf16, grid, dim3(256), (size_t)a.NmP * (a.NcP + 4) * 2 + (size_t)a.N * 4, s, a);
     return hipGetLastError();
 }
 
