@@ -67,8 +67,8 @@ typedef struct dct_opts {
     int chunk;                /* iteration sets enqueued between host convergence polls (0 = 4) */
     int use_graph;            /* 1: capture `chunk` iteration sets once in a HIP graph and
                                  replay it until every right-hand side has converged */
-    int profile;              /* 1: time every sweep launch with HIP events (dct_stats);
-                                 ignored when use_graph = 1 */
+    int profile;              /* k >= 1: time every k-th sweep launch with HIP events
+                                 (dct_stats); ignored when use_graph = 1 */
     int keep_adjoint;         /* 1: keep every group's final angular flux and fixup pattern
                                  on the device so that dct_adjoint can follow this solve */
     int autotune;             /* 1: time the candidate sweep schedules (z layers per
@@ -98,12 +98,13 @@ typedef struct dct_stats {
     /* filled by the library */
     long long sweep_updates;  /* sum over sweeps of C * N (cell-angle updates, all groups, RHS) */
     int sweep_launches;       /* sweep kernel launches whose time is in sweep_ms */
-    double sweep_ms;          /* summed device time of sweep launches (profile = 1) */
+    double sweep_ms;          /* summed device time of the timed sweep launches (profile > 0) */
     double solve_ms;          /* device time of the whole dct_solve (HIP events) */
     int iteration_sets;       /* iteration launch sets enqueued (>= max over RHS of iterations) */
     int sweep_bk;             /* sweep schedule that ran: z layers per workgroup */
     int sweep_sync;           /* and coupling (1 LDS counters, 2 barriers, 3 pipelined blocks) */
     double tune_ms;           /* device time spent timing candidate schedules in this call */
+    long long sweep_launches_all; /* sweep kernel launches of the iteration sets (timed or not) */
 } dct_stats;
 
 /* Create a context on HIP device `device` using `stream` (a hipStream_t; NULL

@@ -953,7 +953,9 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     for (int g = 0; g < G; ++g) cap_sets += (o.fixed_iters ? o.fixed_iters[g] : o.max_iter) + 1;
     const int chunk = o.chunk > 0 ? o.chunk : 4;
     const bool profile = o.profile && !o.use_graph;
+    const int pevery = o.profile > 1 ? o.profile : 1;   // time every pevery-th sweep launch
     int nprof = 0;
+    long nsweeps = 0;
     auto enqueue_set = [&](hipStream_t es) -> hipError_t {
         hipError_t e = launch_transition(tr, is64, es);
         if (e != hipSuccess) return e;
@@ -961,7 +963,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
         for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
             sw.diag = d;
-            if (profile) {
+            const bool timed = profile && nsweeps++ % pevery == 0;
+            if (timed) {
                 while ((int)ctx->evpool.size() < 2 * (nprof + 1)) {
                     hipEvent_t ev;
                     if ((e = hipEventCreate(&ev)) != hipSuccess) return e;
@@ -970,7 +973,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 if ((e = hipEventRecord(ctx->evpool[2 * nprof], es)) != hipSuccess) return e;
             }
             if ((e = launch_sweep(sw, is64, es, ctx->sweep_seq++)) != hipSuccess) return e;
-            if (profile) {
+            if (timed) {
                 if ((e = hipEventRecord(ctx->evpool[2 * nprof + 1], es)) != hipSuccess) return e;
                 ++nprof;
             }
@@ -1087,6 +1090,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
         stats->sweep_ms = swms;
         stats->sweep_launches = nprof;
+        stats->sweep_launches_all = (long long)sets * (sw.pipe ? 1 : pl.ndiag);
         stats->iteration_sets = (int)sets;
         stats->sweep_bk = pl.BK;
         stats->sweep_sync = ctx->last_sync;

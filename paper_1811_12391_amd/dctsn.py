@@ -47,7 +47,7 @@ class dct_stats(ct.Structure):
                 ("balance", ct.POINTER(ct.c_double)), ("sweep_updates", ct.c_longlong),
                 ("sweep_launches", ct.c_int), ("sweep_ms", ct.c_double), ("solve_ms", ct.c_double),
                 ("iteration_sets", ct.c_int), ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int),
-                ("tune_ms", ct.c_double)]
+                ("tune_ms", ct.c_double), ("sweep_launches_all", ct.c_longlong)]
 
 
 _lib = None
@@ -165,6 +165,7 @@ class SolveStats:
     sweep_bk: int
     sweep_sync: int
     tune_ms: float
+    sweep_launches_all: int = 0
 
 
 def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=None, fixup=True,
@@ -203,7 +204,7 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     ok = (DCT_OK, DCT_ENOTCONV) if allow_notconv else (DCT_OK,)
     rc = _chk(h, lib().dct_solve(h, ct.byref(o), ct.byref(st)), ok)
     return SolveStats(rc, iters, eps, bal, st.sweep_updates, st.sweep_launches, st.sweep_ms, st.solve_ms,
-                      st.iteration_sets, st.sweep_bk, st.sweep_sync, st.tune_ms)
+                      st.iteration_sets, st.sweep_bk, st.sweep_sync, st.tune_ms, st.sweep_launches_all)
 
 
 def dose(h, B, G, C, *, summed=False, want_phi=False):
