@@ -180,7 +180,7 @@ def main():
                    "voxels": C, "groups": G, "directions": N, "legendre_order": prob.L, "sources": prob.B,
                    "precision": best},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best) if args.workload == "c2" else None,
                      "kernel": "k_sweep", "avg_launch_ms": avg_launch_ms,
                      "bytes_per_launch": bytes_per_solve / launches},
         "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()},
