@@ -129,7 +129,8 @@ def main():
             "iteration_sets": int(stats[-1].iteration_sets),
             "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
                                "wave_coupling": {1: "lds_counters", 2: "barrier",
-                                                  3: "pipelined_blocks"}[int(stats[-1].sweep_sync)]},
+                                                  3: "pipelined_blocks", 4: "layered_waves_4",
+                                                  5: "layered_waves_2"}[int(stats[-1].sweep_sync)]},
             "dose": dose,
         }
         _log(f"[bench] {tag}: {res['ms_per_step']:.2f} ms/solve wall, {res['device_ms_per_solve']:.2f} ms device, "

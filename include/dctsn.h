@@ -79,7 +79,11 @@ typedef struct dct_opts {
                                  a workgroup, 2 = one barrier per step, 3 = as 2 with all
                                  blocks of a sweep in one launch, handing block faces over
                                  as they are produced (needs >= 2 blocks of >= 2 z layers,
-                                 otherwise runs as 1); 0 = tuned or 1 */
+                                 otherwise runs as 1), 4 / 5 = layered waves: every wave
+                                 sweeps 4 / 2 z layers as a skewed pipeline in registers,
+                                 one barrier per step (needs one block: ny <= 64, nz <= 16,
+                                 sweep_bk >= nz; otherwise runs as 2; the transposed sweeps
+                                 of dct_adjoint then use 2); 0 = tuned or 1 */
     int superpose;            /* sources per right-hand side S (0 or 1: one each).  With
                                  S > 1 the B sources of dct_set_source form B / S right-hand
                                  sides of S consecutive sources; each is solved once with
@@ -102,7 +106,8 @@ typedef struct dct_stats {
     double solve_ms;          /* device time of the whole dct_solve (HIP events) */
     int iteration_sets;       /* iteration launch sets enqueued (>= max over RHS of iterations) */
     int sweep_bk;             /* sweep schedule that ran: z layers per workgroup */
-    int sweep_sync;           /* and coupling (1 LDS counters, 2 barriers, 3 pipelined blocks) */
+    int sweep_sync;           /* and coupling (1 LDS counters, 2 barriers, 3 pipelined blocks,
+                                 4 / 5 layered waves of 4 / 2 z layers) */
     double tune_ms;           /* device time spent timing candidate schedules in this call */
     long long sweep_launches_all; /* sweep kernel launches of the iteration sets (timed or not) */
 } dct_stats;

@@ -274,6 +274,7 @@ struct SweepArgs {
     unsigned long long *hint; // [B*N][nblk] progress of each pipelined block: (launch tag << 32) | steps done
     unsigned seq;             // host launch counter, part of the launch tag
     int *err;                 // set to non-zero when a bounded wait overflowed
+    int layers;               // > 1: every wave sweeps this many z layers (single block, forward only)
 };
 
 struct AdjTransArgs {

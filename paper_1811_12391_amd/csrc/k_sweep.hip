@@ -542,6 +542,181 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     }
 }
 
+// Layered waves (single block, forward sweep): every wave owns ZL consecutive
+// z layers and sweeps them as a skewed pipeline in registers.  Layer z of
+// wave w handles reflected x index t - l - (ZL w + z) at step t, the same
+// diagonal as one wave per layer, so its z inflow is layer z-1's outflow of
+// the previous step (a register) and only the bottom layer of a wave takes
+// its inflow from the wave below through LDS.  The ZL cell updates of a step
+// are independent, so a wave hides its own latency with them instead of
+// relying on several waves per SIMD; one barrier per step couples the
+// (fewer) waves.  Each cell's arithmetic is the same as in k_sweep, so the
+// results are bitwise the same.
+template <typename T, int ZL, int PF, int MODE>
+__global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
+{
+    static_assert(MODE != 2, "the transposed sweep uses k_sweep");
+    constexpr bool KEEP = MODE == 1;
+    constexpr unsigned TS = sizeof(T);
+    __shared__ T zbuf[2][17][64];                            // row w + 1: top layer of wave w; row 0: boundary
+    __shared__ double red[3][16];
+    const int item = blockIdx.x;
+    const int b = item / a.N;
+    const int n = item - b * a.N;
+    if (a.state[b].finished) return;
+    const int g = eff_group(a.state[b].g, a.G, a.reverse);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const long C = a.C;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nwv = blockDim.x >> 6;
+    const double ox = a.dirs[3 * n], oy = a.dirs[3 * n + 1], oz = a.dirs[3 * n + 2];
+    const bool sx = ox > 0, sy = oy > 0, sz = oz > 0;
+    const int cls = dir_class(ox, oy);
+    const T cx = (T)(2.0 * fabs(ox) / a.dx), cy = (T)(2.0 * fabs(oy) / a.dy), cz = (T)(2.0 * fabs(oz) / a.dz);
+    const T csum = cx + cy + cz;
+    const bool lv = l < ny;                                  // one y block: ny <= 64
+    const int j = lv ? (sy ? l : ny - 1 - l) : 0;
+    const int jm = j % nx;
+    const rsrc_t rq = mk_rsrc((const T *)a.q + (long)item * C, C * TS);
+    const rsrc_t rpsi = mk_rsrc((T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs + n) * C, C * TS);
+    const rsrc_t rmask = mk_rsrc(KEEP && a.mask ? a.mask + (((long)b * a.G + g) * a.N + n) * C : nullptr, C);
+    const rsrc_t rsg = mk_rsrc((const T *)a.sigc + ((long)cls * a.G + g) * C, C * TS);
+    const T bc = a.inflow ? (T)a.inflow[g] : (T)0;
+    const int fixup = a.fixup;
+    const int NT = nx + min(ny, 64) + nz - 2;
+    const int NTp = ((NT + PF - 1) / PF) * PF;
+    const int dr = sx ? 1 : -1;
+    const int dny = sx ? ny : -ny;
+    const int wrap_at_r = (sx ? nx : -1) * ny, wrap_to_r = (sx ? 0 : nx - 1) * ny;
+    const int rstart = rot_row(cls, sx ? 0 : nx - 1, jm, nx);
+    // per layer: validity, lane part of the offsets, start step, wave-uniform
+    // row offset of the prefetched step (step -1 first)
+    bool vz[ZL];
+    int rowbase[ZL], t0[ZL], sre[ZL];
+    bool zlast[ZL];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z) {
+        const int kp = w * ZL + z;
+        vz[z] = lv && kp < nz;
+        const int k = vz[z] ? (sz ? kp : nz - 1 - kp) : 0;
+        rowbase[z] = k * nx * ny + j;
+        t0[z] = l + kp;
+        sre[z] = __builtin_amdgcn_readfirstlane((((rstart - dr * (t0[z] + 1)) % nx) + nx) % nx) * ny;
+        zlast[z] = kp == nz - 1;
+    }
+    if (w == 0) zbuf[0][0][l] = zbuf[1][0][l] = bc;
+    __syncthreads();
+    T qr[ZL][PF], sr[ZL][PF];
+    unsigned sbr[ZL][PF], ser[KEEP ? ZL : 1][KEEP ? PF : 1];
+    bool actr[ZL][PF];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z)
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            qr[z][u] = sr[z][u] = (T)0;
+            sbr[z][u] = DCT_OOB;
+            if (KEEP) ser[KEEP ? z : 0][KEEP ? u : 0] = DCT_OOB;
+            actr[z][u] = false;
+        }
+    T ycar[ZL], xo[ZL], yo[ZL], zo[ZL], lyv[ZL];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z) {
+        ycar[z] = xo[z] = bc;
+        yo[z] = zo[z] = lyv[z] = (T)0;
+    }
+    double lzv = 0.0;
+    for (int tb = -PF; tb < NTp; tb += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int t = tb + u;
+            // z inflows of this step (outflows of the previous step)
+            T zin[ZL];
+            zin[0] = zbuf[(t + 1) & 1][w][l];
+#pragma unroll
+            for (int z = 1; z < ZL; ++z) zin[z] = zo[z - 1];
+            __builtin_amdgcn_sched_barrier(0);
+            // operands of step t + PF - 1 into the slot step t - 1 consumed
+            {
+                const int tp = t + PF - 1;
+                const int ps = (u + PF - 1) % PF;
+#pragma unroll
+                for (int z = 0; z < ZL; ++z) {
+                    const bool inp = vz[z] && (unsigned)(tp - t0[z]) < (unsigned)nx;
+                    const unsigned pb = inp ? (unsigned)(rowbase[z] + sre[z]) * TS : DCT_OOB;
+                    sbr[z][ps] = pb;
+                    actr[z][ps] = inp;
+                    if (KEEP) ser[KEEP ? z : 0][KEEP ? ps : 0] = inp ? (unsigned)(rowbase[z] + sre[z]) : DCT_OOB;
+                    qr[z][ps] = bld<T>(rq, pb);
+                    sr[z][ps] = bld<T>(rsg, pb);
+                    sre[z] += dny;
+                    sre[z] = sre[z] == wrap_at_r ? wrap_to_r : sre[z];
+                }
+            }
+            // everything except the z term, for every layer
+            T a0[ZL], b0[ZL], yin[ZL], xin[ZL];
+#pragma unroll
+            for (int z = 0; z < ZL; ++z) {
+                ycar[z] = dpp_shift_up_or<T>(yo[z], ycar[z]);
+                yin[z] = ycar[z];
+                xin[z] = xo[z];
+                const T y0 = rcp_nr(sr[z][u] + csum);
+                a0[z] = (qr[z][u] + cx * xin[z] + cy * yin[z]) * y0;
+                b0[z] = cz * y0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // the ZL cell updates (independent of each other)
+#pragma unroll
+            for (int z = 0; z < ZL; ++z) {
+                const bool act = actr[z][u];
+                Cell4<T> c;
+                c.pc = fma(b0[z], zin[z], a0[z]);
+                c.xo = c.pc + c.pc - xin[z];
+                c.yo = c.pc + c.pc - yin[z];
+                c.zo = c.pc + c.pc - zin[z];
+                c.fixed = 0;
+                if (fixup && act && fmin(c.xo, fmin(c.yo, c.zo)) < (T)0)
+                    c = dd_fixup<T>(qr[z][u], sr[z][u], cx, cy, cz, xin[z], yin[z], zin[z], c);
+                if (z == ZL - 1) zbuf[t & 1][w + 1][l] = c.zo;   // z handoff to the wave above
+                bst(rpsi, sbr[z][u], c.pc);
+                if (KEEP)
+                    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)c.fixed, rmask, ser[KEEP ? z : 0][KEEP ? u : 0], 0, 0);
+                lyv[z] += act ? c.yo : (T)0;
+                if (zlast[z]) lzv += act ? (double)c.zo : 0.0;
+                xo[z] = act ? c.xo : xo[z];
+                yo[z] = c.yo;
+                zo[z] = c.zo;
+            }
+            __syncthreads();
+        }
+    }
+    // boundary outflow sums (particle balance): last x outflow of every row,
+    // y outflows of the last row, z outflows of the top layer
+    const bool ylast = l == ny - 1;
+    double lx = 0.0, ly = 0.0;
+#pragma unroll
+    for (int z = 0; z < ZL; ++z) {
+        lx += vz[z] ? (double)xo[z] : 0.0;
+        ly += (vz[z] && ylast) ? (double)lyv[z] : 0.0;
+    }
+    double lz = lzv;
+    for (int o = 32; o > 0; o >>= 1) {
+        lx += __shfl_down(lx, o, 64);
+        ly += __shfl_down(ly, o, 64);
+        lz += __shfl_down(lz, o, 64);
+    }
+    if (l == 0) {
+        red[0][w] = lx;
+        red[1][w] = ly;
+        red[2][w] = lz;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int q = 0; q < nwv; ++q) s += red[threadIdx.x][q];
+        a.leak_part[(long)item * a.nblk * 3 + threadIdx.x] = s;
+    }
+}
+
 hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
 {
     a.seq = seq;
@@ -558,6 +733,20 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
         grid = dim3((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
     }
     const int mode = a.adjoint ? 2 : (a.mask ? 1 : 0);
+    if ((a.layers == 2 || a.layers == 4) && !multi && mode != 2 && a.ny <= 64 && a.nz <= 16) {
+        const int nwv = (a.nz + a.layers - 1) / a.layers;
+        const dim3 lgrid((unsigned)(a.B * a.N)), lblock(64 * nwv);
+#define DCT_LW(T, ZL, MD) hipLaunchKernelGGL((k_sweep_lw<T, ZL, 8, MD>), lgrid, lblock, 0, s, a)
+        if (is_f64) {
+            if (a.layers == 4) { if (mode == 1) DCT_LW(double, 4, 1); else DCT_LW(double, 4, 0); }
+            else { if (mode == 1) DCT_LW(double, 2, 1); else DCT_LW(double, 2, 0); }
+        } else {
+            if (a.layers == 4) { if (mode == 1) DCT_LW(float, 4, 1); else DCT_LW(float, 4, 0); }
+            else { if (mode == 1) DCT_LW(float, 2, 1); else DCT_LW(float, 2, 0); }
+        }
+#undef DCT_LW
+        return hipGetLastError();
+    }
 #define DCT_LAUNCH_SWEEP(T, PF, M, S, MD, P) hipLaunchKernelGGL((k_sweep<T, PF, M, S, MD, P>), grid, block, 0, s, a)
 #define DCT_LAUNCH_SWEEP_M(T, PF, M, S, P)                   \
     do {                                                     \

@@ -455,7 +455,7 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
                                              std::to_string(std::max(pl.Nc[0], pl.Nc[1])) + ")");
     }
     if (o.sweep_bk < 0 || o.sweep_bk > 16) return fail(ctx, DCT_EINVAL, "solve: sweep_bk must be in [0, 16]");
-    if (o.sweep_sync < 0 || o.sweep_sync > 3) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 3]");
+    if (o.sweep_sync < 0 || o.sweep_sync > 5) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 5]");
     if (o.superpose < 0 || (o.superpose > 1 && ctx->B % o.superpose != 0))
         return fail(ctx, DCT_EINVAL, "solve: superpose must divide the number of sources (" + std::to_string(ctx->B) + ")");
     if (o.superpose > 1 && o.keep_adjoint)
@@ -797,6 +797,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     sw.fixup = o.fixup;
     sw.sync = o.sweep_sync == 2 ? 0 : 1;
     sw.pipe = 0;
+    sw.layers = 0;
     sw.yface_p = d_yfp;
     sw.zface_p = d_zfp;
     sw.hint = (unsigned long long *)d_hint;
@@ -846,11 +847,15 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // ---------------- sweep schedule: given, cached, or timed now
     // schedule = (z layers per workgroup, coupling): coupling 1 = LDS progress
     // counters between the waves of a workgroup, 2 = one barrier per step,
-    // 3 = as 2 with every block of a sweep in one launch (pipelined blocks)
+    // 3 = as 2 with every block of a sweep in one launch (pipelined blocks),
+    // 4 / 5 = layered waves (every wave sweeps 4 / 2 z layers; one block,
+    // ny <= 64 and nz <= 16, forward sweeps)
     double tune_ms = 0.0;
+    const bool layered_ok = ny <= 64 && nz <= 16;
     auto set_coupling = [&](int cpl) {
-        sw.sync = cpl != 2;
+        sw.sync = cpl == 1;
         sw.pipe = cpl == 3;
+        sw.layers = (cpl == 4 && layered_ok) ? 4 : ((cpl == 5 && layered_ok) ? 2 : 0);
     };
     auto pipe_ready = [&]() -> int {
         // faces handed over inside a launch start out empty (all bits set)
@@ -896,9 +901,10 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 for (int cb : bks) {
                     const bool multi = (ny + 63) / 64 > 1 || (nz + cb - 1) / cb > 1;
-                    for (int cc : {1, 2, 3}) {
+                    for (int cc : {1, 2, 3, 4, 5}) {
                         if (!free_cpl && cc != cpl) continue;
                         if (cc == 3 && (!multi || cb < 2)) continue;   // pipelining needs several blocks
+                        if (cc >= 4 && (!layered_ok || cb != std::min(16, nz))) continue;   // one block of every layer
                         cands.push_back({cb, cc});
                     }
                 }
@@ -939,6 +945,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
         apply_blocks(bk);
         if (cpl == 3 && (pl.nblk == 1 || pl.BK < 2)) cpl = 1;   // one block (or 1-layer blocks): not pipelined
+        if (cpl >= 4 && (!layered_ok || pl.nblk != 1)) cpl = 2;   // layered waves need one block
         set_coupling(cpl);
         if (cpl == 3) {
             int r = pipe_ready();
@@ -1433,8 +1440,9 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     sw.state = (const RhsState *)B_("state");
     sw.inflow = nullptr;
     sw.fixup = 0;
-    sw.sync = ctx->last_sync != 2;
+    sw.sync = ctx->last_sync == 1;
     sw.pipe = ctx->last_sync == 3;
+    sw.layers = 0;                     // transposed sweeps run on k_sweep (barrier coupling for layered schedules)
     sw.yface_p = B_("yfp");
     sw.zface_p = B_("zfp");
     sw.hint = (unsigned long long *)B_("hint");

@@ -199,6 +199,22 @@ def test_autograd_wrapper():
         s.close()
 
 
+def test_adjoint_after_layered_forward():
+    """A forward solve on layered waves keeps the same fixup sets, and the
+    adjoint that follows (transposed sweeps on the barrier coupling) matches
+    the oracle."""
+    prob, roi, fi, fa, ref = _oracle_adjoint("tiny_abd")
+    s = dctsn.Solver(prob)
+    try:
+        st = s.solve(precision="fp64", fixed_iters=fi, keep_adjoint=True, sweep_bk=16, sweep_sync=4)
+        assert st.sweep_sync == 4
+        a = s.adjoint(roi, fixed_iters=fa)
+    finally:
+        s.close()
+    assert rel(a.d_density, ref.d_density) < 1e-9
+    assert rel(a.d_group_w, ref.d_group_w) < 1e-9
+
+
 @pytest.mark.parametrize("bk,sync", [(5, 3), (4, 2)])
 def test_adjoint_other_schedules(bk, sync):
     """The adjoint sweeps reuse the forward solve's schedule (here pipelined

@@ -267,6 +267,8 @@ def test_sweep_schedules_are_bitwise_identical(name):
     ref_st, ref = _dose_with(prob, precision="fp64", tol=1e-8)
     _, ref32 = _dose_with(prob, precision="fp32", tol=1e-6)
     cases = [(bk, sync) for bk in (16, 5, 2, 1) for sync in (1, 2)] + [(5, 3), (2, 3)]
+    if name == "tiny_abd":
+        cases += [(16, 4), (16, 5)]   # layered waves (one block: ny <= 64, nz <= 16)
     for bk, sync in cases:
         _say(f"[schedule] {name} sweep_bk={bk} sweep_sync={sync}")
         for prec in ("fp64", "fp32"):
@@ -278,6 +280,25 @@ def test_sweep_schedules_are_bitwise_identical(name):
                 assert np.array_equal(d, ref)
             else:
                 assert np.array_equal(d, ref32)
+
+
+def test_layered_waves_c2_bitwise_and_fallback():
+    """Layered waves on the full 64x64x16 grid (full 64-lane waves, 4 and 8
+    waves per workgroup) give the barrier schedule's dose bit for bit, also
+    while keeping the fixup sets for the adjoint; a grid with more than 64 y
+    rows falls back to the barrier coupling."""
+    prob = I.make_problem("c2")
+    fi = np.full(prob.G, 2, dtype=np.int32)
+    st0, ref = _dose_with(prob, precision="fp32", fixed_iters=fi, sweep_bk=16, sweep_sync=2)
+    for sync in (4, 5):
+        for keep in (False, True):
+            _say(f"[layered] c2 fp32 sweep_sync={sync} keep_adjoint={keep}")
+            st, d = _dose_with(prob, precision="fp32", fixed_iters=fi, sweep_bk=16, sweep_sync=sync,
+                               keep_adjoint=keep)
+            assert st.sweep_sync == sync
+            assert np.array_equal(d, ref)
+    st, _ = _dose_with(_multiblock_problem(), precision="fp64", tol=1e-8, sweep_bk=16, sweep_sync=4)
+    assert st.sweep_sync == 2
 
 
 def test_graph_replay_matches_stream_launches():
@@ -307,7 +328,7 @@ def test_autotune_picks_a_schedule_and_caches_it():
     try:
         st1 = s.solve(precision="fp32", tol=1e-6, autotune=True)
         _say(f"[autotune] chose bk={st1.sweep_bk} sync={st1.sweep_sync} in {st1.tune_ms:.2f} ms")
-        assert st1.tune_ms > 0 and 1 <= st1.sweep_bk <= 16 and st1.sweep_sync in (1, 2, 3)
+        assert st1.tune_ms > 0 and 1 <= st1.sweep_bk <= 16 and st1.sweep_sync in (1, 2, 3, 4, 5)
         d1 = s.dose()
         st2 = s.solve(precision="fp32", tol=1e-6, autotune=True)
         assert st2.tune_ms == 0 and (st2.sweep_bk, st2.sweep_sync) == (st1.sweep_bk, st1.sweep_sync)
