@@ -226,7 +226,8 @@ struct CombArgs {
     int max_iter;
     int nblocks_per_b;
     int reverse;              // groups run from G-1 down to 0
-    unsigned *cnt_mom;        // [B][Nm][32] per-moment completion counters, one per 128-byte line
+    unsigned *cnt_mom;        // [B][Nm][32] completion counters of the moment groups, one per 128-byte line
+    int mpw;                  // moments per workgroup (>= 1)
 };
 
 struct MapArgs {

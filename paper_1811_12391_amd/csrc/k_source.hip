@@ -357,7 +357,11 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     const long C = a.geo.C;
     const int G = a.G, Nm = a.Nm, L = a.L;
     const int nslj = (ny + 15) >> 4;
-    const int lm = blockIdx.z;
+    // moments lm_lo .. lm_hi - 1 of this workgroup, one after the other
+    // (several per workgroup keep the slab's material and density in the
+    // CU's caches for all of them)
+    const int mg = blockIdx.z, nmg = gridDim.z;
+    const int lm_lo = mg * a.mpw, lm_hi = min(Nm, lm_lo + a.mpw);
     const int nslab = a.geo.nz * nslj;
     const bool live = true;
     const int k = blockIdx.x / nslj;
@@ -367,23 +371,24 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
     // the 16 rows when pitch -+ 1 are odd
     const int pitch = (nx | 1) + 1;
     const int tile_n = 16 * nx;
+    T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
+    double dmax = 0.0, fmax_ = 0.0;
+    // self-scatter moments of group g per material, for the next source
+    __shared__ double ssg[DCT_MAXMAT * (DCT_MAXL + 1)];
+    if (E > 0 && (int)threadIdx.x < a.M * (L + 1)) {
+        const int mm = threadIdx.x / (L + 1), ll = threadIdx.x - mm * (L + 1);
+        ssg[threadIdx.x] = a.ss[(((long)mm * (L + 1) + ll) * G + g) * G + g];
+    }
+    for (int lm = lm_lo; lm < lm_hi; ++lm) {
     const int l = l_of(lm);
     const T *partA = (const T *)a.part + ((long)b * Nm + lm) * C;
     const T *partB = (const T *)a.part + (((long)a.B + b) * Nm + lm) * C;
     T *QA = (T *)a.Qc + ((long)b * Nm + lm) * C;
     T *QB = (T *)a.Qc + (((long)a.B + b) * Nm + lm) * C;
     const T *ext = (const T *)a.ext + ((long)b * Nm + lm) * C;
-    T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
-    double dmax = 0.0, fmax_ = 0.0;
     if (E > 0) {
         constexpr int EE = E > 0 ? E : 1;
         constexpr unsigned TS = sizeof(T);
-        // self-scatter moments of group g per material, for the next source
-        __shared__ double ssg[DCT_MAXMAT * (DCT_MAXL + 1)];
-        if ((int)threadIdx.x < a.M * (L + 1)) {
-            const int mm = threadIdx.x / (L + 1), ll = threadIdx.x - mm * (L + 1);
-            ssg[threadIdx.x] = a.ss[(((long)mm * (L + 1) + ll) * G + g) * G + g];
-        }
         // every load is issued up front through descriptors; elements outside
         // the tile use an out-of-range offset (no branch, no memory access)
         const rsrc_t rA = mk_rsrc(partA, C * TS), rB = mk_rsrc(partB, C * TS);
@@ -506,13 +511,14 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
         }
         __syncthreads();
     }
+    }   // moments of the workgroup
     double dm = 0.0, fm = 0.0;
-    if (lm == 0) {
+    if (lm_lo == 0) {
         dm = block_max(dmax, red);
         fm = block_max(fmax_, red);
     }
     if (threadIdx.x == 0) {
-        if (lm == 0 && live) {
+        if (lm_lo == 0 && live) {
             atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
             atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
         }
@@ -521,7 +527,7 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
         // moment's counter (its own cache line), the last of them on the
         // right-hand side's counter, so no counter takes an atomic from every
         // workgroup; the last block of the last moment closes the iteration
-        unsigned *cm = a.cnt_mom + ((long)b * Nm + lm) * 32;
+        unsigned *cm = a.cnt_mom + ((long)b * Nm + mg) * 32;
         const unsigned prev1 = live ? atomicAdd(cm, 1u) : 0u;
         unsigned prev = 0u;
         if (live && prev1 == (unsigned)nslab - 1) {
@@ -529,7 +535,7 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             wait_own_memory_ops();
             prev = atomicAdd(&st->cnt_combine, 1u) + 1u;
         }
-        if (prev == (unsigned)Nm) {
+        if (prev == (unsigned)nmg) {
             wait_own_memory_ops();
             double num = __longlong_as_double((long long)atomicAdd(&st->eps_num, 0ull));
             double den = __longlong_as_double((long long)atomicAdd(&st->eps_den, 0ull));
@@ -614,7 +620,7 @@ hipError_t launch_qinit(const CombArgs &a, int is_f64, hipStream_t s)
 hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s)
 {
     const int nslj = (a.geo.ny + 15) >> 4;
-    dim3 grid((unsigned)(a.geo.nz * nslj), a.B, a.Nm);
+    dim3 grid((unsigned)(a.geo.nz * nslj), a.B, (a.Nm + a.mpw - 1) / a.mpw);
     size_t shm = (size_t)16 * ((a.geo.nx | 1) + 1) * (is_f64 ? 8 : 4);
     const int per = (16 * a.geo.nx + 255) / 256;   // tile elements per thread
 #define DCT_LAUNCH_COMBINE(T)                                                                          do {                                                                                                   if (per <= 1) hipLaunchKernelGGL((k_combine<T, 1>), grid, dim3(256), shm, s, a);                  else if (per <= 2) hipLaunchKernelGGL((k_combine<T, 2>), grid, dim3(256), shm, s, a);             else if (per <= 4) hipLaunchKernelGGL((k_combine<T, 4>), grid, dim3(256), shm, s, a);             else if (per <= 8) hipLaunchKernelGGL((k_combine<T, 8>), grid, dim3(256), shm, s, a);             else hipLaunchKernelGGL((k_combine<T, 0>), grid, dim3(256), shm, s, a);                       } while (0)

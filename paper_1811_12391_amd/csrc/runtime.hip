@@ -822,6 +822,9 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     cb.iters = (int *)d_iters;
     cb.eps = (double *)d_eps;
     cb.cnt_mom = (unsigned *)d_ccnt;
+    // several moments per combine workgroup once there are workgroups to spare
+    // (the slab's material and density then stay in the CU's caches)
+    cb.mpw = (long)nz * ((ny + 15) / 16) * B * Nm >= 8192 ? 4 : 1;
     cb.fixed_iters = (const int *)d_fixed;
     cb.tol = o.tol;
     cb.max_iter = o.max_iter;
@@ -1467,6 +1470,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     cb.iters = (int *)d_ait;
     cb.eps = (double *)d_aeps;
     cb.cnt_mom = (unsigned *)B_("ccnt");
+    cb.mpw = (long)nz * ((ny + 15) / 16) * B * Nm >= 8192 ? 4 : 1;
     cb.fixed_iters = o.fixed_iters ? (const int *)d_fix : nullptr;
     cb.tol = o.tol;
     cb.max_iter = o.max_iter;
