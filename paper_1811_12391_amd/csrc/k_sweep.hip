@@ -312,6 +312,44 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     int known_prev = 0, known_next = 0, spins = 0;   // wave-uniform
     typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(rh, 0, 0, 0)) u64v;
     u64v hz = {0u, 0u}, hy = {0u, 0u};
+    // prefetch of step t + PF - 1 into the ring slot that step t - 1 consumed
+    // (u = t mod PF, a constant once the step loop is unrolled)
+    auto prefetch = [&](const int t, const int u) __attribute__((always_inline)) {
+        const int tp = t + PF - 1;
+        const int ps = (u + PF - 1) % PF;           // constant once the step loop is unrolled
+        const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
+        // idle lanes sit on their first or last row, away from the
+        // active ones: an out-of-range offset keeps their loads off
+        // the memory system (they return 0, never used)
+        const unsigned pp = inp ? (unsigned)(rowbase + sre) : DCT_OOB;
+        const unsigned pb = inp ? lane_b + (unsigned)sre * TS : DCT_OOB;
+        sbr[ps] = pb;
+        actr[ps] = inp;
+        if (KEEP) ser[KEEP ? ps : 0] = pp;
+        qr[ps] = bld<T>(rq, pb);
+        sr[ps] = bld<T>(rsg, pb);
+        if (ADJ) fr[ADJ ? ps : 0] = __builtin_amdgcn_raw_buffer_load_b8(rmask, pp, 0, 0);
+        if (MULTI) {
+            // block faces of step t + FD - 1 (only the lanes that take
+            // a block face load one) into the slot consumed at that
+            // step PF steps earlier
+            const int tf = t + FD - 1;
+            const bool inf = valid && (unsigned)(tf - t0l) < (unsigned)nx;
+            const int ipn = tf - t0l;
+            const unsigned yo_off = (inf && ytaker) ? (unsigned)(ipn + nx * kp) * TS : DCT_OOB;
+            const unsigned zo_off = (inf && ztaker) ? (unsigned)((ipn + l) * 64 + l) * TS : DCT_OOB;
+            const int fs = (u + FD - 1) % PF;
+            if (PIPE) {
+                yr[MULTI ? fs : 0] = bld_dev<T>(ryi, yo_off);
+                zr[MULTI ? fs : 0] = bld_dev<T>(rzi, zo_off);
+            } else {
+                yr[MULTI ? fs : 0] = bld<T>(ryi, yo_off);
+                zr[MULTI ? fs : 0] = bld<T>(rzi, zo_off);
+            }
+        }
+        sre += dny;
+        sre = sre == wrap_at_r ? wrap_to_r : sre;
+    };
     for (int tb = -PF; tb < NTp; tb += PF) {
         if (PIPE && (bj > 0 || bk > 0)) {
             // this group of steps loads faces up to step tb + PF + FD - 2; the
@@ -334,6 +372,18 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             // read ahead for the next group's check
             hz = __builtin_amdgcn_raw_buffer_load_b64(rh, hoff_z, 0, 16);
             hy = __builtin_amdgcn_raw_buffer_load_b64(rh, hoff_y, 0, 16);
+        }
+        if (!MULTI && tb < 0) {
+            // the first PF steps: every lane is idle, only the prefetches run
+            // (each with a store that goes nowhere, so the loop is entered
+            // with the memory-counter state of the steady state)
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                prefetch(tb + u, u);
+                bst(rpsi, DCT_OOB + 64u * u, (T)0);
+                if (KEEP) __builtin_amdgcn_raw_buffer_store_b8((unsigned char)0, rmask, DCT_OOB + 64u * u, 0, 0);
+            }
+            continue;
         }
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -397,43 +447,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 zin = (w > 0) ? zbuf[(t + 1) & 1][w > 0 ? w - 1 : 0][l] : zface_in;
             }
             __builtin_amdgcn_sched_barrier(0);
-            // prefetch step t + PF - 1 into the slot that step t - 1 consumed
-            {
-                const int tp = t + PF - 1;
-                const int ps = (u + PF - 1) % PF;           // constant once the step loop is unrolled
-                const bool inp = valid && (unsigned)(tp - t0l) < (unsigned)nx;
-                // idle lanes sit on their first or last row, away from the
-                // active ones: an out-of-range offset keeps their loads off
-                // the memory system (they return 0, never used)
-                const unsigned pp = inp ? (unsigned)(rowbase + sre) : DCT_OOB;
-                const unsigned pb = inp ? lane_b + (unsigned)sre * TS : DCT_OOB;
-                sbr[ps] = pb;
-                actr[ps] = inp;
-                if (KEEP) ser[KEEP ? ps : 0] = pp;
-                qr[ps] = bld<T>(rq, pb);
-                sr[ps] = bld<T>(rsg, pb);
-                if (ADJ) fr[ADJ ? ps : 0] = __builtin_amdgcn_raw_buffer_load_b8(rmask, pp, 0, 0);
-                if (MULTI) {
-                    // block faces of step t + FD - 1 (only the lanes that take
-                    // a block face load one) into the slot consumed at that
-                    // step PF steps earlier
-                    const int tf = t + FD - 1;
-                    const bool inf = valid && (unsigned)(tf - t0l) < (unsigned)nx;
-                    const int ipn = tf - t0l;
-                    const unsigned yo_off = (inf && ytaker) ? (unsigned)(ipn + nx * kp) * TS : DCT_OOB;
-                    const unsigned zo_off = (inf && ztaker) ? (unsigned)((ipn + l) * 64 + l) * TS : DCT_OOB;
-                    const int fs = (u + FD - 1) % PF;
-                    if (PIPE) {
-                        yr[MULTI ? fs : 0] = bld_dev<T>(ryi, yo_off);
-                        zr[MULTI ? fs : 0] = bld_dev<T>(rzi, zo_off);
-                    } else {
-                        yr[MULTI ? fs : 0] = bld<T>(ryi, yo_off);
-                        zr[MULTI ? fs : 0] = bld<T>(rzi, zo_off);
-                    }
-                }
-                sre += dny;
-                sre = sre == wrap_at_r ? wrap_to_r : sre;
-            }
+            prefetch(t, u);
             // y inflow: lane l-1's outflow of the previous step; lane 0 takes the
             // boundary / block face value through the DPP "old" operand
             T yin;
