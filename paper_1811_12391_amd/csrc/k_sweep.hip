@@ -49,27 +49,41 @@ template <typename T> __device__ inline T qdiv(T n, T d) { return qdiv_y(n, d, r
 // negative face appears.  Returns (psi_c, out_x, out_y, out_z) by value.
 template <typename T> struct Cell4 { T pc, xo, yo, zo; int fixed; };
 
+// q / d inside the fixup: FP64 as qdiv; FP32 takes the hardware reciprocal
+// alone (the plain update already does), which keeps the pass short
+__device__ inline double fix_div(double n, double d) { return qdiv(n, d); }
+__device__ inline float fix_div(float n, float d) { return n * rcp_nr(d); }
+
+// Every pass is free of branches: the open / closed state of a face is a
+// multiplier e_a (1 open, 0 closed), so the balance is
+//   psi_c (sigma + sum_a e_a c_a) = q + sum_a (1 + e_a) (c_a / 2) in_a
+// with c_a pre-doubled, and a closed face's outflow e_a (2 psi_c - in_a) is 0.
+// Only an open face can test negative (a closed one holds 0), so a pass
+// closes exactly the new negative faces.  The loop ends for a lane as soon
+// as it has none; the wave runs a pass while any lane needs it.
 template <typename T>
 __device__ __forceinline__ Cell4<T> dd_fixup(T qv, T sv, T cx, T cy, T cz, T xin, T yin, T zin,
                                                          Cell4<T> c)
 {
-    bool fx = false, fy = false, fz = false;
+    T ex = (T)1, ey = (T)1, ez = (T)1;
+    const T hx = (T)0.5 * cx, hy = (T)0.5 * cy, hz = (T)0.5 * cz;
     for (int pass = 0; pass < 3; ++pass) {
-        bool fresh = false;
-        if (!fx && c.xo < (T)0) { fx = true; fresh = true; }
-        if (!fy && c.yo < (T)0) { fy = true; fresh = true; }
-        if (!fz && c.zo < (T)0) { fz = true; fresh = true; }
-        if (!fresh) break;
-        T n2 = qv, d2 = sv;
-        if (fx) n2 += (T)0.5 * cx * xin; else { n2 += cx * xin; d2 += cx; }
-        if (fy) n2 += (T)0.5 * cy * yin; else { n2 += cy * yin; d2 += cy; }
-        if (fz) n2 += (T)0.5 * cz * zin; else { n2 += cz * zin; d2 += cz; }
-        c.pc = qdiv(n2, d2);
-        c.xo = fx ? (T)0 : c.pc + c.pc - xin;
-        c.yo = fy ? (T)0 : c.pc + c.pc - yin;
-        c.zo = fz ? (T)0 : c.pc + c.pc - zin;
+        if (!(fmin(c.xo, fmin(c.yo, c.zo)) < (T)0)) break;
+        ex = c.xo < (T)0 ? (T)0 : ex;
+        ey = c.yo < (T)0 ? (T)0 : ey;
+        ez = c.zo < (T)0 ? (T)0 : ez;
+        T n2 = qv + fma(hx, ex, hx) * xin;
+        n2 += fma(hy, ey, hy) * yin;
+        n2 += fma(hz, ez, hz) * zin;
+        T d2 = fma(cx, ex, sv);
+        d2 = fma(cy, ey, d2);
+        d2 = fma(cz, ez, d2);
+        c.pc = fix_div(n2, d2);
+        c.xo = ex * (c.pc + c.pc - xin);
+        c.yo = ey * (c.pc + c.pc - yin);
+        c.zo = ez * (c.pc + c.pc - zin);
     }
-    c.fixed = (fx ? 1 : 0) | (fy ? 2 : 0) | (fz ? 4 : 0);
+    c.fixed = (ex > (T)0 ? 0 : 1) | (ey > (T)0 ? 0 : 2) | (ez > (T)0 ? 0 : 4);
     return c;
 }
 
