@@ -338,6 +338,7 @@ hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, cons
                        void *sigc, int is_f64, hipStream_t s);
 hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_qinit(const CombArgs &a, int is_f64, hipStream_t s);   // Q = ext in the class layouts after a transition
 hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f64, 1 f32, 2 bf16
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);
 hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq);

@@ -94,11 +94,7 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
             const int i = (int)(v % geo.nx);
             const int j = (int)((v / geo.nx) % geo.ny);
             const int k = (int)(v / ((long)geo.nx * geo.ny));
-            T *ext = (T *)a.ext + (long)b * Nm * C;   // the first source of the group, natural layout
-            // ... and in both class layouts, where the M map of the group's
-            // first iteration reads it (scattered stores, once per group)
-            T *QA = (T *)a.Qc + (long)b * Nm * C, *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
-            const long pA = cls_pos(0, i, j, k, geo.nx, geo.ny), pB = cls_pos(1, i, j, k, geo.nx, geo.ny);
+            T *ext = (T *)a.ext + (long)b * Nm * C;   // the first source of the group (k_qinit lays it out for the sweep)
             // every moment accumulates in the same order as before: first-
             // collision terms g' = 0..g (per superposed source, each source's
             // sum added in turn), the volume source, then downscatter
@@ -146,8 +142,6 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
             for (int lm = 0; lm < NM; ++lm) {
                 T et = (T)e[lm];
                 ext[(long)lm * C + v] = et;
-                QA[(long)lm * C + pA] = et;
-                QB[(long)lm * C + pB] = et;
                 phi_all[(((long)b * G + g) * Nm + lm) * C + v] = (T)0;
                 if (lm == 0) Pp = e[0];
             }
@@ -284,10 +278,7 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
         if (gs < G) {
             const int g = G - 1 - gs;              // the group to set up
             T *pb = (T *)a.phibar + (long)b * Nm * C;
-            // the first adjoint source of the group is phibar, written in the
-            // natural layout and in both class layouts (for the M-map slot)
-            T *QA = (T *)a.Qc + (long)b * Nm * C, *QB = (T *)a.Qc + ((long)a.B + b) * Nm * C;
-            const long pA = cls_pos(0, i, j, k, geo.nx, geo.ny), pB = cls_pos(1, i, j, k, geo.nx, geo.ny);
+            // the first adjoint source of the group is phibar (k_qinit lays it out for the sweep)
 #pragma unroll
             for (int lm = 0; lm < NM; ++lm) {
                 const int l = l_of(lm);
@@ -299,8 +290,6 @@ __global__ __launch_bounds__(256) void k_adj_transition(AdjTransArgs a)
                 }
                 const T et = (T)e;
                 pb[(long)lm * C + v] = et;
-                QA[(long)lm * C + pA] = et;
-                QB[(long)lm * C + pB] = et;
                 lam_all[(((long)b * G + g) * Nm + lm) * C + v] = (T)0;
             }
         }
@@ -576,6 +565,56 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             st->cnt_combine = 0;
         }
     }
+}
+
+// First within-group source of a group (phi = 0, so Q = ext): after a group
+// transition (iteration count 0, nothing pending) copy ext from the natural
+// layout into both class layouts through an LDS slab tile, as k_combine does
+// for the later iterations.  Every other iteration it returns at once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qinit(CombArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T *tile = (T *)smem_raw;
+    const int b = blockIdx.y;
+    const RhsState *st = a.state + b;
+    if (st->finished || st->pending || st->it != 0) return;
+    const int nx = a.geo.nx, ny = a.geo.ny;
+    const long C = a.geo.C;
+    const int Nm = a.Nm;
+    const int nslj = (ny + 15) >> 4;
+    const int k = blockIdx.x / nslj;
+    const int j0 = (blockIdx.x % nslj) * 16;
+    const int lm = blockIdx.z;
+    const int pitch = (nx | 1) + 1;
+    const int tile_n = 16 * nx;
+    const T *ext = (const T *)a.ext + ((long)b * Nm + lm) * C;
+    T *QA = (T *)a.Qc + ((long)b * Nm + lm) * C;
+    T *QB = (T *)a.Qc + (((long)a.B + b) * Nm + lm) * C;
+    for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+        const int jn = idx / nx, in = idx - jn * nx, jj = j0 + jn;
+        if (jj < ny) tile[jn * pitch + in] = ext[in + (long)nx * (jj + (long)ny * k)];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+        const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+        if (j < ny) {
+            const int jm = j % nx;
+            const long p = ((long)k * nx + r) * ny + j;
+            QA[p] = tile[jl * pitch + rot_row(1, r, jm, nx)];
+            QB[p] = tile[jl * pitch + rot_row(0, r, jm, nx)];
+        }
+    }
+}
+
+hipError_t launch_qinit(const CombArgs &a, int is_f64, hipStream_t s)
+{
+    const int nslj = (a.geo.ny + 15) >> 4;
+    dim3 grid((unsigned)(a.geo.nz * nslj), a.B, a.Nm);
+    size_t shm = (size_t)16 * ((a.geo.nx | 1) + 1) * (is_f64 ? 8 : 4);
+    if (is_f64) hipLaunchKernelGGL(k_qinit<double>, grid, dim3(256), shm, s, a);
+    else hipLaunchKernelGGL(k_qinit<float>, grid, dim3(256), shm, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s)

@@ -885,6 +885,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 // the M map fills q; the candidate sweeps below all compute
                 // that same first sweep
                 HC(launch_transition(tr, is64, s));
+                HC(launch_qinit(cb, is64, s));
                 HC(launch_mmap(ma, mode, s));
                 while (ctx->evpool.size() < 2) {
                     hipEvent_t ev;
@@ -968,6 +969,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     auto enqueue_set = [&](hipStream_t es) -> hipError_t {
         hipError_t e = launch_transition(tr, is64, es);
         if (e != hipSuccess) return e;
+        if ((e = launch_qinit(cb, is64, es)) != hipSuccess) return e;
         if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
         for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
             sw.diag = d;
@@ -1480,6 +1482,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     auto enqueue_set = [&]() -> hipError_t {
         hipError_t e = launch_adj_transition(at, is64, s);
         if (e != hipSuccess) return e;
+        if ((e = launch_qinit(cb, is64, s)) != hipSuccess) return e;
         if ((e = launch_mmap(ma, mode, s)) != hipSuccess) return e;
         for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
             sw.diag = d;
