@@ -168,20 +168,32 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
     const bool inb = p < C;
     const long pc = inb ? p : C - 1;
     const int Nm = a.Nm, Nc = a.Nc[c], NcP = a.NcP, ST = a.NcP + 1;
-    T *tab = (T *)smem_map;                              // [NmP][NcP + 1]
-    int *cds = (int *)(tab + (long)a.NmP * ST);
-    stage_table(tab, ST, (const T *)a.Dtab + (long)c * a.NmP * NcP, a.NmP, NcP, cds, a.cdir + c * a.N, Nc);
-    __syncthreads();
     const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const T *psi = (const T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
+    // the psi operands of the first K-chunk are requested before the table
+    // is staged, their direction slots read straight from global memory (a
+    // few hundred bytes, cache-resident), so the table staging and its
+    // barrier overlap the psi loads instead of preceding them
+    const int *cdg = a.cdir + c * a.N;
+    T bv[KC];
+    auto load_chunk = [&](int k0) __attribute__((always_inline)) {
+        int dn[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) dn[u] = cdg[min(k0 + 4 * u + kr, Nc - 1)];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) bv[u] = psi[(long)dn[u] * C + pc];
+    };
+    load_chunk(0);
+    T *tab = (T *)smem_map;                              // [NmP][NcP + 1]
+    int *cds = (int *)(tab + (long)a.NmP * ST);
+    stage_table(tab, ST, (const T *)a.Dtab + (long)c * a.NmP * NcP, a.NmP, NcP, cds, cdg, Nc);
+    __syncthreads();
     T *part = (T *)a.part + ((long)c * a.B + b) * Nm * C;
     A4 acc[NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) acc[rb] = A4{0, 0, 0, 0};
     for (int k0 = 0; k0 < Nc; k0 += 4 * KC) {
-        T bv[KC];
-#pragma unroll
-        for (int u = 0; u < KC; ++u) bv[u] = psi[(long)cds[min(k0 + 4 * u + kr, Nc - 1)] * C + pc];
+        if (k0 > 0) load_chunk(k0);
 #pragma unroll
         for (int u = 0; u < KC; ++u)
             if (k0 + 4 * u < Nc) {
