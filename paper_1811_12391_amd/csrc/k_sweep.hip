@@ -472,24 +472,24 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 yin = ycar;
             }
             const T xin = xo;
-            // Everything except the z term: psi_c = a + b zin with
-            // a = (q + cx xin + cy yin) / d and b = cz / d (the reciprocal of
-            // d refined once, so the quotient is within a few ulp).
-            T a0, b0;
+            // Everything except the z term: psi_c = (n0 + cz zin) y0 with
+            // n0 = q + cx xin + cy yin and y0 = 1 / d (FP64: the reciprocal
+            // refined, so the quotient is within a few ulp)
+            T n0, y0, zc;
             if (ADJ) {
                 const bool ux = !(fv & 1), uy = !(fv & 2), uz = !(fv & 4);
                 const T ex = ux ? cx : (T)0, ey = uy ? cy : (T)0, ez = uz ? cz : (T)0;
-                const T y0 = rcp_nr(sv + ex + ey + ez);
-                a0 = (qv + ex * xin + ey * yin) * y0;
-                b0 = ez * y0;
+                y0 = rcp_nr(sv + ex + ey + ez);
+                n0 = qv + ex * xin + ey * yin;
+                zc = ez;
             } else {
-                const T y0 = rcp_nr(sv + csum);
-                a0 = (qv + cx * xin + cy * yin) * y0;
-                b0 = cz * y0;
+                y0 = rcp_nr(sv + csum);
+                n0 = qv + cx * xin + cy * yin;
+                zc = cz;
             }
             __builtin_amdgcn_sched_barrier(0);
             Cell4<T> c;
-            c.pc = fma(b0, zin, a0);
+            c.pc = fma(zc, zin, n0) * y0;
             if (ADJ) {
                 const bool ux = !(fv & 1), uy = !(fv & 2), uz = !(fv & 4);
                 c.xo = ux ? c.pc + c.pc - xin : c.pc;
@@ -681,15 +681,14 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
                 }
             }
             // everything except the z term, for every layer
-            T a0[ZL], b0[ZL], yin[ZL], xin[ZL];
+            T n0[ZL], y0[ZL], yin[ZL], xin[ZL];
 #pragma unroll
             for (int z = 0; z < ZL; ++z) {
                 ycar[z] = dpp_shift_up_or<T>(yo[z], ycar[z]);
                 yin[z] = ycar[z];
                 xin[z] = xo[z];
-                const T y0 = rcp_nr(sr[z][u] + csum);
-                a0[z] = (qr[z][u] + cx * xin[z] + cy * yin[z]) * y0;
-                b0[z] = cz * y0;
+                y0[z] = rcp_nr(sr[z][u] + csum);
+                n0[z] = qr[z][u] + cx * xin[z] + cy * yin[z];
             }
             __builtin_amdgcn_sched_barrier(0);
             // the ZL cell updates (independent of each other)
@@ -697,7 +696,7 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
             for (int z = 0; z < ZL; ++z) {
                 const bool act = actr[z][u];
                 Cell4<T> c;
-                c.pc = fma(b0[z], zin[z], a0[z]);
+                c.pc = fma(cz, zin[z], n0[z]) * y0[z];
                 c.xo = c.pc + c.pc - xin[z];
                 c.yo = c.pc + c.pc - yin[z];
                 c.zo = c.pc + c.pc - zin[z];
