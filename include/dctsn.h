@@ -92,6 +92,14 @@ typedef struct dct_opts {
                                  beams in one simulation, Sec. III-C).  Every [B] below then
                                  counts right-hand sides.  EINVAL if S does not divide B or
                                  if keep_adjoint is set with S > 1. */
+    int stall_window;         /* reduced-precision stop (DCT_FP32 / DCT_FP32_BF16MAP; the
+                                 forward solve's precision for dct_adjoint): a group also stops
+                                 once eps <= 10 tol has gone stall_window consecutive
+                                 iterations without a new minimum.  In FP32 the set-to-zero
+                                 decisions of near-zero outflows flip with rounding and can
+                                 hold eps at a few tol for many iterations.  0 = default (4 in
+                                 the reduced-precision modes), < 0 = off; never used in FP64.
+                                 Such a stop is not DCT_ENOTCONV; stats->eps shows its eps. */
 } dct_opts;
 
 typedef struct dct_stats {

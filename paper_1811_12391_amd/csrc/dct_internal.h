@@ -156,6 +156,8 @@ struct RhsState {
     int notconv;    // some group stopped at max_iter above tol
     unsigned long long eps_num, eps_den;   // bit patterns of non-negative doubles (max)
     unsigned int cnt_combine, cnt_trans;   // last-block-done counters
+    double eps_best;  // smallest eps of the group so far (reduced-precision stop)
+    int stall;        // consecutive iterations near tol without a new minimum
 };
 
 // group actually processed at position g of the group sequence
@@ -224,6 +226,7 @@ struct CombArgs {
     const int *fixed_iters;   // [G] or null
     double tol;
     int max_iter;
+    int stall_window;         // reduced-precision stagnation stop (0 = off)
     int nblocks_per_b;
     int reverse;              // groups run from G-1 down to 0
     unsigned *cnt_mom;        // [B][Nm][32] completion counters of the moment groups, one per 128-byte line

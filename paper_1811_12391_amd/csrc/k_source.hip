@@ -550,8 +550,22 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             } else if (a.fixed_iters) {
                 stop = it >= a.fixed_iters[g];
             } else {
-                stop = (e <= a.tol) || (it >= a.max_iter);
-                if (stop && e > a.tol) st->notconv = 1;
+                bool conv = e <= a.tol;
+                if (!conv && a.stall_window > 0) {
+                    // reduced precision: eps near tol that stops improving is
+                    // rounding noise (flipping set-to-zero decisions), not
+                    // slow convergence
+                    if (it == 1 || e < st->eps_best) {
+                        st->eps_best = e;
+                        st->stall = 0;
+                    } else if (e <= 10.0 * a.tol) {
+                        conv = ++st->stall >= a.stall_window;
+                    } else {
+                        st->stall = 0;
+                    }
+                }
+                stop = conv || (it >= a.max_iter);
+                if (stop && !conv) st->notconv = 1;
             }
             if (stop) {
                 a.iters[(long)b * G + g] = it;

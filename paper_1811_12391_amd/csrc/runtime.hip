@@ -828,6 +828,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     cb.fixed_iters = (const int *)d_fixed;
     cb.tol = o.tol;
     cb.max_iter = o.max_iter;
+    cb.stall_window = o.precision == DCT_FP64 ? 0 : (o.stall_window == 0 ? 4 : (o.stall_window > 0 ? o.stall_window : 0));
     cb.reverse = 0;
 
     auto apply_blocks = [&](int bk) {
@@ -1474,6 +1475,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     cb.fixed_iters = o.fixed_iters ? (const int *)d_fix : nullptr;
     cb.tol = o.tol;
     cb.max_iter = o.max_iter;
+    cb.stall_window = o.precision == DCT_FP64 ? 0 : (o.stall_window == 0 ? 4 : (o.stall_window > 0 ? o.stall_window : 0));
     cb.reverse = 1;
 
     long cap_sets = 2;

@@ -39,7 +39,8 @@ class dct_opts(ct.Structure):
                 ("fixed_iters", ct.POINTER(ct.c_int)), ("fixup", ct.c_int),
                 ("test_inflow", ct.POINTER(ct.c_double)), ("chunk", ct.c_int), ("use_graph", ct.c_int),
                 ("profile", ct.c_int), ("keep_adjoint", ct.c_int), ("autotune", ct.c_int),
-                ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int), ("superpose", ct.c_int)]
+                ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int), ("superpose", ct.c_int),
+                ("stall_window", ct.c_int)]
 
 
 class dct_stats(ct.Structure):
@@ -170,7 +171,7 @@ class SolveStats:
 
 def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=None, fixup=True,
           test_inflow=None, chunk=0, use_graph=False, profile=False, keep_adjoint=False, autotune=False,
-          sweep_bk=0, sweep_sync=0, superpose=1, allow_notconv=False) -> SolveStats:
+          sweep_bk=0, sweep_sync=0, superpose=1, stall_window=0, allow_notconv=False) -> SolveStats:
     """B = number of sources; with superpose = S > 1 the per-right-hand-side
     outputs have B // S rows."""
     o = dct_opts()
@@ -190,6 +191,7 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     o.sweep_bk = int(sweep_bk)
     o.sweep_sync = int(sweep_sync)
     o.superpose = int(superpose)
+    o.stall_window = int(stall_window)
     S = max(1, int(superpose))
     if B % S:
         raise ValueError(f"superpose={S} must divide the number of sources {B}")
@@ -243,7 +245,8 @@ class AdjointResult:
     solve_ms: float
 
 
-def adjoint(h, B, G, C, roi, *, tol=1e-6, max_iter=1000, fixed_iters=None, chunk=0) -> AdjointResult:
+def adjoint(h, B, G, C, roi, *, tol=1e-6, max_iter=1000, fixed_iters=None, chunk=0,
+            stall_window=0) -> AdjointResult:
     """Gradient of sum_b sum_v roi[v] dose_b(v) after a solve with keep_adjoint=True."""
     roi = _f64(roi).reshape(-1)
     if roi.size != C:
@@ -254,6 +257,7 @@ def adjoint(h, B, G, C, roi, *, tol=1e-6, max_iter=1000, fixed_iters=None, chunk
     fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, dtype=np.int32)
     o.fixed_iters = _p(fi, ct.POINTER(ct.c_int)) if fi is not None else None
     o.chunk = int(chunk)
+    o.stall_window = int(stall_window)
     R = np.zeros(1)
     dd = np.zeros(C)
     dg = np.zeros(G)
