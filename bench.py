@@ -257,8 +257,8 @@ def other_forms(args):
 
     base = dict(autotune=True, use_graph=True, chunk=8)
     _, st64, ref = timed(prob, precision="fp64", tol=prob.tol, superpose=16, **base)
-    # FP32 stalls at a few 1e-6 in the highest groups of this form (set-to-zero
-    # decisions that flip between iterations), so it runs the FP64 counts
+    # the three FP32 timings run the FP64 solve's per-group iteration counts,
+    # so they do the same work (superposed, one beam, 16 separate)
     fi = st64.iters[0].astype(np.int32)
     w_sup, st, d = timed(prob, precision="fp32", fixed_iters=fi, superpose=16, **base)
     w_one, st1, _ = timed(one, precision="fp32", fixed_iters=fi, **base)
