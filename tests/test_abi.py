@@ -93,3 +93,31 @@ def test_null_context():
     lib = dctsn.lib()
     assert lib.dct_set_geometry(None, 1, 1, 1, 1.0, 1.0, 1.0, None, None, None) == dctsn.DCT_EINVAL
     assert lib.dct_destroy(None) == dctsn.DCT_OK
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of dct_opts and dct_stats have the header's field
+    offsets and sizes (a field added on one side only would shift the rest)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"dct_opts": dctsn.dct_opts, "dct_stats": dctsn.dct_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dctsn.h"', "int main(void) {"]
+    for name, py in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, py in structs.items():
+        assert got[(name, "size")] == ct.sizeof(py), name
+        for fname, _ in py._fields_:
+            assert got[(name, fname)] == getattr(py, fname).offset, (name, fname)
