@@ -75,8 +75,8 @@ def main():
                     help="first run a plain 256 MiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this solve is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the solve over several "
+              "GPUs (right-hand sides, then z slabs) is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
