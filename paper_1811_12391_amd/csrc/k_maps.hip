@@ -150,10 +150,11 @@ __global__ __launch_bounds__(256) void k_mmap_bf16(MapArgs a)
 }
 
 // ---------------------------------------------------------------- D map
-// As the M map: the class's table and direction slots in LDS, the psi
-// operands of up to KC K-steps loaded at once (clamped, unconditional; the
-// table columns of padded directions are zero), NRB 16-row blocks of
-// moments accumulated together so psi is read once.
+// As the M map: the class's table in LDS, the psi operands of up to KC
+// K-steps loaded at once (clamped, unconditional; the table columns of
+// padded directions are zero; their direction slots read from global memory
+// so the loads need not wait for the staging), NRB 16-row blocks of moments
+// accumulated together so psi is read once.
 template <typename T, int NRB>
 __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
 {
