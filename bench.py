@@ -73,6 +73,10 @@ def main():
                     help="skip the batched axial-scan and adjoint forms (reported beside the headline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference dispatch for HBM byte counters)")
+    ap.add_argument("--schedule", default=None, metavar="BK:SYNC",
+                    help="pin the sweep schedule of the timed solves (z layers per workgroup : wave "
+                         "coupling) instead of autotuning; for counter runs, where the profiler's "
+                         "serialisation can change the tuner's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the solve over several "
@@ -99,6 +103,9 @@ def main():
 
     def run(precision, steps, warmup, tag, fixed=None):
         kw = dict(precision=precision, tol=prob.tol, fixed_iters=fixed, autotune=True)
+        if args.schedule:
+            bk, sync = (int(x) for x in args.schedule.split(":"))
+            kw.update(autotune=False, sweep_bk=bk, sweep_sync=sync)
         for _ in range(warmup):
             solver.solve(**kw)
             dctsn.dose_dev(solver.h, dose_dev, summed=True)
