@@ -343,10 +343,11 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     }
     T ycar = bc;                                            // lane 0 keeps the boundary value
     T xo = bc, yo = 0, zo = 0;                              // x inflow of a row starts at the boundary value
-    // leakage: the y outflow of a lane is summed in T (at most nx terms per
-    // lane) and widened at the end; only the wave on the z boundary sums z
+    // leakage: the y and z outflows of a lane are summed in T (at most nx
+    // terms each per lane) and widened at the end; only the wave on the z
+    // boundary sums z
     T lyv = 0;
-    double lzv = 0.0;
+    T lzv = 0;
     const bool zlast_wave = __builtin_amdgcn_readfirstlane(kp) == nz - 1;
     int known_prev = 0, known_next = 0, spins = 0;   // wave-uniform
     typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(rh, 0, 0, 0)) u64v;
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
                 }
             }
             lyv += act ? c.yo : (T)0;
-            if (zlast_wave) lzv += act ? (double)c.zo : 0.0;
+            if (zlast_wave) lzv += act ? c.zo : (T)0;
             xo = act ? c.xo : xo;
             yo = c.yo;
             zo = c.zo;
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     // x outflow of every row, and the y / z outflows of the boundary rows
     double lx = valid ? (double)xo : 0.0;
     double ly = (valid && ylast) ? (double)lyv : 0.0;
-    double lz = (valid && zlast) ? lzv : 0.0;
+    double lz = (valid && zlast) ? (double)lzv : 0.0;
     for (int o = 32; o > 0; o >>= 1) {
         lx += __shfl_down(lx, o, 64);
         ly += __shfl_down(ly, o, 64);
@@ -677,7 +678,7 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
         ycar[z] = xo[z] = bc;
         yo[z] = zo[z] = lyv[z] = (T)0;
     }
-    double lzv = 0.0;
+    T lzv = 0;
     for (int tb = -PF; tb < NTp; tb += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -733,7 +734,7 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
                 if (KEEP)
                     __builtin_amdgcn_raw_buffer_store_b8((unsigned char)c.fixed, rmask, ser[KEEP ? z : 0][KEEP ? u : 0], 0, 0);
                 lyv[z] += act ? c.yo : (T)0;
-                if (zlast[z]) lzv += act ? (double)c.zo : 0.0;
+                if (zlast[z]) lzv += act ? c.zo : (T)0;
                 xo[z] = act ? c.xo : xo[z];
                 yo[z] = c.yo;
                 zo[z] = c.zo;
@@ -750,7 +751,7 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
         lx += vz[z] ? (double)xo[z] : 0.0;
         ly += (vz[z] && ylast) ? (double)lyv[z] : 0.0;
     }
-    double lz = lzv;
+    double lz = (double)lzv;
     for (int o = 32; o > 0; o >>= 1) {
         lx += __shfl_down(lx, o, 64);
         ly += __shfl_down(ly, o, 64);
