@@ -93,6 +93,15 @@ def _declare(L):
                                 ct.c_double, ct.c_int, _i, ct.c_int, _d, ct.c_int,
                                 _d, _d, _d, _i, _d, _d, _l])
     L.orc_solve_sup.restype = ct.c_int
+    L.orc_scatter_moments.argtypes = [ct.c_long, _u8, _d, ct.c_int, ct.c_int, _d, ct.c_int, ct.c_int, _d, _d, _d,
+                                      ct.c_int]
+    L.orc_scatter_moments.restype = ct.c_int
+    L.orc_solve_fixed.argtypes = ([ct.c_int] * 3 + [ct.c_double] * 3 + [_d, _u8, _d,
+                                  ct.c_int, ct.c_int, ct.c_int, _d, _d, _d,
+                                  ct.c_int, _d, _d, _d, _d,
+                                  ct.c_double, ct.c_int, ct.c_int, ct.c_int,
+                                  _d, _d, _i, _d, _d])
+    L.orc_solve_fixed.restype = ct.c_int
 
 
 def _p(a, t=_d):
@@ -126,6 +135,50 @@ def moment_maps(L: int, dirs, w):
     D = np.zeros((Nm, N))
     assert lib().orc_moment_maps(L, N, _p(dirs), _p(w), _p(M), _p(D)) == 0
     return M, D
+
+
+def scatter_moments(material, density, sigma_s, L, gf, gt, phi, base=None, threads=None):
+    """Scattering source moments of eq. (2) that the flux moments phi[Nm][C]
+    of group gf put into group gt: base + rho s_l^{gf->gt}[m] phi (per moment
+    of degree l).  sigma_s is [M][>=L+1][G][G] (from, to)."""
+    ss = _f64(sigma_s[:, : L + 1])
+    G = ss.shape[-1]
+    mat = np.ascontiguousarray(material, dtype=np.uint8)
+    rho, phi = _f64(density), _f64(phi)
+    C = mat.shape[0]
+    out = np.zeros(((L + 1) ** 2, C))
+    b = None if base is None else _f64(base)
+    rc = lib().orc_scatter_moments(C, _p(mat, _u8), _p(rho), G, L, _p(ss), int(gf), int(gt), _p(phi), _p(b), _p(out),
+                                   threads or default_threads())
+    assert rc == 0
+    return out
+
+
+def solve_fixed(ph, xs, dirs, w, L, ext, inflow_dir=None, *, tol=1e-6, max_iter=1000, fixup=True, threads=None):
+    """Collided solve of one right-hand side from a given fixed source
+    ext[G][Nm][C] (any moments) with the angular inflow inflow_dir[G][N] on
+    every boundary face (None: vacuum).  Returns (phi[G][Nm][C], dose[C],
+    iters[G], eps[G], bal[G][3])."""
+    G, M = xs.sigma_t.shape[1], xs.sigma_t.shape[0]
+    st, ss, ka = _f64(xs.sigma_t), _f64(xs.sigma_s[:, : L + 1]), _f64(xs.kerma)
+    dirs, w = _f64(dirs), _f64(w)
+    N, Nm, C = dirs.shape[0], (L + 1) ** 2, ph.C
+    ext = _f64(ext).reshape(G, Nm, C)
+    ind = None if inflow_dir is None else _f64(inflow_dir).reshape(G, N)
+    mat = np.ascontiguousarray(ph.material, dtype=np.uint8)
+    rho, org = _f64(ph.density), _f64(ph.origin)
+    phi = np.zeros((G, Nm, C))
+    dose = np.zeros(C)
+    iters = np.zeros(G, dtype=np.int32)
+    eps = np.zeros(G)
+    bal = np.zeros((G, 3))
+    rc = lib().orc_solve_fixed(ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, _p(org), _p(mat, _u8), _p(rho),
+                               G, M, L, _p(st), _p(ss), _p(ka), N, _p(dirs), _p(w), _p(ext), _p(ind),
+                               float(tol), int(max_iter), int(fixup), threads or default_threads(),
+                               _p(phi), _p(dose), _p(iters, _i), _p(eps), _p(bal))
+    if rc != 0:
+        raise RuntimeError("oracle fixed-source solve failed: %d" % rc)
+    return phi, dose, iters, eps, bal
 
 
 def siddon(grid, p, x):

@@ -35,7 +35,11 @@
  * Parity: every function below is pinned by the CPU test suite against closed
  * forms, hand values, brute force or invariants, except the phantom
  * generator, the fixup pattern and the stopping point, which have no external
- * values ("parity unpinned" beyond oracle <-> GPU self-consistency).
+ * values ("parity unpinned" beyond oracle <-> GPU self-consistency).  The
+ * scattering source of every degree l (within-group and downscatter, forward
+ * and adjoint) goes through orc_scatter_moments, which is pinned against the
+ * direction-to-direction form of eq. (2) and, inside the full solve, against
+ * the anisotropic infinite-medium closed form.
  */
 #include <math.h>
 #include <stdint.h>
@@ -449,6 +453,34 @@ int orc_first_collision(int nx, int ny, int nz, double dx, double dy, double dz,
     return 0;
 }
 
+/* Scattering source of eq. (2) in moment form.  With the scattering kernel
+ * expanded in Legendre polynomials and P_l(Omega . Omega') written by the
+ * addition theorem as sum_m Y_lm(Omega) Y_lm(Omega'), the direction-to-
+ * direction sum of eq. (2) becomes one product per moment: the flux moments
+ * phi[Nm][C] of group gf put the source  rho_v s_l^{gf->gt}[m_v] phi[lm][v]
+ * into moment lm (degree l) of group gt.  This function writes
+ *   out[lm][v] = base[lm][v] + rho_v s_l^{gf->gt}[m_v] phi[lm][v]
+ * (base NULL: 0; base may be out itself, which accumulates).  gf == gt is the
+ * within-group term, gf < gt the downscatter of eq. (2)'s group sum; the
+ * adjoint applies the same products with the roles of the groups exchanged
+ * (weights of gt carried back to gf).  ss is [M][L+1][G][G] (from, to). */
+int orc_scatter_moments(long C, const uint8_t *mat, const double *rho, int G, int L, const double *ss, int gf,
+                        int gt, const double *phi, const double *base, double *out, int nthreads)
+{
+    if (L < 0 || gf < 0 || gt < 0 || gf >= G || gt >= G) return -1;
+    for (int l = 0; l <= L; ++l)
+        for (int m = -l; m <= l; ++m) {
+            const size_t lm = (size_t)(l * l + l + m);
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+            for (long v = 0; v < C; ++v) {
+                const double s = ss[(((size_t)mat[v] * (L + 1) + l) * G + gf) * G + gt];
+                const double b = base ? base[lm * C + v] : 0.0;
+                out[lm * C + v] = b + rho[v] * s * phi[lm * C + v];
+            }
+        }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Full solve: uncollided -> first-collision source -> per-group source        */
 /* iteration with downscatter -> dose.  Each right-hand side (source) b is      */
@@ -474,11 +506,13 @@ static double ss_at(const Prob *P, int m, int l, int gf, int gt)
 /* Forward solve of one right-hand side.  ext = its first-collision source
  * [G][Nm][C] (owned by the call: downscatter is added to it in place), pu =
  * its uncollided flux [G][C].  Outputs phi[G][Nm][C], dose[C], iters[G],
- * eps[G], bal[G][3].  When psi_store / mask_store are given, the cell fluxes
+ * eps[G], bal[G][3].  inflow_dir[G][N] (or NULL: vacuum) is the angular flux
+ * entering through the boundary in each direction.  When psi_store /
+ * mask_store are given, the cell fluxes
  * [G][N][C] and fixed-face sets of the final sweep of every group are kept
  * (for the adjoint). */
 static int forward_rhs(const Prob *P, double *ext, const double *pu,
-                       double tol, int max_iter, const int *fixed_iters, int fixup, const double *test_inflow,
+                       double tol, int max_iter, const int *fixed_iters, int fixup, const double *inflow_dir,
                        int nthreads, double *phi, double *dose, int *iters, double *eps, double *bal,
                        long *nfix_total, double *psi_store, uint8_t *mask_store)
 {
@@ -497,29 +531,25 @@ static int forward_rhs(const Prob *P, double *ext, const double *pu,
     uint8_t *mask = (uint8_t *)malloc((size_t)N * C);
     if (!Q || !q || !ps || !cur || !nxt || !sigt || !leak || !inflow || !mask) return -4;
     for (int g = 0; g < G; ++g) {
-        double bc = test_inflow ? test_inflow[g] : 0.0;
-        for (int n = 0; n < N; ++n) inflow[n] = bc;
+        const double *ig = inflow_dir ? inflow_dir + (size_t)g * N : NULL;
+        for (int n = 0; n < N; ++n) inflow[n] = ig ? ig[n] : 0.0;
         for (size_t v = 0; v < C; ++v) sigt[v] = P->rho[v] * P->st[(size_t)P->mat[v] * G + g];
         double *eg = ext + (size_t)g * Nm * C;
         /* production: volumetric source plus boundary inflow */
         double Pr = 0.0;
         for (size_t v = 0; v < C; ++v) Pr += eg[v];
         Pr *= V;
-        if (bc != 0.0)
-            for (int n = 0; n < N; ++n)
-                Pr += bc * P->w[n] * (fabs(P->dirs[3 * n]) * Ax * P->ny * P->nz + fabs(P->dirs[3 * n + 1]) * Ay * P->nx * P->nz +
-                                      fabs(P->dirs[3 * n + 2]) * Az * P->nx * P->ny);
+        /* each direction enters through one face per axis */
+        for (int n = 0; n < N; ++n)
+            if (inflow[n] != 0.0)
+                Pr += inflow[n] * P->w[n] * (fabs(P->dirs[3 * n]) * Ax * P->ny * P->nz + fabs(P->dirs[3 * n + 1]) * Ay * P->nx * P->nz +
+                                             fabs(P->dirs[3 * n + 2]) * Az * P->nx * P->ny);
         memset(cur, 0, sizeof(double) * (size_t)Nm * C);
         int it = 0;
         double e = 0.0;
         for (;;) {
             /* scattering source within the group plus the fixed source */
-#pragma omp parallel for schedule(static) num_threads(nthreads)
-            for (long v = 0; v < (long)C; ++v) {
-                int m = P->mat[v];
-                for (int lm = 0; lm < Nm; ++lm)
-                    Q[(size_t)lm * C + v] = eg[(size_t)lm * C + v] + P->rho[v] * ss_at(P, m, P->lof[lm], g, g) * cur[(size_t)lm * C + v];
-            }
+            orc_scatter_moments((long)C, P->mat, P->rho, G, L, P->ss, g, g, cur, eg, Q, nthreads);
             /* moments -> directions */
 #pragma omp parallel for schedule(static) num_threads(nthreads)
             for (long v = 0; v < (long)C; ++v)
@@ -569,12 +599,7 @@ static int forward_rhs(const Prob *P, double *ext, const double *pu,
         /* downscatter into every lower-energy group */
         for (int g2 = g + 1; g2 < G; ++g2) {
             double *e2 = ext + (size_t)g2 * Nm * C;
-#pragma omp parallel for schedule(static) num_threads(nthreads)
-            for (long v = 0; v < (long)C; ++v) {
-                int m = P->mat[v];
-                for (int lm = 0; lm < Nm; ++lm)
-                    e2[(size_t)lm * C + v] += P->rho[v] * ss_at(P, m, P->lof[lm], g, g2) * cur[(size_t)lm * C + v];
-            }
+            orc_scatter_moments((long)C, P->mat, P->rho, G, L, P->ss, g, g2, cur, e2, e2, nthreads);
         }
         memcpy(phi + (size_t)g * Nm * C, cur, sizeof(double) * (size_t)Nm * C);
         /* dose: collision kerma of uncollided + collided scalar fluence */
@@ -642,6 +667,13 @@ int orc_solve_sup(int nx, int ny, int nz, double dx, double dy, double dz, const
     if (!pu_src || !ext || !ext1) return -4;
     orc_uncollided(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, st, B, pos, axis, fan_deg, cone_deg, gw, nthreads,
                    pu_src);
+    double *inflow_dir = NULL;
+    if (test_inflow) {
+        inflow_dir = (double *)malloc(sizeof(double) * (size_t)G * N);
+        if (!inflow_dir) return -4;
+        for (int g = 0; g < G; ++g)
+            for (int n = 0; n < N; ++n) inflow_dir[(size_t)g * N + n] = test_inflow[g];
+    }
     long nfix = 0;
     int rc = 0;
     for (int r = 0; r < R && rc == 0; ++r) {
@@ -657,11 +689,12 @@ int orc_solve_sup(int nx, int ny, int nz, double dx, double dy, double dz, const
             for (size_t i = 0; i < (size_t)G * Nm * C; ++i) ext[i] += ext1[i];
             for (size_t i = 0; i < (size_t)G * C; ++i) pu[i] += pb[i];
         }
-        rc = forward_rhs(&P, ext, pu, tol, max_iter, fixed_iters, fixup, test_inflow, nthreads,
+        rc = forward_rhs(&P, ext, pu, tol, max_iter, fixed_iters, fixup, inflow_dir, nthreads,
                          phi + (size_t)r * G * Nm * C, dose + (size_t)r * C, iters + r * G, eps + r * G,
                          bal + (size_t)r * G * 3, &nfix, NULL, NULL);
     }
     if (nfix_out) *nfix_out = nfix;
+    free(inflow_dir);
     free(pu_src);
     free(ext);
     free(ext1);
@@ -683,6 +716,38 @@ int orc_solve(int nx, int ny, int nz, double dx, double dy, double dz, const dou
     return orc_solve_sup(nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, L, st, ss, kap, N, dirs, w, B, 1, pos, axis,
                          fan_deg, cone_deg, gw, ext_iso, tol, max_iter, fixed_iters, fixup, test_inflow, nthreads,
                          phi_u, phi, dose, iters, eps, bal, nfix_out);
+}
+
+/* Collided solve of one right-hand side from a given fixed source: the
+ * per-group source iteration with downscatter and the dose tally of
+ * forward_rhs, with ext[G][Nm][C] (any moments, anisotropic included) in place
+ * of the first-collision source, no uncollided flux, and inflow_dir[G][N]
+ * (or NULL: vacuum) the angular flux entering through the boundary in every
+ * direction.  Outputs phi[G][Nm][C], dose[C], iters[G], eps[G], bal[G][3]. */
+int orc_solve_fixed(int nx, int ny, int nz, double dx, double dy, double dz, const double *org,
+                    const uint8_t *mat, const double *rho,
+                    int G, int M, int L, const double *st, const double *ss, const double *kap,
+                    int N, const double *dirs, const double *w,
+                    const double *ext_in, const double *inflow_dir,
+                    double tol, int max_iter, int fixup, int nthreads,
+                    double *phi, double *dose, int *iters, double *eps, double *bal)
+{
+    size_t C = (size_t)nx * ny * nz;
+    int lof[289];
+    Prob P;
+    make_prob(&P, nx, ny, nz, dx, dy, dz, org, mat, rho, G, M, L, st, ss, kap, N, dirs, w, lof);
+    const int Nm = P.Nm;
+    double *ext = (double *)malloc(sizeof(double) * (size_t)G * Nm * C);
+    double *pu = (double *)calloc((size_t)G * C, sizeof(double));
+    if (!ext || !pu) return -4;
+    memcpy(ext, ext_in, sizeof(double) * (size_t)G * Nm * C);
+    long nfix = 0;
+    int rc = forward_rhs(&P, ext, pu, tol, max_iter, NULL, fixup, inflow_dir, nthreads, phi, dose, iters, eps, bal,
+                         &nfix, NULL, NULL);
+    free(ext);
+    free(pu);
+    free_prob(&P);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -761,20 +826,14 @@ int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, const d
             for (size_t v = 0; v < C; ++v) sigt[v] = rho[v] * st[(size_t)mat[v] * G + g];
             /* moment weight of phi_g: dose seed + what the lower groups took from it */
             for (int lm = 0; lm < Nm; ++lm)
-                for (size_t v = 0; v < C; ++v) {
-                    double acc = lm == 0 ? roi[v] * kap[(size_t)mat[v] * G + g] : 0.0;
-                    for (int g2 = g + 1; g2 < G; ++g2)
-                        acc += rho[v] * ss_at(&P, mat[v], lof[lm], g, g2) * lam[((size_t)g2 * Nm + lm) * C + v];
-                    pb[(size_t)lm * C + v] = acc;
-                }
+                for (size_t v = 0; v < C; ++v) pb[(size_t)lm * C + v] = lm == 0 ? roi[v] * kap[(size_t)mat[v] * G + g] : 0.0;
+            for (int g2 = g + 1; g2 < G; ++g2)
+                orc_scatter_moments((long)C, mat, rho, G, L, ss, g, g2, lam + (size_t)g2 * Nm * C, pb, pb, nthreads);
             memset(cur, 0, sizeof(double) * (size_t)Nm * C);
             int it = 0;
             const uint8_t *mg = mask + (size_t)g * N * C;
             for (;;) {
-                for (int lm = 0; lm < Nm; ++lm)
-                    for (size_t v = 0; v < C; ++v)
-                        mu[(size_t)lm * C + v] = pb[(size_t)lm * C + v] +
-                                                 rho[v] * ss_at(&P, mat[v], lof[lm], g, g) * cur[(size_t)lm * C + v];
+                orc_scatter_moments((long)C, mat, rho, G, L, ss, g, g, cur, pb, mu, nthreads);
                 /* D^T: moment weights -> direction weights */
 #pragma omp parallel for schedule(static) num_threads(nthreads)
                 for (long v = 0; v < (long)C; ++v)
