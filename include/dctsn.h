@@ -46,8 +46,10 @@ extern "C" {
 #define DCT_ENUMERIC (-6)  /* NaN or Inf met in a convergence reduction */
 
 /* Arithmetic of the collided solve.  The ray-traced optical depth, the
- * convergence and balance reductions and the dose tally are FP64 in every
- * mode. */
+ * convergence reductions, the dose tally and the balance sums are FP64 in
+ * every mode, except that in DCT_FP32 / DCT_FP32_BF16MAP each sweep row's
+ * boundary outflows (at most nx, ny or nz terms) are summed in FP32 before
+ * they enter the FP64 leakage sum. */
 #define DCT_FP64 0          /* everything FP64 */
 #define DCT_FP32 1          /* sweeps, moment maps and moment storage FP32 */
 #define DCT_FP32_BF16MAP 2  /* as DCT_FP32, with bf16 inputs to both moment maps
@@ -135,7 +137,9 @@ const char *dct_last_error(const dct_ctx *ctx);
 
 /* Voxel phantom (Sec. II-B: CT volume converted to dosimetric materials;
  * Sec. II-D: rectangular mesh of cubic or box voxels).
- *   nx, ny, nz > 0; dx, dy, dz > 0 (cm); origin[3] = grid corner (cm);
+ *   nx, ny, nz in [1, 4096] with C = nx ny nz < 2^28 (the kernels use 32-bit
+ *   byte offsets into per-voxel FP64 arrays); dx, dy, dz > 0 (cm);
+ *   origin[3] = grid corner (cm);
  *   material[C] (uint8, < M of dct_set_xs); density[C] (g/cm^3, finite, >= 0).
  * EINVAL on bad sizes or values. */
 int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy, double dz,

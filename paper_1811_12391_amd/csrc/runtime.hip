@@ -209,8 +209,10 @@ int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy,
     if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, DCT_EINVAL, "set_geometry: nx, ny, nz must be > 0");
     if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(dz))
         return fail(ctx, DCT_EINVAL, "set_geometry: voxel sizes must be finite and > 0");
-    if (nx > 4096 || ny > 4096 || nz > 4096 || (double)nx * ny * nz > 2.0e9)
-        return fail(ctx, DCT_EINVAL, "set_geometry: grid too large");
+    // the kernels address a per-voxel array through 32-bit byte offsets of
+    // FP64 elements (buffer descriptors), so C * 8 must stay below 2^31
+    if (nx > 4096 || ny > 4096 || nz > 4096 || (long long)nx * ny * nz * 8 >= (1LL << 31))
+        return fail(ctx, DCT_EINVAL, "set_geometry: grid too large (nx * ny * nz must be below 2^28 = 268435456 voxels)");
     if (!origin || !material || !density) return fail(ctx, DCT_EINVAL, "set_geometry: NULL array");
     if (!finite_all(origin, 3)) return fail(ctx, DCT_EINVAL, "set_geometry: origin not finite");
     size_t C = (size_t)nx * ny * nz;

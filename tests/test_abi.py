@@ -59,6 +59,17 @@ def test_validation_codes(host_ctx):
     with pytest.raises(dctsn.DctError):
         dctsn.set_geometry(h, ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, ph.origin, ph.material, bad)
     dctsn.set_geometry(h, ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, ph.origin, ph.material, ph.density)
+    # a grid of 2^28 voxels would overflow the kernels' 32-bit byte offsets of
+    # per-voxel FP64 arrays: rejected before its arrays are read (so
+    # one-element arrays suffice here)
+    one_m, one_d = np.zeros(1, np.uint8), np.ones(1)
+    lib = dctsn.lib()
+    rc = lib.dct_set_geometry(h, 1024, 1024, 256, 1.0, 1.0, 1.0, ph.origin.ctypes.data_as(ct.POINTER(ct.c_double)),
+                              one_m.ctypes.data_as(ct.POINTER(ct.c_uint8)), one_d.ctypes.data_as(ct.POINTER(ct.c_double)))
+    assert rc == dctsn.DCT_EINVAL and "too large" in dctsn.last_error(h)
+    rc = lib.dct_set_geometry(h, 4096, 4096, 0, 1.0, 1.0, 1.0, None, None, None)
+    assert rc == dctsn.DCT_EINVAL
+    dctsn.set_geometry(h, ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, ph.origin, ph.material, ph.density)
     # source before xs -> ESTATE (needs G)
     with pytest.raises(dctsn.DctError) as e:
         dctsn.set_source(h, 1, prob.src_pos, prob.src_axis, 20.0, 10.0, prob.group_w)
