@@ -1,19 +1,23 @@
 """Benchmark of the multigroup discrete-ordinates dose solve on one MI355X.
 
-Workload: water cylinder (35 cm diameter) in air on a 64 x 64 x 16 grid of
-0.6 cm voxels, one collimated point source 54 cm from the axis (20 deg fan x
-10 deg cone), 19 groups over 10-120 keV with Kramers 120 kVp weights, S8
-level-symmetric quadrature (80 directions), P3 scattering, source iteration
-to 1e-6 per group.  A step is one whole solve (ray trace, first-collision
-source, every group's source iterations with sweeps and moment maps, dose
-tally) with every input already resident on the device, plus the dose
-written to a device buffer.
+Headline workload: the axial scan -- water cylinder (35 cm diameter) in air on
+a 64 x 64 x 16 grid of 0.6 cm voxels, 36 collimated point sources (20 deg fan
+x 10 deg cone) every 10 deg on a 54 cm circle solved together as 36
+right-hand sides, 19 groups over 10-120 keV with Kramers 120 kVp weights, S6
+level-symmetric quadrature (48 directions), P3 scattering, source iteration to
+1e-6 per group and per source.  A step is one whole solve (ray traces,
+first-collision sources, every group's source iterations with sweeps and
+moment maps, dose tally) with every input already resident on the device,
+plus the summed dose written to a device buffer.
 
 Prints one JSON line.  Metric: sweep cell x angle x group updates per second
 over the whole solve, for the fastest precision whose dose stays within 1e-4
-(L2, relative) of the FP64 solve.  Also reports the sweep kernel's achieved
-HBM bandwidth (algorithmic bytes / measured kernel time) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+(L2, relative) of the FP64 solve of the same workload on the GPU.  Also
+reports the sweep kernel's achieved HBM bandwidth (algorithmic bytes /
+measured kernel time, HIP events on the solver's stream), the other workloads
+(the 128 x 128 x 32 abdomen, the single-source cylinder, the superposed CT
+scan, the ROI-dose gradient) and the FP64 CPU oracle timed on a bounded
+sample of the headline workload.
 """
 import argparse
 import json
@@ -26,51 +30,144 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sweep cell·angle·group updates/s + ms/solve at ≤1e-4 rel dose err vs FP64"
 HBM_PEAK_GBS = 8000.0
+BAR = 1e-4
 
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, groups=None):
-    """FP64 oracle on the first `groups` groups of the same workload (all of
-    them by default; groups only couple downward, so a prefix is exactly the
-    first part of the full solve), all host threads it is given."""
-    import numpy as np
-
+def cpu_baseline(prob, sources=None):
+    """FP64 oracle on the first `sources` sources of the same workload (every
+    source's solve is independent of the others, so a prefix of the sources
+    is a prefix of the whole job), all host threads it is given."""
     import oracle
-    from paper_1811_12391_amd import inputs as I
 
-    xs = prob.xs
-    groups = prob.G if groups is None else groups
-    sub = xs if groups == prob.G else I.XSTables(edges=xs.edges[: groups + 1], sigma_t=xs.sigma_t[:, :groups].copy(),
-                     sigma_s=xs.sigma_s[:, :, :groups, :groups].copy(), kerma=xs.kerma[:, :groups].copy(),
-                     cutoff=xs.cutoff[:, :groups].copy(), names=xs.names, Z=xs.Z)
+    k = prob.B if sources is None else min(sources, prob.B)
     threads = oracle.default_threads()
     oracle.lib()
     t0 = time.perf_counter()
-    r = oracle.solve(prob.phantom, sub, prob.dirs, prob.weights, prob.L, prob.src_pos, prob.src_axis,
-                     prob.fan_deg, prob.cone_deg, prob.group_w[:groups], tol=prob.tol, threads=threads)
+    r = oracle.solve(prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos[:k], prob.src_axis[:k],
+                     prob.fan_deg, prob.cone_deg, prob.group_w, tol=prob.tol, threads=threads)
     dt = time.perf_counter() - t0
     upd = float(r.iters.sum()) * prob.phantom.C * prob.N
     return {"value": upd / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": (f"the whole solve, all {prob.G} groups" if groups == prob.G else
-                       f"first {groups} of {prob.G} groups of the same solve")
+            "sample": (f"whole solves of the first {k} of the {prob.B} sources" if k < prob.B else
+                       f"the whole solve, all {prob.B} source(s)")
                       + f" ({int(r.iters.sum())} source iterations, {dt:.1f} s wall, FP64 C oracle, "
                         f"OpenMP over directions/voxels)"}
+
+
+def sweep_roofline(res, C, workload):
+    """Achieved HBM bandwidth of the sweep kernel: algorithmic bytes (read q,
+    write psi per cell-direction update, plus the two class copies of sigma_t
+    per launch) over the average launch time from HIP events."""
+    s = 8 if res["precision"] == "fp64" else 4
+    launches = res["sweep_launches_per_solve"]
+    bytes_per_solve = res["sweep_updates_per_solve"] * 2 * s + launches * 2 * C * s
+    avg_launch_ms = res["sweep_ms_timed_per_solve"] / res["sweep_launches_timed_per_solve"]
+    achieved = bytes_per_solve / launches / (avg_launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, res["precision"]),
+            "kernel": "k_sweep", "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_solve / launches}
+
+
+def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=None, schedule=None, **extra):
+    """warmup + steps solves (stream launches; HIP events around every
+    PROFILE_EVERY-th sweep launch), each followed by the summed dose into a
+    device buffer; wall time of the timed steps."""
+    import numpy as np
+    import torch
+
+    from paper_1811_12391_amd import dctsn
+
+    kw = dict(precision=precision, tol=prob.tol, fixed_iters=fixed, autotune=True, **extra)
+    if schedule:
+        bk, sync = (int(x) for x in schedule.split(":"))
+        kw.update(autotune=False, sweep_bk=bk, sweep_sync=sync)
+    for _ in range(warmup):
+        solver.solve(**kw)
+        dctsn.dose_dev(solver.h, dose_dev, summed=True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(solver.solve(profile=PROFILE_EVERY, **kw))
+        dctsn.dose_dev(solver.h, dose_dev, summed=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dose = dose_dev.cpu().numpy().copy()
+    upd = float(np.mean([s.sweep_updates for s in stats]))
+    res = {
+        "precision": precision,
+        "ms_per_step": 1e3 * wall / steps,
+        "updates_per_s": upd * steps / wall,
+        "device_ms_per_solve": float(np.mean([s.solve_ms for s in stats])),
+        "sweep_ms_timed_per_solve": float(np.mean([s.sweep_ms for s in stats])),
+        "sweep_launches_per_solve": float(np.mean([s.sweep_launches_all for s in stats])),
+        "sweep_launches_timed_per_solve": float(np.mean([s.sweep_launches for s in stats])),
+        "sweep_updates_per_solve": upd,
+        "iterations": int(stats[-1].iters.sum()),
+        "iters_per_group_max_over_sources": stats[-1].iters.max(0).tolist(),
+        "fixed_iters": fixed is not None,
+        "iteration_sets": int(stats[-1].iteration_sets),
+        "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
+                           "wave_coupling": COUPLINGS.get(int(stats[-1].sweep_sync), str(stats[-1].sweep_sync))},
+        "dose": dose,
+    }
+    _log(f"[bench] {tag}: {res['ms_per_step']:.2f} ms/solve wall, {res['device_ms_per_solve']:.2f} ms device, "
+         f"sweep {1e3 * res['sweep_ms_timed_per_solve'] / res['sweep_launches_timed_per_solve']:.1f} us per launch "
+         f"({res['sweep_launches_timed_per_solve']:.0f} of {res['sweep_launches_per_solve']:.0f} timed), "
+         f"{res['updates_per_s']:.3e} updates/s")
+    return res
+
+
+def run_workload(name, precisions, steps, warmup, schedule=None):
+    """Every precision of one workload; dose error of each against the FP64
+    GPU solve of the same workload (when FP64 is among them)."""
+    import numpy as np
+    import torch
+
+    from paper_1811_12391_amd import dctsn, inputs as I
+
+    prob = I.make_problem(name)
+    C, G = prob.phantom.C, prob.G
+    stream = torch.cuda.current_stream()
+    solver = dctsn.Solver(prob, device=0, stream=ct_stream(stream))
+    dose_dev = torch.empty(C, dtype=torch.float64, device="cuda")
+    results = {}
+    try:
+        for p in precisions:
+            fixed = None
+            if p == "fp32_bf16map":
+                # bf16 map inputs leave a rounding floor above tol 1e-6; run them at
+                # the iteration counts the FP32 solve needed
+                src = results.get("fp32") or results.get("fp64")
+                fixed = (np.array(src["iters_per_group_max_over_sources"], dtype=np.int32) if src
+                         else np.full(G, 12, np.int32))
+            results[p] = timed_solves(solver, prob, p, steps, warmup, f"{name} {p}", dose_dev, fixed, schedule)
+    finally:
+        solver.close()
+    ref = results["fp64"]["dose"] if "fp64" in results else None
+    for r in results.values():
+        if ref is not None:
+            r["dose_l2_rel_err_vs_fp64"] = float(np.linalg.norm(r["dose"] - ref) / np.linalg.norm(ref))
+        r["roofline"] = sweep_roofline(r, C, name)
+    return prob, results
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precisions", default="fp64,fp32,fp32_bf16map")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
-                    help="configuration to time (the headline metric is quoted on c2; the others are for profiling)")
+    ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="configuration of the headline line (the metric is quoted on c4, the largest "
+                         "single-GPU job; the others are for profiling)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched axial-scan and adjoint forms (reported beside the headline)")
+                    help="skip the other workloads and forms reported beside the headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference dispatch for HBM byte counters)")
     ap.add_argument("--schedule", default=None, metavar="BK:SYNC",
@@ -83,94 +180,22 @@ def main():
               "GPUs (right-hand sides, then z slabs) is not built", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_1811_12391_amd import dctsn, inputs as I
-
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prob = I.make_problem(args.workload)
-    C, G, N = prob.phantom.C, prob.G, prob.N
-    solver = dctsn.Solver(prob, device=0, stream=ct_stream(stream))
-    dose_dev = torch.empty(C, dtype=torch.float64, device="cuda")
-
-    def run(precision, steps, warmup, tag, fixed=None):
-        kw = dict(precision=precision, tol=prob.tol, fixed_iters=fixed, autotune=True)
-        if args.schedule:
-            bk, sync = (int(x) for x in args.schedule.split(":"))
-            kw.update(autotune=False, sweep_bk=bk, sweep_sync=sync)
-        for _ in range(warmup):
-            solver.solve(**kw)
-            dctsn.dose_dev(solver.h, dose_dev, summed=True)
-        torch.cuda.synchronize()
-        stats = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            # HIP events around every PROFILE_EVERY-th sweep launch (a sample
-            # over all groups; fewer events disturb the timed solve less)
-            stats.append(solver.solve(profile=PROFILE_EVERY, **kw))
-            dctsn.dose_dev(solver.h, dose_dev, summed=True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        dose = dose_dev.cpu().numpy().copy()
-        upd = float(np.mean([s.sweep_updates for s in stats]))
-        res = {
-            "precision": precision,
-            "ms_per_step": 1e3 * wall / steps,
-            "updates_per_s": upd * steps / wall,
-            "device_ms_per_solve": float(np.mean([s.solve_ms for s in stats])),
-            "sweep_ms_timed_per_solve": float(np.mean([s.sweep_ms for s in stats])),
-            "sweep_launches_per_solve": float(np.mean([s.sweep_launches_all for s in stats])),
-            "sweep_launches_timed_per_solve": float(np.mean([s.sweep_launches for s in stats])),
-            "sweep_updates_per_solve": upd,
-            "iterations": int(stats[-1].iters.sum()),
-            "iters_per_group": stats[-1].iters[0].tolist(),
-            "fixed_iters": fixed is not None,
-            "iteration_sets": int(stats[-1].iteration_sets),
-            "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
-                               "wave_coupling": {1: "lds_counters", 2: "barrier",
-                                                  3: "pipelined_blocks", 4: "layered_waves_4",
-                                                  5: "layered_waves_2"}[int(stats[-1].sweep_sync)]},
-            "dose": dose,
-        }
-        _log(f"[bench] {tag}: {res['ms_per_step']:.2f} ms/solve wall, {res['device_ms_per_solve']:.2f} ms device, "
-             f"sweep {1e3 * res['sweep_ms_timed_per_solve'] / res['sweep_launches_timed_per_solve']:.1f} us per launch "
-             f"({res['sweep_launches_timed_per_solve']:.0f} of {res['sweep_launches_per_solve']:.0f} timed), "
-             f"{res['updates_per_s']:.3e} updates/s")
-        return res
-
     precs = [p for p in args.precisions.split(",") if p]
-    results = {}
-    for p in precs:
-        fixed = None
-        if p == "fp32_bf16map":
-            # bf16 map inputs leave a rounding floor above tol 1e-6; run them at
-            # the iteration counts the FP32 solve needed
-            src = results.get("fp32") or results.get("fp64")
-            fixed = np.array(src["iters_per_group"], dtype=np.int32) if src else np.full(G, 12, np.int32)
-        results[p] = run(p, args.steps, args.warmup, p, fixed)
-    ref = results["fp64"]["dose"] if "fp64" in results else None
-    for p, r in results.items():
-        if ref is not None:
-            r["dose_l2_rel_err_vs_fp64"] = float(np.linalg.norm(r["dose"] - ref) / np.linalg.norm(ref))
+    prob, results = run_workload(args.workload, precs, args.steps, args.warmup, args.schedule)
+    C, G, N = prob.phantom.C, prob.G, prob.N
     # headline: fastest precision meeting the dose-error bar
-    ok = [p for p, r in results.items() if r.get("dose_l2_rel_err_vs_fp64", 0.0) <= 1e-4]
+    ok = [p for p, r in results.items() if r.get("dose_l2_rel_err_vs_fp64", 0.0) <= BAR]
     best = max(ok, key=lambda p: results[p]["updates_per_s"])
     hb = results[best]
-    s = 8 if best == "fp64" else 4
-    # algorithmic bytes of the sweep: read q, write psi per update, plus the
-    # two class copies of sigma_t per cell per launch
-    launches = hb["sweep_launches_per_solve"]
-    bytes_per_solve = hb["sweep_updates_per_solve"] * 2 * s + launches * 2 * C * s
-    avg_launch_ms = hb["sweep_ms_timed_per_solve"] / hb["sweep_launches_timed_per_solve"]
-    achieved = bytes_per_solve / launches / (avg_launch_ms * 1e-3) / 1e9
     line = {
         "metric": METRIC,
         "value": hb["updates_per_s"],
@@ -187,59 +212,59 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "voxels": C, "groups": G, "directions": N, "legendre_order": prob.L, "sources": prob.B,
                    "precision": best},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best) if args.workload == "c2" else None,
-                     "kernel": "k_sweep", "avg_launch_ms": avg_launch_ms,
-                     "bytes_per_launch": bytes_per_solve / launches},
+        "roofline": hb["roofline"],
         "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()},
     }
     if not args.no_forms:
-        solver.close()
-        solver = None
         line["forms"] = other_forms(args)
     if not args.no_cpu_baseline:
         _log("[bench] timing the FP64 CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(prob)
-    if solver is not None:
-        solver.close()
+        line["cpu_baseline"] = cpu_baseline(prob, CPU_SOURCES.get(args.workload))
     print(json.dumps(line), flush=True)
 
 
 def other_forms(args):
-    """The batched, superposed and differentiated forms of the solve, each
-    against the same form in FP64 on the GPU: the 36-source axial scan (FP32,
-    autotuned, graph replay), the 16-beam CT scan superposed into one
-    collided solve (FP32 at the FP64 solve's iteration counts), and the
-    ROI-dose gradient on the 64x64x16 abdomen (FP32 forward + adjoint)."""
+    """The other workloads and forms of the solve, each against the same
+    workload in FP64 on the GPU: the 128 x 128 x 32 abdomen (one source, S8,
+    converged FP32 solve), the single-source 64 x 64 x 16 cylinder (S8; FP64,
+    FP32 and bf16 map inputs), the headline workload replayed from a HIP
+    graph, the 16-beam CT scan superposed into one collided solve (FP32 at
+    the FP64 solve's iteration counts), and the ROI-dose gradient on the
+    64 x 64 x 16 abdomen (FP32 forward + adjoint)."""
     import numpy as np
     import torch
 
     from paper_1811_12391_amd import dctsn, inputs as I
 
     out = {}
-    # axial scan: 36 right-hand sides in one solve
-    prob = I.make_problem("c4")
+
+    def summary(name, results):
+        return {"workload": WORKLOADS[name],
+                "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()}}
+
+    reps = max(1, min(args.steps, 3))
+    for name, precs in (("c3", ["fp64", "fp32"]), ("c2", ["fp64", "fp32", "fp32_bf16map"])):
+        _, res = run_workload(name, precs, reps, 1)
+        out[name] = summary(name, res)
+    # the headline workload with its iteration sets replayed from a HIP graph
+    prob = I.make_problem(args.workload)
     s = dctsn.Solver(prob)
     try:
-        s.solve(precision="fp64", tol=prob.tol)
-        ref = s.dose(summed=True)
         kw = dict(precision="fp32", tol=prob.tol, autotune=True, use_graph=True, chunk=8)
         s.solve(**kw)
         torch.cuda.synchronize()
-        reps = max(1, min(args.steps, 3))
         t0 = time.perf_counter()
         for _ in range(reps):
             st = s.solve(**kw)
         wall = (time.perf_counter() - t0) / reps
-        d = s.dose(summed=True)
         upd = float(st.iters.sum()) * prob.phantom.C * prob.N
-        out["axial_scan_batched"] = {
-            "workload": "c2 cylinder, 36 sources every 10 deg on a 54 cm circle, 19 groups, S6 (48 dirs), P3",
-            "precision": "fp32", "ms_per_solve": 1e3 * wall, "updates_per_s": upd / wall,
-            "sweep_schedule": {"z_layers_per_workgroup": int(st.sweep_bk), "coupling": int(st.sweep_sync)},
-            "summed_dose_l2_rel_err_vs_fp64_gpu": float(np.linalg.norm(d - ref) / np.linalg.norm(ref)),
+        out["headline_graph_replay"] = {
+            "workload": WORKLOADS[args.workload], "precision": "fp32", "ms_per_solve": 1e3 * wall,
+            "updates_per_s": upd / wall, "iteration_sets": int(st.iteration_sets),
+            "sweep_schedule": {"z_layers_per_workgroup": int(st.sweep_bk),
+                               "wave_coupling": COUPLINGS.get(int(st.sweep_sync), str(st.sweep_sync))},
         }
-        _log(f"[bench] axial scan (36 sources) fp32: {1e3 * wall:.1f} ms/solve, {upd / wall:.3e} updates/s")
+        _log(f"[bench] {args.workload} fp32 graph replay: {1e3 * wall:.1f} ms/solve, {upd / wall:.3e} updates/s")
     finally:
         s.close()
     # CT scan as 16 concurrent cone beams superposed into one collided solve,
@@ -328,21 +353,25 @@ WORKLOADS = {
 }
 COPY_BYTES = 256 << 20
 PROFILE_EVERY = 4
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c2_hbm_traffic.txt")
+# sources of the headline workload the CPU oracle solves for its baseline
+# (about 10-20 s of host time)
+CPU_SOURCES = {"c4": 6}
+COUPLINGS = {1: "lds_counters", 2: "barrier", 3: "pipelined_blocks", 4: "layered_waves_4", 5: "layered_waves_2"}
 SWEEP_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_sweep.hip")
 
 
-def measured_traffic(precision):
+def measured_traffic(workload, precision):
     """HBM bytes per sweep launch (FETCH_SIZE + WRITE_SIZE, scaled by the
     same counters on a plain copy of known size) from the committed counter
-    summary, or None when there is none for this precision or the sweep
-    source has changed since the counters were taken."""
+    summary of that workload, or None when there is none for this precision
+    or the sweep source has changed since the counters were taken."""
     import hashlib
 
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)

@@ -244,7 +244,7 @@ def test_c2_bf16_maps_error(c2_ref):
     st, dose, pu, mom = gpu_solve(prob, precision="fp32_bf16map", fixed_iters=c2_ref.iters[0])
     err = l2rel(dose, c2_ref.dose)
     _say(f"[c2] bf16-map dose L2 rel err = {err:.3e}")
-    assert err <= 2e-2
+    assert err <= 3e-4
 
 
 # ------------------------------------------------------------------ schedules, graphs, autotuning
