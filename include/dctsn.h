@@ -225,6 +225,21 @@ int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_u, double *
 int dct_effective_dose(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
                        const uint8_t *zero_material, double *out, int summed);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dct_effective_dose of the last solve written into a caller-allocated
+ * DEVICE buffer out_dev ([B][C] or [C] doubles on the context's device), on
+ * the context's stream (asynchronous; the host tables are read before the
+ * call returns).  It allocates nothing: the per-group factors and material
+ * flags go into a fixed scratch array of the library (2304 bytes per GPU,
+ * held until the process ends) instead of context buffers.
+ *   Limits: G <= 256, M <= 8 (EINVAL beyond).  Errors as dct_effective_dose.
+ *   Every call on one GPU shares that GPU's scratch: calls that overlap on
+ *   one GPU (other streams or threads) race and must be serialised by the
+ *   caller. */
+int dct_effective_dose_noalloc(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
+                               const uint8_t *zero_material, double *out_dev, int summed);
+
 /* Gradient of the response R = sum_b sum_v roi[v] dose_b(v) with respect to
  * every voxel density and every source group weight, by the adjoint of the
  * discretised solve at the converged state of the last dct_solve (which must

@@ -335,6 +335,14 @@ struct DoseArgs {
     const uint8_t *zero_mat;  // [M] nonzero: dose 0 in that material (fluences still written), or null
 };
 
+// Small constant tables passed by value to a one-workgroup kernel that stores
+// them into device memory (no host buffer involved): nd doubles, nb bytes.
+struct StageConsts {
+    int nd, nb;
+    double d[256];
+    unsigned char b[DCT_MAXMAT];
+};
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_trace(const TraceArgs &a, hipStream_t s);
 hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, const double *st, int G, int M,
@@ -350,6 +358,7 @@ hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t 
 hipError_t launch_adj_ray(const AdjRayArgs &a, hipStream_t s);
 hipError_t launch_adj_init(long C, int G, int B, const uint8_t *mat, const double *kap, const double *roi,
                            double *pbu, hipStream_t s);
+hipError_t launch_stage_consts(const StageConsts &c, double *dst_d, unsigned char *dst_b, hipStream_t s);
 hipError_t launch_moments_out(const void *phi_all, long n, double *out, int is_f64, hipStream_t s);
 
 }  // namespace dct

@@ -309,6 +309,20 @@ hipError_t launch_dose(const DoseArgs &a, int is_f64, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_stage_consts(StageConsts c, double *dst_d, unsigned char *dst_b)
+{
+    const int t = threadIdx.x;
+    if (t < c.nd) dst_d[t] = c.d[t];
+    if (t < c.nb) dst_b[t] = c.b[t];
+}
+
+hipError_t launch_stage_consts(const StageConsts &c, double *dst_d, unsigned char *dst_b, hipStream_t s)
+{
+    if (c.nd < 0 || c.nd > 256 || c.nb < 0 || c.nb > DCT_MAXMAT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stage_consts, dim3(1), dim3(256), 0, s, c, dst_d, dst_b);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_widen(const T *src, long n, double *dst)
 {

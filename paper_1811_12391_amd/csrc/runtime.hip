@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,9 +30,45 @@
 
 using namespace dct;
 
+// Fixed device scratch of dct_effective_dose_noalloc: the per-group
+// fluence-to-dose factors (FP64, at most 256 groups, the cap of dct_set_xs)
+// at byte 0 and the per-material zero flags (at most DCT_MAXMAT) at byte 2048.
+// Every GPU holds its own copy for the life of the process; host code only
+// ever uses the device address resolved for that GPU (scratch_dev), never
+// this name.
+#define DCT_NOALLOC_MAXG 256
+#define DCT_NOALLOC_ZOFF 2048
+static __device__ __align__(256) unsigned char scratch[DCT_NOALLOC_ZOFF + 256];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), resolved
+// once per device.
+hipError_t scratch_resolve(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = p;
+    return hipSuccess;
+}
+
+void *scratch_dev(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
 
 struct DevBuf {
     void *p = nullptr;
@@ -159,6 +196,7 @@ int dct_create(dct_ctx **out, int device, void *stream)
             return DCT_EDEVICE;
         }
         e = hipSetDevice(device);
+        if (e == hipSuccess && device < kMaxDevices) e = scratch_resolve(device);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[0]);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[1]);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_t0);
@@ -1198,23 +1236,23 @@ extern "C" int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_
     return dose_common(ctx, dose, summed, phi_u, phi_c, true);
 }
 
-extern "C" int dct_effective_dose(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
-                                  const uint8_t *zero_material, double *out, int summed)
+// Checks of dct_effective_dose's table and its per-group factors: the table
+// at each group's mid energy, linear between points, the end value beyond
+// either end (Sec. III-A).
+static int effective_dose_factors(dct_ctx *ctx, const char *who, int n, const double *energy_keV,
+                                  const double *factor, const void *out, std::vector<double> &hg)
 {
-    if (!ctx) return DCT_EINVAL;
-    ctx->err.clear();
-    if (!ctx->solved) return fail(ctx, DCT_ESTATE, "effective_dose: no valid solve since the last set_* call");
+    const std::string w(who);
+    if (!ctx->solved) return fail(ctx, DCT_ESTATE, w + ": no valid solve since the last set_* call");
     if ((int)ctx->edges.size() != ctx->G + 1)
-        return fail(ctx, DCT_ESTATE, "effective_dose: the group edges were not given to dct_set_xs");
-    if (n < 1 || !energy_keV || !factor || !out) return fail(ctx, DCT_EINVAL, "effective_dose: empty table or NULL");
+        return fail(ctx, DCT_ESTATE, w + ": the group edges were not given to dct_set_xs");
+    if (n < 1 || !energy_keV || !factor || !out) return fail(ctx, DCT_EINVAL, w + ": empty table or NULL");
     if (!finite_all(energy_keV, n) || !finite_all(factor, n))
-        return fail(ctx, DCT_EINVAL, "effective_dose: non-finite table entry");
+        return fail(ctx, DCT_EINVAL, w + ": non-finite table entry");
     for (int i = 0; i + 1 < n; ++i)
         if (!(energy_keV[i] < energy_keV[i + 1]))
-            return fail(ctx, DCT_EINVAL, "effective_dose: table energies must be strictly increasing");
-    // group factor: the table at the group's mid energy, linear between
-    // points, the end value beyond either end
-    std::vector<double> hg(ctx->G);
+            return fail(ctx, DCT_EINVAL, w + ": table energies must be strictly increasing");
+    hg.assign(ctx->G, 0.0);
     for (int g = 0; g < ctx->G; ++g) {
         const double e = 0.5 * (ctx->edges[g] + ctx->edges[g + 1]);
         double h;
@@ -1228,7 +1266,65 @@ extern "C" int dct_effective_dose(dct_ctx *ctx, int n, const double *energy_keV,
         }
         hg[g] = h;
     }
+    return DCT_OK;
+}
+
+extern "C" int dct_effective_dose(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
+                                  const uint8_t *zero_material, double *out, int summed)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    std::vector<double> hg;
+    const int rc = effective_dose_factors(ctx, "effective_dose", n, energy_keV, factor, out, hg);
+    if (rc != DCT_OK) return rc;
     return dose_common(ctx, out, summed, nullptr, nullptr, false, hg.data(), zero_material);
+}
+
+extern "C" int dct_effective_dose_noalloc(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
+                                          const uint8_t *zero_material, double *out_dev, int summed)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (ctx->device < 0) return fail(ctx, DCT_EDEVICE, "effective_dose_noalloc: host-only context");
+    if (ctx->G > DCT_NOALLOC_MAXG || ctx->M > DCT_MAXMAT)
+        return fail(ctx, DCT_EINVAL, "effective_dose_noalloc: at most " + std::to_string(DCT_NOALLOC_MAXG) +
+                                         " groups and " + std::to_string(DCT_MAXMAT) +
+                                         " materials fit the fixed scratch (G = " + std::to_string(ctx->G) + ")");
+    std::vector<double> hg;
+    const int rc = effective_dose_factors(ctx, "effective_dose_noalloc", n, energy_keV, factor, out_dev, hg);
+    if (rc != DCT_OK) return rc;
+    HC(hipSetDevice(ctx->device));
+    unsigned char *sp = (unsigned char *)scratch_dev(ctx->device);
+    if (!sp) return fail(ctx, DCT_EDEVICE, "effective_dose_noalloc: the device scratch was not resolved");
+    hipStream_t s = ctx->stream;
+    const long C = (long)ctx->nx * ctx->ny * ctx->nz;
+    // the factors and flags travel as kernel arguments into the scratch (no
+    // host buffer is read after this call returns, nothing is allocated)
+    StageConsts sc;
+    std::memset(&sc, 0, sizeof(sc));
+    sc.nd = ctx->G;
+    for (int g = 0; g < ctx->G; ++g) sc.d[g] = hg[g];
+    sc.nb = zero_material ? ctx->M : 0;
+    for (int m = 0; m < sc.nb; ++m) sc.b[m] = zero_material[m];
+    HC(launch_stage_consts(sc, (double *)sp, sp + DCT_NOALLOC_ZOFF, s));
+    DoseArgs da;
+    da.C = C;
+    da.G = ctx->G;
+    da.B = ctx->B / ctx->solved_S;
+    da.S = ctx->solved_S;
+    da.Nm = ctx->solved_Nm;
+    da.mat = (const uint8_t *)ctx->bufs["mat"].p;
+    da.kap = (const double *)ctx->bufs["kap"].p;
+    da.phi_u = (const double *)ctx->bufs["phiu"].p;
+    da.phi_all = ctx->bufs["phi"].p;
+    da.dose = out_dev;
+    da.phi_c = nullptr;
+    da.phi_u_out = nullptr;
+    da.summed = summed;
+    da.hg = (const double *)sp;
+    da.zero_mat = zero_material ? (const uint8_t *)(sp + DCT_NOALLOC_ZOFF) : nullptr;
+    HC(launch_dose(da, ctx->solved_prec == DCT_FP64, s));
+    return DCT_OK;
 }
 
 extern "C" int dct_moments(dct_ctx *ctx, double *phi)

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "DCT_OK", -1: "DCT_EINVAL", -2: "DCT_ESTATE", -3: "DCT_EDEVIC
 # every symbol include/dctsn.h declares
 EXPORTS = ["dct_create", "dct_destroy", "dct_last_error", "dct_set_geometry", "dct_set_xs",
            "dct_set_quadrature", "dct_set_source", "dct_set_volume_source", "dct_solve", "dct_dose",
-           "dct_dose_dev", "dct_effective_dose", "dct_adjoint", "dct_moments"]
+           "dct_dose_dev", "dct_effective_dose", "dct_effective_dose_noalloc", "dct_adjoint", "dct_moments"]
 
 
 class DctError(RuntimeError):
@@ -81,6 +81,7 @@ def lib():
         L.dct_adjoint.argtypes = [_vp, _d, ct.POINTER(dct_opts), _d, _d, _d, ct.POINTER(dct_stats)]
         L.dct_moments.argtypes = [_vp, _d]
         L.dct_effective_dose.argtypes = [_vp, ct.c_int, _d, _d, _u8, _d, ct.c_int]
+        L.dct_effective_dose_noalloc.argtypes = [_vp, ct.c_int, _d, _d, _u8, _vp, ct.c_int]
         for n in EXPORTS:
             if n != "dct_last_error":
                 getattr(L, n).restype = ct.c_int
@@ -228,6 +229,17 @@ def effective_dose(h, B, C, energy_keV, factor, *, zero_material=None, summed=Fa
     out = np.zeros(C if summed else (B, C))
     _chk(h, lib().dct_effective_dose(h, int(e.size), _p(e), _p(f), _p(z, _u8), _p(out), int(summed)))
     return out
+
+
+def effective_dose_noalloc(h, energy_keV, factor, out_t, *, zero_material=None, summed=False):
+    """As effective_dose, into a float64 torch tensor on the context's device,
+    through the entry point that allocates no device memory."""
+    e, f = _f64(energy_keV).reshape(-1), _f64(factor).reshape(-1)
+    if e.size != f.size:
+        raise ValueError("energy and factor tables differ in length")
+    z = None if zero_material is None else np.ascontiguousarray(zero_material, dtype=np.uint8)
+    return _chk(h, lib().dct_effective_dose_noalloc(h, int(e.size), _p(e), _p(f), _p(z, _u8), _dev_ptr(out_t),
+                                                    int(summed)))
 
 
 def dose_dev(h, dose_t, summed=False, phi_u_t=None, phi_c_t=None):
