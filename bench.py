@@ -72,7 +72,29 @@ def sweep_roofline(res, C, workload):
             "kernel": "k_sweep", "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_solve / launches}
 
 
+def fused_roofline(res, prob, workload):
+    """Achieved HBM bandwidth of the fused iteration kernel (direction->moment
+    map, combine, moment->direction map): algorithmic bytes per cell of one
+    right-hand side and iteration -- read psi and write q (N values each), read
+    the group source ext and write the moments (Nm values each), read the old
+    phi_00, the material byte and the FP64 density -- over the average launch
+    time from HIP events."""
+    if not res.get("fused_maps") or not res.get("fused_launches_timed_per_solve"):
+        return None
+    s = 8 if res["precision"] == "fp64" else 4
+    N, Nm = prob.N, (prob.L + 1) ** 2
+    cell_iters = res["sweep_updates_per_solve"] / N
+    launches = res["iteration_sets"]                     # one fused launch per iteration set
+    bytes_per_solve = cell_iters * ((2 * N + 2 * Nm + 1) * s + 9)
+    avg_launch_ms = res["fused_ms_timed_per_solve"] / res["fused_launches_timed_per_solve"]
+    achieved = bytes_per_solve / launches / (avg_launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, res["precision"], "k_dcm"),
+            "kernel": "k_dcm", "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_solve / launches}
+
+
 def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=None, schedule=None, **extra):
+    extra.setdefault("fuse_maps", FUSE.get(_ARGS_FUSE[0], 0))
     """warmup + steps solves (stream launches; HIP events around every
     PROFILE_EVERY-th sweep launch), each followed by the summed dose into a
     device buffer; wall time of the timed steps."""
@@ -83,8 +105,10 @@ def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=No
 
     kw = dict(precision=precision, tol=prob.tol, fixed_iters=fixed, autotune=True, **extra)
     if schedule:
-        bk, sync = (int(x) for x in schedule.split(":"))
-        kw.update(autotune=False, sweep_bk=bk, sweep_sync=sync)
+        parts = [int(x) for x in schedule.split(":")]
+        kw.update(autotune=False, sweep_bk=parts[0], sweep_sync=parts[1])
+        if len(parts) > 2:
+            kw.update(sweep_chain=parts[2])
     for _ in range(warmup):
         solver.solve(**kw)
         dctsn.dose_dev(solver.h, dose_dev, summed=True)
@@ -106,13 +130,17 @@ def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=No
         "sweep_ms_timed_per_solve": float(np.mean([s.sweep_ms for s in stats])),
         "sweep_launches_per_solve": float(np.mean([s.sweep_launches_all for s in stats])),
         "sweep_launches_timed_per_solve": float(np.mean([s.sweep_launches for s in stats])),
+        "fused_ms_timed_per_solve": float(np.mean([s.fused_ms for s in stats])),
+        "fused_launches_timed_per_solve": float(np.mean([s.fused_launches for s in stats])),
         "sweep_updates_per_solve": upd,
         "iterations": int(stats[-1].iters.sum()),
         "iters_per_group_max_over_sources": stats[-1].iters.max(0).tolist(),
         "fixed_iters": fixed is not None,
         "iteration_sets": int(stats[-1].iteration_sets),
         "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
-                           "wave_coupling": COUPLINGS.get(int(stats[-1].sweep_sync), str(stats[-1].sweep_sync))},
+                           "wave_coupling": COUPLINGS.get(int(stats[-1].sweep_sync), str(stats[-1].sweep_sync)),
+                           "chained_directions": int(stats[-1].sweep_chain)},
+        "fused_maps": bool(stats[-1].fused_maps),
         "dose": dose,
     }
     _log(f"[bench] {tag}: {res['ms_per_step']:.2f} ms/solve wall, {res['device_ms_per_solve']:.2f} ms device, "
@@ -152,7 +180,13 @@ def run_workload(name, precisions, steps, warmup, schedule=None):
     for r in results.values():
         if ref is not None:
             r["dose_l2_rel_err_vs_fp64"] = float(np.linalg.norm(r["dose"] - ref) / np.linalg.norm(ref))
-        r["roofline"] = sweep_roofline(r, C, name)
+        kernels = [sweep_roofline(r, C, name)]
+        fr = fused_roofline(r, prob, name)
+        if fr is not None:
+            kernels.append(fr)
+        # the dominant kernel: the largest device time per solve
+        r["roofline_kernels"] = kernels
+        r["roofline"] = max(kernels, key=lambda k: k["avg_launch_ms"])
     return prob, results
 
 
@@ -170,11 +204,14 @@ def main():
                     help="skip the other workloads and forms reported beside the headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference dispatch for HBM byte counters)")
+    ap.add_argument("--fuse", default="auto", choices=["auto", "on", "off"],
+                    help="maps and combine as one kernel per iteration (auto: by shape)")
     ap.add_argument("--schedule", default=None, metavar="BK:SYNC",
                     help="pin the sweep schedule of the timed solves (z layers per workgroup : wave "
-                         "coupling) instead of autotuning; for counter runs, where the profiler's "
-                         "serialisation can change the tuner's choice")
+                         "coupling [: chained directions]) instead of autotuning; for counter runs, where "
+                         "the profiler's serialisation can change the tuner's choice")
     args = ap.parse_args()
+    _ARGS_FUSE[0] = args.fuse
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the solve over several "
               "GPUs (right-hand sides, then z slabs) is not built", file=sys.stderr)
@@ -207,12 +244,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp32_bf16map": "f32+bf16"}[best],
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32_bf16map": "f32+bf16", "fp32_bf16x3": "f32+bf16x3"}[best],
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
                    "voxels": C, "groups": G, "directions": N, "legendre_order": prob.L, "sources": prob.B,
                    "precision": best},
         "roofline": hb["roofline"],
+        "roofline_kernels": hb["roofline_kernels"],
         "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()},
     }
     if not args.no_forms:
@@ -243,7 +281,7 @@ def other_forms(args):
                 "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()}}
 
     reps = max(1, min(args.steps, 3))
-    for name, precs in (("c3", ["fp64", "fp32"]), ("c2", ["fp64", "fp32", "fp32_bf16map"])):
+    for name, precs in (("c3", ["fp64", "fp32"]), ("c2", ["fp64", "fp32", "fp32_bf16map", "fp32_bf16x3"])):
         _, res = run_workload(name, precs, reps, 1)
         out[name] = summary(name, res)
     # the headline workload with its iteration sets replayed from a HIP graph
@@ -267,6 +305,63 @@ def other_forms(args):
         _log(f"[bench] {args.workload} fp32 graph replay: {1e3 * wall:.1f} ms/solve, {upd / wall:.3e} updates/s")
     finally:
         s.close()
+    # within-group acceleration (Anderson, depth 2) against plain source
+    # iteration, on the strongly scattering 4-group cylinder and on the headline
+    # workload; and a scan solved position by position, cold and warm started
+    def accel_case(name, precision, reps_):
+        p_ = I.make_problem(name)
+        s_ = dctsn.Solver(p_)
+        res_ = {}
+        try:
+            for m in (0, 2):
+                kw = dict(precision=precision, tol=p_.tol, autotune=True, accel_depth=m)
+                s_.solve(**kw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps_):
+                    st = s_.solve(**kw)
+                wall = (time.perf_counter() - t0) / reps_
+                res_[m] = (wall, st, s_.dose(summed=True))
+        finally:
+            s_.close()
+        (w0, st0, d0), (w2, st2, d2) = res_[0], res_[2]
+        return {"workload": WORKLOADS[name], "precision": precision,
+                "plain": {"ms_per_solve": 1e3 * w0, "iterations": int(st0.iters.sum()),
+                          "fused_maps": bool(st0.fused_maps)},
+                "anderson_depth_2": {"ms_per_solve": 1e3 * w2, "iterations": int(st2.iters.sum()),
+                                     "fused_maps": bool(st2.fused_maps)},
+                "summed_dose_l2_rel_diff": float(np.linalg.norm(d2 - d0) / np.linalg.norm(d0))}
+
+    out["accelerated_c1_fp64"] = accel_case("c1", "fp64", reps)
+    out["accelerated_c4_fp32"] = accel_case("c4", "fp32", 1)
+    for k_, v_ in (("c1", out["accelerated_c1_fp64"]), ("c4", out["accelerated_c4_fp32"])):
+        _log(f"[bench] {k_} accelerated: plain {v_['plain']['iterations']} iterations "
+             f"{v_['plain']['ms_per_solve']:.1f} ms, Anderson {v_['anderson_depth_2']['iterations']} iterations "
+             f"{v_['anderson_depth_2']['ms_per_solve']:.1f} ms")
+    prob = I.make_problem("c4")
+    scan = {}
+    for warm in (False, True):
+        one = I.Problem("c4_one", prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos[:1],
+                        prob.src_axis[:1], prob.fan_deg, prob.cone_deg, prob.group_w)
+        s = dctsn.Solver(one)
+        try:
+            s.solve(precision="fp32", tol=prob.tol, autotune=True)
+            torch.cuda.synchronize()
+            n_it, t0 = 0, time.perf_counter()
+            for p_ in range(prob.B):
+                dctsn.set_source(s.h, 1, prob.src_pos[p_:p_ + 1], prob.src_axis[p_:p_ + 1], prob.fan_deg,
+                                 prob.cone_deg, prob.group_w)
+                st = s.solve(precision="fp32", tol=prob.tol, autotune=True, warm_start=warm)
+                n_it += int(st.iters.sum())
+            wall = time.perf_counter() - t0
+        finally:
+            s.close()
+        scan["warm" if warm else "cold"] = {"ms_total": 1e3 * wall, "iterations": n_it}
+    out["sequential_scan_warm_start"] = {
+        "workload": "the 36 positions of the axial scan solved one after the other (one source per solve), "
+                    "FP32, S6, P3, tol 1e-6", **scan}
+    _log(f"[bench] sequential scan: cold {scan['cold']['iterations']} iterations {scan['cold']['ms_total']:.0f} ms, "
+         f"warm {scan['warm']['iterations']} iterations {scan['warm']['ms_total']:.0f} ms")
     # CT scan as 16 concurrent cone beams superposed into one collided solve,
     # beside one beam alone and the 16 beams as separate right-hand sides
     prob = I.make_problem("ct16")
@@ -356,18 +451,22 @@ PROFILE_EVERY = 4
 # sources of the headline workload the CPU oracle solves for its baseline
 # (about 10-20 s of host time)
 CPU_SOURCES = {"c4": 6}
-COUPLINGS = {1: "lds_counters", 2: "barrier", 3: "pipelined_blocks", 4: "layered_waves_4", 5: "layered_waves_2"}
+COUPLINGS = {1: "lds_counters", 2: "barrier", 3: "pipelined_blocks", 4: "layered_waves_4", 5: "layered_waves_2",
+             6: "chained_directions_1", 7: "chained_directions_2", 8: "chained_directions_4"}
+FUSE = {"auto": 0, "on": 1, "off": -1}
+_ARGS_FUSE = ["auto"]
 SWEEP_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_sweep.hip")
+FUSED_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_source.hip")
 
 
-def measured_traffic(workload, precision):
+def measured_traffic(workload, precision, kernel="k_sweep"):
     """HBM bytes per sweep launch (FETCH_SIZE + WRITE_SIZE, scaled by the
     same counters on a plain copy of known size) from the committed counter
     summary of that workload, or None when there is none for this precision
     or the sweep source has changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -376,9 +475,10 @@ def measured_traffic(workload, precision):
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    with open(SWEEP_SRC, "rb") as f:
+    src = SWEEP_SRC if kernel == "k_sweep" else FUSED_SRC
+    with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if kv.get("k_sweep_sha256") != sha:
+    if kv.get(f"{kernel}_sha256") != sha:
         return None
     v = kv.get(f"bytes_per_launch_{precision}")
     return float(v) if v is not None else None

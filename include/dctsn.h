@@ -54,11 +54,15 @@ extern "C" {
 #define DCT_FP32 1          /* sweeps, moment maps and moment storage FP32 */
 #define DCT_FP32_BF16MAP 2  /* as DCT_FP32, with bf16 inputs to both moment maps
                                (fp32 accumulation) */
+#define DCT_FP32_BF16X3 3   /* as DCT_FP32_BF16MAP with every map input and table entry
+                               split into its bf16 rounding and the bf16 rounding of the
+                               remainder, a b ~ ah bh + ah bl + al bh (three bf16
+                               products per term, fp32 accumulation) */
 
 typedef struct dct_ctx dct_ctx;
 
 typedef struct dct_opts {
-    int precision;            /* DCT_FP64 / DCT_FP32 / DCT_FP32_BF16MAP */
+    int precision;            /* DCT_FP64 / DCT_FP32 / DCT_FP32_BF16MAP / DCT_FP32_BF16X3 */
     double tol;               /* per-group stop: max|dphi_00| / max|phi_00| <= tol */
     int max_iter;             /* per-group iteration cap (>= 1) */
     const int *fixed_iters;   /* [G] or NULL: run exactly this many iterations per group
@@ -69,8 +73,8 @@ typedef struct dct_opts {
     int chunk;                /* iteration sets enqueued between host convergence polls (0 = 4) */
     int use_graph;            /* 1: capture `chunk` iteration sets once in a HIP graph and
                                  replay it until every right-hand side has converged */
-    int profile;              /* k >= 1: time every k-th sweep launch with HIP events
-                                 (dct_stats); ignored when use_graph = 1 */
+    int profile;              /* k >= 1: time every k-th sweep launch (and fused-map launch)
+                                 with HIP events (dct_stats); ignored when use_graph = 1 */
     int keep_adjoint;         /* 1: keep every group's final angular flux and fixup pattern
                                  on the device so that dct_adjoint can follow this solve */
     int autotune;             /* 1: time the candidate sweep schedules (z layers per
@@ -85,7 +89,9 @@ typedef struct dct_opts {
                                  sweeps 4 / 2 z layers as a skewed pipeline in registers,
                                  one barrier per step (needs one block: ny <= 64, nz <= 16,
                                  sweep_bk >= nz; otherwise runs as 2; the transposed sweeps
-                                 of dct_adjoint then use 2); 0 = tuned or 1 */
+                                 of dct_adjoint then use 2); 6 / 7 / 8 = chained directions
+                                 (sweep_chain) with 1 / 2 / 4 z layers per wave; 0 = tuned
+                                 or 1 */
     int superpose;            /* sources per right-hand side S (0 or 1: one each).  With
                                  S > 1 the B sources of dct_set_source form B / S right-hand
                                  sides of S consecutive sources; each is solved once with
@@ -102,6 +108,40 @@ typedef struct dct_opts {
                                  hold eps at a few tol for many iterations.  0 = default (4 in
                                  the reduced-precision modes), < 0 = off; never used in FP64.
                                  Such a stop is not DCT_ENOTCONV; stats->eps shows its eps. */
+    int sweep_chain;          /* directions chained through one sweep workgroup by couplings
+                                 6 / 7 / 8 (1 / 2 / 4 z layers per wave): the K consecutive
+                                 directions of one octant are swept back to back, so the
+                                 wavefront fills and drains once per K directions.  Needs one
+                                 block (ny <= 64, nz <= 16), ny <= nx, keep_adjoint = 0, K
+                                 dividing N with every chain inside one octant; otherwise the
+                                 solve runs coupling 2.  K in [2, 16]; 0 or 1 = no chaining
+                                 (a whole octant when a chained coupling is asked for);
+                                 -1 = the autotuner times the chain lengths with the other
+                                 candidates.  q and psi then use the chain layout. */
+    int fuse_maps;            /* 1: the direction->moment map, the combine (new moments,
+                                 convergence, next within-group source) and the
+                                 moment->direction map of every iteration run as one kernel
+                                 per (z layer, 16 y rows) slab, with the moments and the next
+                                 source kept in LDS (DCT_FP64 / DCT_FP32 only; needs the slab
+                                 tile, about 16 (L+1)^2 nx words, within the workgroup LDS);
+                                 -1: separate kernels; 0: fused when eligible, there are at
+                                 least 1024 slabs over all right-hand sides and two such
+                                 workgroups fit one CU's LDS. */
+    int warm_start;           /* 1: every group starts its source iteration from the moments
+                                 the previous solve on this context left (same right-hand
+                                 sides, groups, P_N order, grid and precision; e.g. the next
+                                 position of a scan after dct_set_source, or perturbed
+                                 densities), instead of from zero; the solve converges to the
+                                 same fixed point.  Falls back to zero when shapes differ. */
+    int accel_depth;          /* 0: plain source iteration within each group.  m in [1, 4]:
+                                 Anderson acceleration of depth m on the scalar-flux moment:
+                                 with G_k the moments from the sweep of iterate phi_k and
+                                 f_k = G_k - phi_k, the next phi_00 is G_k minus the
+                                 combination of the last m differences of G whose f
+                                 differences best cancel f_k (least squares over the voxels,
+                                 FP64); the higher moments keep G_k.  Converges to the same
+                                 discrete solution; eps then measures max|f| / max|G|.  Uses
+                                 the separate map and combine kernels (fuse_maps ignored). */
 } dct_opts;
 
 typedef struct dct_stats {
@@ -117,9 +157,15 @@ typedef struct dct_stats {
     int iteration_sets;       /* iteration launch sets enqueued (>= max over RHS of iterations) */
     int sweep_bk;             /* sweep schedule that ran: z layers per workgroup */
     int sweep_sync;           /* and coupling (1 LDS counters, 2 barriers, 3 pipelined blocks,
-                                 4 / 5 layered waves of 4 / 2 z layers) */
+                                 4 / 5 layered waves of 4 / 2 z layers, 6 / 7 / 8 chained
+                                 directions with 1 / 2 / 4 z layers per wave) */
     double tune_ms;           /* device time spent timing candidate schedules in this call */
     long long sweep_launches_all; /* sweep kernel launches of the iteration sets (timed or not) */
+    int sweep_chain;          /* directions per chained sweep workgroup that ran (1 = none) */
+    int fused_maps;           /* 1 when the maps and the combine ran as one kernel */
+    int warm_start;           /* 1 when the solve started from the previous solve's moments */
+    double fused_ms;          /* summed device time of the timed fused-map launches (profile > 0) */
+    int fused_launches;       /* fused-map launches whose time is in fused_ms */
 } dct_stats;
 
 /* Create a context on HIP device `device` using `stream` (a hipStream_t; NULL

@@ -26,6 +26,7 @@
 #define DCT_MAXMAT 8
 #define DCT_MAXL 5
 #define DCT_MAXNM ((DCT_MAXL + 1) * (DCT_MAXL + 1))
+#define DCT_MAXCHAIN 16   // directions chained through one sweep workgroup
 #define DCT_PI 3.14159265358979323846
 
 namespace dct {
@@ -83,6 +84,44 @@ __host__ __device__ inline void real_sh_cart(int L, R x, R y, R z, R *Y)
         }
     }
 }
+
+// Chain layout of the direction-space arrays (K consecutive directions of one
+// octant swept by one workgroup): direction n = n0 + d of the chain starting
+// at n0 keeps its cell (i, j, k) at element n0 C + (k K nx + row) ny + j with
+//   X = d nx + i (Omega_x > 0) or (K - 1 - d) nx + i (Omega_x < 0),
+//   row = (X + j) mod K nx (class A) or (X - j) mod K nx (class B).
+// K = 1 is the class layout.  From a class-layout position (k, r, j):
+// i = (r -+ j) mod nx.
+__host__ __device__ inline long chain_pos(int cls, int K, int d, bool sxpos, int r, int j, int k, int nx, int ny)
+{
+    const int Knx = K * nx;
+    int i = cls == 0 ? r - j % nx : r + j % nx;
+    if (i < 0) i += nx;
+    if (i >= nx) i -= nx;
+    const int X = (sxpos ? d : K - 1 - d) * nx + i;
+    int row = (cls == 0 ? X + j : X - j) % Knx;
+    if (row < 0) row += Knx;
+    return ((long)k * Knx + row) * ny + j;
+}
+
+// ---------------------------------------------------------------- matrix cores
+// 16 x 16 x 4 MFMA tiles (f64, f32): operand placement over the 64 lanes,
+// lane = col + 16 * krow:  A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k;
+// D[i][j]: f32 at lane j + 16 (i / 4), element i % 4; f64 at lane j + 16 (i % 4),
+// element i / 4 (out_row gives i for lane group kr and element r).
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline d4_t mfma_k4(double a, double b, d4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f4_t mfma_k4(float a, float b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+template <typename T> struct acc4;
+template <> struct acc4<double> { typedef d4_t type; };
+template <> struct acc4<float> { typedef f4_t type; };
+
+template <typename T> __device__ inline int out_row(int kr, int r) { return 4 * kr + r; }
+template <> __device__ inline int out_row<double>(int kr, int r) { return kr + 4 * r; }
 
 // ---------------------------------------------------------------- buffer access
 // Raw buffer access through a descriptor (base, byte range): an offset at or
@@ -158,7 +197,11 @@ struct RhsState {
     unsigned int cnt_combine, cnt_trans;   // last-block-done counters
     double eps_best;  // smallest eps of the group so far (reduced-precision stop)
     int stall;        // consecutive iterations near tol without a new minimum
+    int aa_mk;        // Anderson acceleration: differences used in the last mixing
+    double aa_gam[4]; //   and their coefficients
 };
+
+
 
 // group actually processed at position g of the group sequence
 __host__ __device__ inline int eff_group(int g, int G, int reverse) { return reverse ? G - 1 - g : g; }
@@ -168,6 +211,30 @@ struct Geo {
     long C;
     double dx, dy, dz;
     double org[3];
+};
+
+#define DCT_AA_MAXM 4
+#define DCT_AA_NDOT 14   // Gram entries (m (m + 1) / 2) + right-hand side (m) for m <= 4
+
+// Anderson acceleration (depth m) of the within-group source iteration on the
+// scalar-flux moment phi_00 of every right-hand side.
+struct AAArgs {
+    Geo geo;
+    int G, Nm, L, B, m;
+    int reverse;
+    RhsState *state;
+    const uint8_t *mat;
+    const double *rho;
+    const double *ss;         // [M][L+1][G][G]
+    void *phi_all;            // T [B][G][Nm][C]
+    const void *ext;          // T [B][Nm][C]
+    void *Qc;                 // T [2][B][Nm][C]
+    double *phik;             // [B][C] the iterate phi_k,00 whose sweep produced G_k
+    double *hG, *hF;          // [B][m+1][C] rings of G_k,00 = F(phi_k) and f_k = G_k - phi_k
+    double *part;             // [B][nblk][DCT_AA_NDOT] per-workgroup dot products
+    unsigned *cnt_sub;        // [B][nsub][32] completion sub-counters (zero between launches)
+    int nsub;
+    unsigned *cnt_top;        // [B] (one per right-hand side, on its own 128-byte line)
 };
 
 struct TraceArgs {
@@ -187,6 +254,8 @@ struct TransArgs {
     Geo geo;
     int G, M, L, Nm, N, B;
     int S;                    // sources per right-hand side (superposed beams)
+    int warm;                 // 1: a new group starts from the moments already in phi_all
+    double *aa_phik;          // [B][C] starting iterate phi_00 of the group (Anderson), or null
     double V;
     const uint8_t *mat;
     const double *rho;
@@ -231,6 +300,8 @@ struct CombArgs {
     int reverse;              // groups run from G-1 down to 0
     unsigned *cnt_mom;        // [B][Nm][32] completion counters of the moment groups, one per 128-byte line
     int mpw;                  // moments per workgroup (>= 1)
+    int warm;                 // 1: the first source of a group includes the self-scatter of
+                              //    the starting moments (warm start), not Q = ext
 };
 
 struct MapArgs {
@@ -248,7 +319,46 @@ struct MapArgs {
     int G, reverse;
     void *part;               // T [2][B][Nm][C]
     const RhsState *state;
+    int chainK;               // > 1: q and psi in the chain layout (K consecutive directions per block)
+    int nx, ny;               // grid (for the chain layout)
+    const int *chn0;          // [N] first direction of n's chain (chain layout only)
+    const int *chxo;          // [N] x offset of n's slot in the chain's K nx columns: d nx, or
+                              //     (K - 1 - d) nx when Omega_x < 0 (chain layout only)
+    int first_only;           // M map: only right-hand sides at the first iteration of a group
 };
+
+// Cell of a class-layout position p = (k nx + r) ny + j of class cls, for
+// addressing q / psi in the chain layout (x = i, y = j, z = k).
+struct CellKJI {
+    int k, j, i;
+};
+__device__ inline CellKJI cell_of(const MapArgs &a, int cls, long p)
+{
+    const int pl = a.nx * a.ny;                      // C < 2^28: 32-bit arithmetic
+    const int pi = (int)p;
+    const int k = pi / pl;
+    const int rem = pi - k * pl;
+    const int r = rem / a.ny, j = rem - r * a.ny;
+    int i = cls == 0 ? r - j % a.nx : r + j % a.nx;
+    if (i < 0) i += a.nx;
+    if (i >= a.nx) i -= a.nx;
+    return CellKJI{k, j, i};
+}
+
+// Element offset of direction n of class cls at class-layout position p (cell
+// c = cell_of(p)) in q / psi: the class layout, or the chain layout when
+// a.chainK > 1 (a.chn0[n]: first direction of n's chain, a.chxo[n]: x offset
+// of n's slot in the chain's virtual grid of K nx columns).
+__device__ inline long dir_elem(const MapArgs &a, int cls, int n, long p, const CellKJI &c)
+{
+    if (a.chainK <= 1) return (long)n * a.C + p;
+    const int Knx = a.chainK * a.nx;
+    const int X = a.chxo[n] + c.i;
+    int row = cls == 0 ? X + c.j : X - c.j;
+    if (row >= Knx) row -= Knx;
+    if (row < 0) row += Knx;
+    return (long)a.chn0[n] * a.C + ((long)c.k * Knx + row) * a.ny + c.j;
+}
 
 struct SweepArgs {
     int nx, ny, nz;
@@ -279,6 +389,9 @@ struct SweepArgs {
     unsigned seq;             // host launch counter, part of the launch tag
     int *err;                 // set to non-zero when a bounded wait overflowed
     int layers;               // > 1: every wave sweeps this many z layers (single block, forward only)
+    int chainK;               // > 1: K consecutive directions of one octant per workgroup (k_sweep_ch);
+                              //      q, psi in the chain layout, sigma_t from sigch
+    const void *sigch;        // T [2][G][K C] sigma_t in the chain layout of period K nx
 };
 
 struct AdjTransArgs {
@@ -347,9 +460,17 @@ struct StageConsts {
 hipError_t launch_trace(const TraceArgs &a, hipStream_t s);
 hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, const double *st, int G, int M,
                        void *sigc, int is_f64, hipStream_t s);
+// sigma_t of every group in the chain layout of period K nx (K copies)
+hipError_t launch_sigch(const Geo &g, const void *sigc, int G, int K, void *sigch, int is_f64, hipStream_t s);
 hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_combine(const CombArgs &a, int is_f64, hipStream_t s);
-hipError_t launch_qinit(const CombArgs &a, int is_f64, hipStream_t s);   // Q = ext in the class layouts after a transition
+hipError_t launch_qinit(const CombArgs &a, int is_f64, hipStream_t s);
+// Anderson acceleration: dot products and mixing coefficients, then the mixed
+// iterate phi_00 (and the moment-0 source in both class layouts)
+hipError_t launch_aa(const AAArgs &a, int is_f64, hipStream_t s);
+// D map + combine + M map of one iteration in one kernel (forward FP64 / FP32 solves)
+hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s);
+size_t dcm_lds_bytes(const CombArgs &a, const MapArgs &m, int is_f64);   // Q = ext in the class layouts after a transition
 hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f64, 1 f32, 2 bf16
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);
 hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq);

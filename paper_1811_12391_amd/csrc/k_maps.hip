@@ -20,20 +20,6 @@
 
 namespace dct {
 
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef short s4_t __attribute__((ext_vector_type(4)));
-
-__device__ inline d4_t mfma_k4(double a, double b, d4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-__device__ inline f4_t mfma_k4(float a, float b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-
-template <typename T> struct acc4;
-template <> struct acc4<double> { typedef d4_t type; };
-template <> struct acc4<float> { typedef f4_t type; };
-
-// output row (within a 16-row tile) held by lane group kr in element r
-template <typename T> __device__ inline int out_row(int kr, int r) { return 4 * kr + r; }
-template <> __device__ inline int out_row<double>(int kr, int r) { return kr + 4 * r; }
 
 // round-to-nearest-even fp32 -> bf16 bits
 __device__ inline short to_bf16(float f)
@@ -41,6 +27,22 @@ __device__ inline short to_bf16(float f)
     unsigned u = __float_as_uint(f);
     u += 0x7fffu + ((u >> 16) & 1u);
     return (short)(u >> 16);
+}
+
+// bf16 bits back to fp32 (exact)
+__device__ inline float from_bf16(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+// bf16 product of split operands: a b ~ ah bh + ah bl + al bh (the high
+// parts round to bf16, the low parts are the bf16-rounded remainders), summed
+// in fp32 smallest terms first; SPLIT = false keeps the single product ah bh
+template <bool SPLIT>
+__device__ inline f4_t mfma_bf16x(s4_t ah, s4_t al, s4_t bh, s4_t bl, f4_t acc)
+{
+    if (SPLIT) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
 }
 
 // One class's map table [rows][cols] into LDS with row stride ST, and its
@@ -79,11 +81,13 @@ __global__ __launch_bounds__(256) void k_mmap(MapArgs a)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
     if (a.state[b].finished) return;
+    if (a.first_only && (a.state[b].it != 0 || a.state[b].pending)) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
     const long pc = inb ? p : C - 1;
+    const CellKJI cp = a.chainK > 1 ? cell_of(a, c, pc) : CellKJI{0, 0, 0};
     const int Nm = a.Nm, Nc = a.Nc[c], NmP = a.NmP, ST = a.NmP + 1;
     const T *Q = (const T *)a.Qc + ((long)c * a.B + b) * Nm * C;
     T bq[NS];
@@ -101,22 +105,24 @@ __global__ __launch_bounds__(256) void k_mmap(MapArgs a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int nl = rb * 16 + out_row<T>(kr, r);
-            if (nl < Nc && inb) q[(long)cds[nl] * C + p] = acc[r];
+            if (nl < Nc && inb) q[dir_elem(a, c, cds[nl], p, cp)] = acc[r];
         }
     }
 }
 
-template <int NS16>
+template <int NS16, bool SPLIT>
 __global__ __launch_bounds__(256) void k_mmap_bf16(MapArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_map[];
     const int b = blockIdx.z, c = blockIdx.y;
     if (a.state[b].finished) return;
+    if (a.first_only && (a.state[b].it != 0 || a.state[b].pending)) return;
     const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
     const long C = a.C;
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
     const long pc = inb ? p : C - 1;
+    const CellKJI cp = a.chainK > 1 ? cell_of(a, c, pc) : CellKJI{0, 0, 0};
     const int Nm = a.Nm, Nc = a.Nc[c], NmP = a.NmP, ST = a.NmP + 4;   // 8-byte aligned rows
     const float *Q = (const float *)a.Qc + ((long)c * a.B + b) * Nm * C;
     float fq[NS16][4];
@@ -124,27 +130,36 @@ __global__ __launch_bounds__(256) void k_mmap_bf16(MapArgs a)
     for (int s = 0; s < NS16; ++s)
 #pragma unroll
         for (int e = 0; e < 4; ++e) fq[s][e] = Q[(long)min(16 * s + 4 * kr + e, Nm - 1) * C + pc];
-    short *tab = (short *)smem_map;                      // [NcP][NmP + 4]
-    int *cds = (int *)(tab + (long)a.NcP * ST);
+    short *tab = (short *)smem_map;                      // [NcP][NmP + 4] (high parts)
+    short *tabl = tab + (long)a.NcP * ST;                // [NcP][NmP + 4] (remainders, SPLIT)
+    int *cds = (int *)(tab + (long)(SPLIT ? 2 : 1) * a.NcP * ST);
     stage_table(tab, ST, (const short *)a.Mtab + (long)c * a.NcP * NmP, a.NcP, NmP, cds, a.cdir + c * a.N, Nc);
+    if (SPLIT)
+        stage_table(tabl, ST, (const short *)a.Mtab + (long)(2 + c) * a.NcP * NmP, a.NcP, NmP, cds,
+                    a.cdir + c * a.N, Nc);
     __syncthreads();
-    s4_t bq[NS16];
+    s4_t bq[NS16], bql[NS16];
 #pragma unroll
     for (int s = 0; s < NS16; ++s)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) bq[s][e] = to_bf16(fq[s][e]);
+        for (int e = 0; e < 4; ++e) {
+            bq[s][e] = to_bf16(fq[s][e]);
+            bql[s][e] = SPLIT ? to_bf16(fq[s][e] - from_bf16(bq[s][e])) : (short)0;
+        }
     float *q = (float *)a.q + (long)b * a.N * C;
     for (int rb = 0; rb * 16 < Nc; ++rb) {
         f4_t acc = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < NS16; ++s) {
-            s4_t av = *(const s4_t *)(tab + (rb * 16 + col) * ST + 16 * s + 4 * kr);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bq[s], acc, 0, 0, 0);
+            const int o = (rb * 16 + col) * ST + 16 * s + 4 * kr;
+            const s4_t av = *(const s4_t *)(tab + o);
+            const s4_t avl = SPLIT ? *(const s4_t *)(tabl + o) : av;
+            acc = mfma_bf16x<SPLIT>(av, avl, bq[s], bql[s], acc);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int nl = rb * 16 + 4 * kr + r;
-            if (nl < Nc && inb) q[(long)cds[nl] * C + p] = acc[r];
+            if (nl < Nc && inb) q[dir_elem(a, c, cds[nl], p, cp)] = acc[r];
         }
     }
 }
@@ -168,6 +183,7 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
     const long pc = inb ? p : C - 1;
+    const CellKJI cp = a.chainK > 1 ? cell_of(a, c, pc) : CellKJI{0, 0, 0};
     const int Nm = a.Nm, Nc = a.Nc[c], NcP = a.NcP, ST = a.NcP + 1;
     const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const T *psi = (const T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
@@ -182,7 +198,7 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
 #pragma unroll
         for (int u = 0; u < KC; ++u) dn[u] = cdg[min(k0 + 4 * u + kr, Nc - 1)];
 #pragma unroll
-        for (int u = 0; u < KC; ++u) bv[u] = psi[(long)dn[u] * C + pc];
+        for (int u = 0; u < KC; ++u) bv[u] = psi[dir_elem(a, c, dn[u], pc, cp)];
     };
     load_chunk(0);
     T *tab = (T *)smem_map;                              // [NmP][NcP + 1]
@@ -212,6 +228,7 @@ __global__ __launch_bounds__(256) void k_dmap(MapArgs a)
         }
 }
 
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
 {
     constexpr int KC = 4;                                // K-steps of 16 directions per load round
@@ -223,10 +240,15 @@ __global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
     const long p = (long)blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + col;
     const bool inb = p < C;
     const long pc = inb ? p : C - 1;
+    const CellKJI cp = a.chainK > 1 ? cell_of(a, c, pc) : CellKJI{0, 0, 0};
     const int Nm = a.Nm, Nc = a.Nc[c], NcP = a.NcP, ST = a.NcP + 4;
-    short *tab = (short *)smem_map;                      // [NmP][NcP + 4]
-    int *cds = (int *)(tab + (long)a.NmP * ST);
+    short *tab = (short *)smem_map;                      // [NmP][NcP + 4] (high parts)
+    short *tabl = tab + (long)a.NmP * ST;                // [NmP][NcP + 4] (remainders, SPLIT)
+    int *cds = (int *)(tab + (long)(SPLIT ? 2 : 1) * a.NmP * ST);
     stage_table(tab, ST, (const short *)a.Dtab + (long)c * a.NmP * NcP, a.NmP, NcP, cds, a.cdir + c * a.N, Nc);
+    if (SPLIT)
+        stage_table(tabl, ST, (const short *)a.Dtab + (long)(2 + c) * a.NmP * NcP, a.NmP, NcP, cds,
+                    a.cdir + c * a.N, Nc);
     __syncthreads();
     const int g = eff_group(a.state[b].g, a.G, a.reverse);
     const float *psi = (const float *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs) * C;
@@ -239,18 +261,23 @@ __global__ __launch_bounds__(256) void k_dmap_bf16(MapArgs a)
         for (int u = 0; u < KC; ++u)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                fv[u][e] = psi[(long)cds[min(k0 + 16 * u + 4 * kr + e, Nc - 1)] * C + pc];
+                fv[u][e] = psi[dir_elem(a, c, cds[min(k0 + 16 * u + 4 * kr + e, Nc - 1)], pc, cp)];
 #pragma unroll
         for (int u = 0; u < KC; ++u)
             if (k0 + 16 * u < Nc) {
-                s4_t bv;
+                s4_t bv, bvl;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) bv[e] = to_bf16(fv[u][e]);
+                for (int e = 0; e < 4; ++e) {
+                    bv[e] = to_bf16(fv[u][e]);
+                    bvl[e] = SPLIT ? to_bf16(fv[u][e] - from_bf16(bv[e])) : (short)0;
+                }
 #pragma unroll
                 for (int rb = 0; rb < 3; ++rb)
                     if (rb < nrb) {
-                        s4_t av = *(const s4_t *)(tab + (rb * 16 + col) * ST + k0 + 16 * u + 4 * kr);
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[rb], 0, 0, 0);
+                        const int o = (rb * 16 + col) * ST + k0 + 16 * u + 4 * kr;
+                        const s4_t av = *(const s4_t *)(tab + o);
+                        const s4_t avl = SPLIT ? *(const s4_t *)(tabl + o) : av;
+                        acc[rb] = mfma_bf16x<SPLIT>(av, avl, bv, bvl, acc[rb]);
                     }
             }
     }
@@ -305,11 +332,16 @@ hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s)
     if (mode == 0) dispatch_mmap<double>(a, grid, s);
     else if (mode == 1) dispatch_mmap<float>(a, grid, s);
     else {
-        int NS16 = (a.Nm + 15) / 16;
-        const size_t shm = (size_t)a.NcP * (a.NmP + 4) * 2 + (size_t)a.N * 4;
-        if (NS16 == 1) hipLaunchKernelGGL(k_mmap_bf16<1>, grid, dim3(256), shm, s, a);
-        else if (NS16 == 2) hipLaunchKernelGGL(k_mmap_bf16<2>, grid, dim3(256), shm, s, a);
-        else hipLaunchKernelGGL(k_mmap_bf16<3>, grid, dim3(256), shm, s, a);
+        // mode 2: bf16 inputs; mode 3: split bf16 inputs (high part + remainder)
+        const int NS16 = (a.Nm + 15) / 16;
+        const size_t shm = (size_t)(mode == 3 ? 2 : 1) * a.NcP * (a.NmP + 4) * 2 + (size_t)a.N * 4;
+#define DCT_MB(NS, SP) hipLaunchKernelGGL((k_mmap_bf16<NS, SP>), grid, dim3(256), shm, s, a)
+        if (mode == 3) {
+            if (NS16 == 1) DCT_MB(1, true); else if (NS16 == 2) DCT_MB(2, true); else DCT_MB(3, true);
+        } else {
+            if (NS16 == 1) DCT_MB(1, false); else if (NS16 == 2) DCT_MB(2, false); else DCT_MB(3, false);
+        }
+#undef DCT_MB
     }
     return hipGetLastError();
 }
@@ -319,7 +351,11 @@ hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s)
     dim3 grid((unsigned)((a.C + 63) / 64), 2, a.B);
     if (mode == 0) dispatch_dmap<double>(a, grid, s);
     else if (mode == 1) dispatch_dmap<float>(a, grid, s);
-    else hipLaunchKernelGGL(k_dmap_bf16, grid, dim3(256), (size_t)a.NmP * (a.NcP + 4) * 2 + (size_t)a.N * 4, s, a);
+    else {
+        const size_t shm = (size_t)(mode == 3 ? 2 : 1) * a.NmP * (a.NcP + 4) * 2 + (size_t)a.N * 4;
+        if (mode == 3) hipLaunchKernelGGL(k_dmap_bf16<true>, grid, dim3(256), shm, s, a);
+        else hipLaunchKernelGGL(k_dmap_bf16<false>, grid, dim3(256), shm, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -142,7 +142,9 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
             for (int lm = 0; lm < NM; ++lm) {
                 T et = (T)e[lm];
                 ext[(long)lm * C + v] = et;
-                phi_all[(((long)b * G + g) * Nm + lm) * C + v] = (T)0;
+                if (!a.warm) phi_all[(((long)b * G + g) * Nm + lm) * C + v] = (T)0;
+                if (lm == 0 && a.aa_phik)
+                    a.aa_phik[(long)b * C + v] = a.warm ? (double)phi_all[(((long)b * G + g) * Nm) * C + v] : 0.0;
                 if (lm == 0) Pp = e[0];
             }
         }
@@ -334,6 +336,55 @@ hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s)
     if (is_f64) DCT_BY_ORDER(k_transition, double, a.L, grid, dim3(256), 0, s, a);
     else DCT_BY_ORDER(k_transition, float, a.L, grid, dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+// End of an iteration of right-hand side b (called by the one workgroup
+// that completes it, after every workgroup's eps atomics): relative change
+// of phi_00, the stopping rule, and the move to the next group.
+__device__ inline void close_iteration(const CombArgs &a, RhsState *st, int b, int gseq, int g)
+{
+    const int G = a.G;
+    wait_own_memory_ops();
+    double num = __longlong_as_double((long long)atomicAdd(&st->eps_num, 0ull));
+    double den = __longlong_as_double((long long)atomicAdd(&st->eps_den, 0ull));
+    int it = st->it + 1;
+    st->it = it;
+    bool bad = !isfinite(num) || !isfinite(den);
+    double e = den > 0.0 ? num / den : 0.0;
+    bool stop;
+    if (bad) {
+        st->nan = 1;
+        stop = true;
+    } else if (a.fixed_iters) {
+        stop = it >= a.fixed_iters[g];
+    } else {
+        bool conv = e <= a.tol;
+        if (!conv && a.stall_window > 0) {
+            // reduced precision: eps near tol that stops improving is
+            // rounding noise (flipping set-to-zero decisions), not slow
+            // convergence
+            if (it == 1 || e < st->eps_best) {
+                st->eps_best = e;
+                st->stall = 0;
+            } else if (e <= 10.0 * a.tol) {
+                conv = ++st->stall >= a.stall_window;
+            } else {
+                st->stall = 0;
+            }
+        }
+        stop = conv || (it >= a.max_iter);
+        if (stop && !conv) st->notconv = 1;
+    }
+    if (stop) {
+        a.iters[(long)b * G + g] = it;
+        a.eps[(long)b * G + g] = e;
+        st->g = bad ? G : gseq + 1;
+        st->it = 0;
+        st->pending = 1;
+    }
+    st->eps_num = 0ull;
+    st->eps_den = 0ull;
+    st->cnt_combine = 0;
 }
 
 // LDS tile of one slab (z layer k, 16 consecutive y rows, all x).
@@ -535,50 +586,441 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
             wait_own_memory_ops();
             prev = atomicAdd(&st->cnt_combine, 1u) + 1u;
         }
-        if (prev == (unsigned)nmg) {
-            wait_own_memory_ops();
-            double num = __longlong_as_double((long long)atomicAdd(&st->eps_num, 0ull));
-            double den = __longlong_as_double((long long)atomicAdd(&st->eps_den, 0ull));
-            int it = st->it + 1;
-            st->it = it;
-            bool bad = !isfinite(num) || !isfinite(den);
-            double e = den > 0.0 ? num / den : 0.0;
-            bool stop;
-            if (bad) {
-                st->nan = 1;
-                stop = true;
-            } else if (a.fixed_iters) {
-                stop = it >= a.fixed_iters[g];
-            } else {
-                bool conv = e <= a.tol;
-                if (!conv && a.stall_window > 0) {
-                    // reduced precision: eps near tol that stops improving is
-                    // rounding noise (flipping set-to-zero decisions), not
-                    // slow convergence
-                    if (it == 1 || e < st->eps_best) {
-                        st->eps_best = e;
-                        st->stall = 0;
-                    } else if (e <= 10.0 * a.tol) {
-                        conv = ++st->stall >= a.stall_window;
-                    } else {
-                        st->stall = 0;
+        if (prev == (unsigned)nmg) close_iteration(a, st, b, gseq, g);
+    }
+}
+
+// Fused direction->moment map, combine and moment->direction map of one
+// source iteration (eq. 2 with the Legendre-expanded scattering kernel as
+// M Sigma D; eq. 3 is row 0 of D).  One workgroup per slab (z layer k, 16 y
+// rows, all x) of one right-hand side.  A slab is closed under both class
+// rotations, so everything between reading psi and writing the next q stays
+// in LDS:
+//   1. the D map of each class on the matrix cores, its moments scattered
+//      into a natural-layout tile (class A stores, class B adds);
+//   2. combine: the new moments phi (stored), the change of phi_00 and the
+//      next within-group source Q = ext + sigma_s^{gg} phi, into the tile;
+//   3. the M map of each class from the tile; q stored for the next sweep.
+// The class partials and Q never reach HBM.  Each step does the arithmetic
+// of k_dmap, k_combine and k_mmap in the same order, so the results are the
+// same bit for bit.  The last workgroup of the right-hand side applies the
+// stopping rule; when the group stops, the q written here is replaced after
+// the transition (the M map runs for the first iteration of a group).
+template <typename T, int NRB, int KC>
+__global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
+{
+    typedef typename acc4<T>::type A4;                        // KC: K-steps of 4 directions, covering a class
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ double red[16];
+    __shared__ double ssg[DCT_MAXMAT * (DCT_MAXL + 1)];
+    const int b = blockIdx.y;
+    RhsState *st = a.state + b;
+    if (st->finished) return;
+    const int gseq = st->g;
+    const int g = eff_group(gseq, a.G, a.reverse);
+    const int nx = a.geo.nx, ny = a.geo.ny;
+    const long C = a.geo.C;
+    const int G = a.G, Nm = a.Nm, L = a.L, N = m.N;
+    const int nslj = (ny + 15) >> 4;
+    const int k = blockIdx.x / nslj, j0 = (blockIdx.x % nslj) * 16;
+    const int pitch = (nx | 1) + 1;
+    // moment stride of the tile: 16 rows plus 4 words, so that the 4 lane
+    // groups of an MFMA output (moments 4 apart) fall in different banks
+    const int LMS = 16 * pitch + 4;
+    const int NcP = m.NcP, NmP = m.NmP, DST = NcP + 1, MST = NmP + 1;
+    T *tile = (T *)smem_raw;                                  // [Nm][LMS]: 16 rows of pitch, natural x
+    T *Dt = tile + (long)Nm * LMS;                            // [2][NmP][NcP + 1]
+    T *Mt = Dt + 2 * NmP * DST;                               // [2][NcP][NmP + 1]
+    int *cds = (int *)(Mt + 2 * NcP * MST);                   // [2][N] class-local -> global direction
+    for (int i = threadIdx.x; i < 2 * NmP * NcP; i += blockDim.x) {
+        const int c = i / (NmP * NcP), r = (i / NcP) % NmP, q = i % NcP;
+        Dt[(c * NmP + r) * DST + q] = ((const T *)m.Dtab)[i];
+    }
+    for (int i = threadIdx.x; i < 2 * NcP * NmP; i += blockDim.x) {
+        const int c = i / (NcP * NmP), r = (i / NmP) % NcP, q = i % NmP;
+        Mt[(c * NcP + r) * MST + q] = ((const T *)m.Mtab)[i];
+    }
+    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) cds[i] = m.cdir[i];
+    if ((int)threadIdx.x < a.M * (L + 1)) {
+        const int mm = threadIdx.x / (L + 1), ll = threadIdx.x - mm * (L + 1);
+        ssg[threadIdx.x] = a.ss[(((long)mm * (L + 1) + ll) * G + g) * G + g];
+    }
+    __syncthreads();
+    const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
+    const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    const int jj = j0 + col;                                  // y row of this lane's column
+    const bool jok = jj < ny;
+    const int jc = jok ? jj : ny - 1;
+    const int jm = jc % nx;
+    // ---- 1. D map of each class into the natural tile.  A wave takes two
+    // rows at a time and loads the psi operands of its next pair (the first
+    // pair of class B after the last of class A) before the matrix-core work
+    // of the current one, so two pairs of loads are in flight.
+    const T *psi = (const T *)m.psi + ((long)b * m.psi_bs + (long)g * m.psi_gs) * C;
+    T bA[2][KC], bB[2][KC];
+    auto load_pair = [&](int c, int r0, T (&bv)[2][KC]) __attribute__((always_inline)) {
+        const int Nc = m.Nc[c];
+        const int *cd = cds + c * N;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = min(r0 + h * nwv, nx - 1);
+            const long p = ((long)k * nx + r) * ny + jc;
+            const CellKJI cc{k, jc, c == 0 ? (r - jm + nx) % nx : (r + jm) % nx};
+#pragma unroll
+            for (int u = 0; u < KC; ++u) bv[h][u] = psi[dir_elem(m, c, cd[min(4 * u + kr, Nc - 1)], p, cc)];
+        }
+    };
+    bool have = false;                                        // bA holds the operands of the pair at hand
+    for (int c = 0; c < 2; ++c) {
+        const int Nc = m.Nc[c];
+        if (!have && wv < nx) {
+            load_pair(c, wv, bA);
+            have = true;
+        }
+        for (int r0 = wv; r0 < nx; r0 += 2 * nwv) {
+            // operands of the next pair: this class's, or class B's first
+            int rn = r0 + 2 * nwv, cn = c;
+            if (rn >= nx && c == 0) {
+                rn = wv;
+                cn = 1;
+            }
+            const bool next = rn < nx;
+            if (next) load_pair(cn, rn, bB);
+            A4 acc[2][NRB];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb) acc[h][rb] = A4{0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < KC; ++u)
+                if (4 * u < Nc) {
+#pragma unroll
+                    for (int rb = 0; rb < NRB; ++rb) {
+                        const T av = Dt[(c * NmP + rb * 16 + col) * DST + 4 * u + kr];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) acc[h][rb] = mfma_k4(av, bA[h][u], acc[h][rb]);
                     }
                 }
-                stop = conv || (it >= a.max_iter);
-                if (stop && !conv) st->notconv = 1;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = r0 + h * nwv;
+                if (jok && r < nx) {
+                    const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;   // natural x of (r, j)
+#pragma unroll
+                    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int lm = rb * 16 + out_row<T>(kr, e);
+                            if (lm < Nm) {
+                                T *tp = &tile[lm * LMS + col * pitch + i];
+                                *tp = c == 0 ? acc[h][rb][e] : *tp + acc[h][rb][e];
+                            }
+                        }
+                }
             }
-            if (stop) {
-                a.iters[(long)b * G + g] = it;
-                a.eps[(long)b * G + g] = e;
-                st->g = bad ? G : gseq + 1;
-                st->it = 0;
-                st->pending = 1;
+            have = next;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < KC; ++u) bA[h][u] = bB[h][u];
+        }
+        __syncthreads();
+    }
+    // ---- 2. combine in natural order: a thread takes one voxel of the slab at
+    // a time (material, density and the old phi_00 read once) and all its
+    // moments, with the group source of every moment requested up front
+    double dmax = 0.0, fmax_ = 0.0;
+    T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
+    const T *ext = (const T *)a.ext + (long)b * Nm * C;
+    const int tile_n = 16 * nx;
+    for (int idx = threadIdx.x; idx < tile_n; idx += blockDim.x) {
+        const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
+        if (jy >= ny) continue;
+        const long v = i + (long)nx * (jy + (long)ny * k);
+        const double rh = a.rho[v];
+        const int mt = a.mat[v];
+        const T po = phib[v];
+        T ev[16 * NRB];
+#pragma unroll
+        for (int lm = 0; lm < 16 * NRB; ++lm) ev[lm] = ext[(long)min(lm, Nm - 1) * C + v];
+#pragma unroll
+        for (int lm = 0; lm < 16 * NRB; ++lm) {
+            if (lm >= Nm) continue;
+            T *tp = &tile[lm * LMS + jl * pitch + i];
+            const T pn = *tp;
+            if (lm == 0) {
+                const double dn = fabs((double)pn - (double)po);
+                const double an = fabs((double)pn);
+                dmax = (dn > dmax || dn != dn) ? dn : dmax;
+                fmax_ = (an > fmax_ || an != an) ? an : fmax_;
             }
-            st->eps_num = 0ull;
-            st->eps_den = 0ull;
-            st->cnt_combine = 0;
+            phib[(long)lm * C + v] = pn;
+            const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
+            *tp = (T)((double)ev[lm] + sc * (double)pn);
         }
     }
+    __syncthreads();
+    // ---- 3. M map of each class from the tile
+    T *q = (T *)m.q + (long)b * N * C;
+    const int NS = (Nm + 3) / 4;                              // K-steps of 4 moments
+    for (int c = 0; c < 2; ++c) {
+        const int Nc = m.Nc[c];
+        const int *cd = cds + c * N;
+        for (int r = wv; r < nx; r += nwv) {
+            const long p = ((long)k * nx + r) * ny + jc;
+            const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;
+            const CellKJI cc{k, jc, i};
+            T bq[4 * NRB];
+#pragma unroll
+            for (int s = 0; s < 4 * NRB; ++s) bq[s] = tile[min(4 * s + kr, Nm - 1) * LMS + col * pitch + i];
+            for (int rb = 0; rb * 16 < Nc; ++rb) {
+                A4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < 4 * NRB; ++s)
+                    if (s < NS) acc = mfma_k4(Mt[(c * NcP + rb * 16 + col) * MST + 4 * s + kr], bq[s], acc);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int nl = rb * 16 + out_row<T>(kr, e);
+                    if (nl < Nc && jok) q[dir_elem(m, c, cd[nl], p, cc)] = acc[e];
+                }
+            }
+        }
+    }
+    // ---- 4. change of phi_00 and the end of the iteration
+    const double dm = block_max(dmax, red);
+    const double fm = block_max(fmax_, red);
+    if (threadIdx.x == 0) {
+        atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
+        atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
+        if (last_block(a.cnt_mom + (long)b * DCT_MAXNM * 32, &st->cnt_combine, blockIdx.x, gridDim.x))
+            close_iteration(a, st, b, gseq, g);
+    }
+}
+
+size_t dcm_lds_bytes(const CombArgs &a, const MapArgs &m, int is_f64)
+{
+    const size_t ts = is_f64 ? 8 : 4;
+    const size_t pitch = (size_t)((a.geo.nx | 1) + 1);
+    return (size_t)a.Nm * (16 * pitch + 4) * ts + (size_t)2 * m.NmP * (m.NcP + 1) * ts +
+           (size_t)2 * m.NcP * (m.NmP + 1) * ts + (size_t)2 * m.N * 4;
+}
+
+hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s)
+{
+    const int nslj = (a.geo.ny + 15) >> 4;
+    const dim3 grid((unsigned)(a.geo.nz * nslj), a.B);
+    const size_t shm = dcm_lds_bytes(a, m, is_f64);
+    const int nrb = (a.Nm + 15) / 16;
+#define DCT_DCM(T, R, K)                                                                                  \
+    do {                                                                                                  \
+        hipError_t e_ = hipFuncSetAttribute((const void *)k_dcm<T, R, K>,                                  \
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);        \
+        if (e_ != hipSuccess) return e_;                                                                  \
+        hipLaunchKernelGGL((k_dcm<T, R, K>), grid, dim3(512), shm, s, a, m);                               \
+    } while (0)
+#define DCT_DCM_K(T, R)                                                                                   \
+    do {                                                                                                  \
+        if (kc <= 4) DCT_DCM(T, R, 4); else if (kc <= 8) DCT_DCM(T, R, 8); else DCT_DCM(T, R, 12);          \
+    } while (0)
+    const int kc = ((m.Nc[0] > m.Nc[1] ? m.Nc[0] : m.Nc[1]) + 3) / 4;   // K-steps of one class (<= 12)
+    if (kc > 12) return hipErrorInvalidValue;
+    if (is_f64) {
+        if (nrb == 1) DCT_DCM_K(double, 1); else if (nrb == 2) DCT_DCM_K(double, 2); else DCT_DCM_K(double, 3);
+    } else {
+        if (nrb == 1) DCT_DCM_K(float, 1); else if (nrb == 2) DCT_DCM_K(float, 2); else DCT_DCM_K(float, 3);
+    }
+#undef DCT_DCM_K
+#undef DCT_DCM
+    return hipGetLastError();
+}
+
+// Anderson acceleration (depth m) of the within-group source iteration,
+// applied to the scalar-flux moment.  With G_k = F(phi_k) the moments of the
+// sweep of iterate phi_k (as k_combine leaves them) and f_k = G_k - phi_k,
+// the next iterate is
+//   phi_{k+1} = G_k - sum_i gamma_i (G_{k-i+1} - G_{k-i}),
+// gamma minimising || f_k - sum_i gamma_i (f_{k-i+1} - f_{k-i}) ||_2 over the
+// voxels (i = 1 .. min(m, k - 1)); the higher moments keep G_k.  A fixed point
+// of the accelerated iteration is one of the source iteration (f = 0), so the
+// solve converges to the same discrete solution; the stopping rule of
+// k_combine then measures max|f| / max|G|.
+//
+// k_aa_dots: f_k and G_k into the rings, the dot products (FP64, per
+// workgroup, summed in a fixed order by the last workgroup) and the small
+// least-squares problem (normal equations, Gaussian elimination).
+template <typename T>
+__global__ __launch_bounds__(256) void k_aa_dots(AAArgs a)
+{
+    __shared__ double red[8];
+    __shared__ double sdots[DCT_AA_NDOT];
+    const int b = blockIdx.y;
+    RhsState *st = a.state + b;
+    // only after an iteration that did not stop the group
+    if (st->finished || st->pending || st->it == 0) return;
+    const int it = st->it;
+    const int g = eff_group(st->g, a.G, a.reverse);
+    const long C = a.geo.C;
+    const int m = a.m, R = m + 1;
+    const int mk = min(m, it - 1);
+    const int w = (it - 1) % R;                        // ring slot of iteration it
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    double dots[DCT_AA_NDOT];
+#pragma unroll
+    for (int q = 0; q < DCT_AA_NDOT; ++q) dots[q] = 0.0;
+    if (v < C) {
+        const double Gk = (double)((const T *)a.phi_all)[(((long)b * a.G + g) * a.Nm) * C + v];
+        const double fk = Gk - a.phik[(long)b * C + v];
+        double *hG = a.hG + (long)b * R * C, *hF = a.hF + (long)b * R * C;
+        hG[(long)w * C + v] = Gk;
+        hF[(long)w * C + v] = fk;
+        double fr[DCT_AA_MAXM + 1];
+        fr[0] = fk;
+        for (int i = 1; i <= mk; ++i) fr[i] = hF[(long)((w - i + R) % R) * C + v];
+        double df[DCT_AA_MAXM];
+        for (int i = 0; i < mk; ++i) df[i] = fr[i] - fr[i + 1];   // f_{k-i} - f_{k-i-1}
+        int q = 0;
+        for (int i = 0; i < mk; ++i)
+            for (int j = i; j < mk; ++j) dots[q++] = df[i] * df[j];
+        for (int i = 0; i < mk; ++i) dots[q++] = df[i] * fk;
+    }
+    const int nd = mk * (mk + 1) / 2 + mk;
+    for (int q = 0; q < nd; ++q) {
+        const double t = block_sum(dots[q], red);
+        if (threadIdx.x == 0) sdots[q] = t;
+    }
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        double *pp = a.part + ((long)b * gridDim.x + blockIdx.x) * DCT_AA_NDOT;
+        for (int q = 0; q < nd; ++q)
+            atomicExch((unsigned long long *)(pp + q), (unsigned long long)__double_as_longlong(sdots[q]));
+        last = last_block(a.cnt_sub + (long)b * a.nsub * 32, a.cnt_top + (long)b * 32, blockIdx.x, gridDim.x);
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    double tot[DCT_AA_NDOT];
+    for (int q = 0; q < nd; ++q) tot[q] = 0.0;
+    for (unsigned blk = 0; blk < gridDim.x; ++blk) {
+        const unsigned long long *pp =
+            (const unsigned long long *)(a.part + ((long)b * gridDim.x + blk) * DCT_AA_NDOT);
+        for (int q = 0; q < nd; ++q)
+            tot[q] += __longlong_as_double((long long)__hip_atomic_load(pp + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    // normal equations A gamma = r (A = Gram matrix of the differences)
+    double A[DCT_AA_MAXM][DCT_AA_MAXM + 1];
+    int q = 0;
+    for (int i = 0; i < mk; ++i)
+        for (int j = i; j < mk; ++j) {
+            A[i][j] = tot[q];
+            A[j][i] = tot[q];
+            ++q;
+        }
+    for (int i = 0; i < mk; ++i) A[i][mk] = tot[q++];
+    int use = mk;
+    bool ok = mk > 0;
+    for (int c = 0; c < mk && ok; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < mk; ++r)
+            if (fabs(A[r][c]) > fabs(A[pr][c])) pr = r;
+        // a (nearly) dependent difference: mix with none (plain iteration)
+        if (!(fabs(A[pr][c]) > 1e-13 * fabs(A[0][0])) || !isfinite(A[pr][c])) ok = false;
+        if (!ok) break;
+        if (pr != c)
+            for (int k2 = c; k2 <= mk; ++k2) {
+                const double t = A[c][k2];
+                A[c][k2] = A[pr][k2];
+                A[pr][k2] = t;
+            }
+        for (int r = c + 1; r < mk; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int k2 = c; k2 <= mk; ++k2) A[r][k2] -= f * A[c][k2];
+        }
+    }
+    double gam[DCT_AA_MAXM] = {0.0, 0.0, 0.0, 0.0};
+    if (ok) {
+        for (int r = mk - 1; r >= 0; --r) {
+            double t = A[r][mk];
+            for (int k2 = r + 1; k2 < mk; ++k2) t -= A[r][k2] * gam[k2];
+            gam[r] = t / A[r][r];
+        }
+        for (int i = 0; i < mk; ++i) ok = ok && isfinite(gam[i]);
+    }
+    if (!ok) use = 0;
+    st->aa_mk = use;
+    for (int i = 0; i < DCT_AA_MAXM; ++i) st->aa_gam[i] = (ok && i < mk) ? gam[i] : 0.0;
+}
+
+// k_aa_mix: the mixed iterate phi_{k+1,00} (stored as the iterate of the next
+// sweep and over moment 0 of the group's moments, against which k_combine
+// measures the next change) and its moment-0 source ext_00 + rho s_0 phi in
+// both class layouts, through the slab tile of k_qinit.
+template <typename T>
+__global__ __launch_bounds__(256) void k_aa_mix(AAArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T *tile = (T *)smem_raw;
+    const int b = blockIdx.y;
+    const RhsState *st = a.state + b;
+    if (st->finished || st->pending || st->it == 0) return;
+    const int it = st->it;
+    const int g = eff_group(st->g, a.G, a.reverse);
+    const int nx = a.geo.nx, ny = a.geo.ny;
+    const long C = a.geo.C;
+    const int R = a.m + 1, mk = st->aa_mk, w = (it - 1) % R;
+    double gam[DCT_AA_MAXM];
+    for (int i = 0; i < DCT_AA_MAXM; ++i) gam[i] = st->aa_gam[i];
+    const int nslj = (ny + 15) >> 4;
+    const int k = blockIdx.x / nslj, j0 = (blockIdx.x % nslj) * 16;
+    const int pitch = (nx | 1) + 1, tile_n = 16 * nx;
+    const double *hG = a.hG + (long)b * R * C;
+    T *ph0 = (T *)a.phi_all + (((long)b * a.G + g) * a.Nm) * C;
+    const T *ext0 = (const T *)a.ext + (long)b * a.Nm * C;
+    const int L = a.L;
+    for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+        const int jn = idx / nx, in = idx - jn * nx, jj = j0 + jn;
+        if (jj >= ny) continue;
+        const long v = in + (long)nx * (jj + (long)ny * k);
+        double gp = hG[(long)w * C + v];
+        double x = gp;
+        for (int i = 0; i < mk; ++i) {
+            const double gq = hG[(long)((w - i - 1 + R) % R) * C + v];
+            x -= gam[i] * (gp - gq);                    // G_{k-i} - G_{k-i-1}
+            gp = gq;
+        }
+        a.phik[(long)b * C + v] = x;
+        ph0[v] = (T)x;
+        const int mm = a.mat[v];
+        const double sc = a.rho[v] * a.ss[(((long)mm * (L + 1)) * a.G + g) * a.G + g];
+        tile[jn * pitch + in] = (T)((double)ext0[v] + sc * x);
+    }
+    __syncthreads();
+    T *QA = (T *)a.Qc + (long)b * a.Nm * C;
+    T *QB = (T *)a.Qc + ((long)a.B + b) * a.Nm * C;
+    for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
+        const int r = idx >> 4, jl = idx & 15, j = j0 + jl;
+        if (j < ny) {
+            const int jm = j % nx;
+            const long p = ((long)k * nx + r) * ny + j;
+            QA[p] = tile[jl * pitch + rot_row(1, r, jm, nx)];
+            QB[p] = tile[jl * pitch + rot_row(0, r, jm, nx)];
+        }
+    }
+}
+
+hipError_t launch_aa(const AAArgs &a, int is_f64, hipStream_t s)
+{
+    if (a.m < 1 || a.m > DCT_AA_MAXM) return hipErrorInvalidValue;
+    const dim3 gd((unsigned)((a.geo.C + 255) / 256), a.B);
+    const int nslj = (a.geo.ny + 15) >> 4;
+    const dim3 gm((unsigned)(a.geo.nz * nslj), a.B);
+    const size_t shm = (size_t)16 * ((a.geo.nx | 1) + 1) * (is_f64 ? 8 : 4);
+    if (is_f64) {
+        hipLaunchKernelGGL(k_aa_dots<double>, gd, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_aa_mix<double>, gm, dim3(256), shm, s, a);
+    } else {
+        hipLaunchKernelGGL(k_aa_dots<float>, gd, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_aa_mix<float>, gm, dim3(256), shm, s, a);
+    }
+    return hipGetLastError();
 }
 
 // First within-group source of a group (phi = 0, so Q = ext): after a group
@@ -605,9 +1047,23 @@ __global__ __launch_bounds__(256) void k_qinit(CombArgs a)
     const T *ext = (const T *)a.ext + ((long)b * Nm + lm) * C;
     T *QA = (T *)a.Qc + ((long)b * Nm + lm) * C;
     T *QB = (T *)a.Qc + (((long)a.B + b) * Nm + lm) * C;
+    // warm start: the group starts from the moments phi already stored, so its
+    // first source is ext + sigma_s^{gg} phi, as k_combine forms the later ones
+    const int g = eff_group(st->g, a.G, a.reverse);
+    const T *ph = (const T *)a.phi_all + (((long)b * a.G + g) * Nm + lm) * C;
+    const int L = a.L, l = l_of(lm);
     for (int idx = threadIdx.x; idx < tile_n; idx += 256) {
         const int jn = idx / nx, in = idx - jn * nx, jj = j0 + jn;
-        if (jj < ny) tile[jn * pitch + in] = ext[in + (long)nx * (jj + (long)ny * k)];
+        if (jj < ny) {
+            const long v = in + (long)nx * (jj + (long)ny * k);
+            if (a.warm) {
+                const int mm = a.mat[v];
+                const double sc = a.rho[v] * a.ss[(((long)mm * (L + 1) + l) * a.G + g) * a.G + g];
+                tile[jn * pitch + in] = (T)((double)ext[v] + sc * (double)ph[v]);
+            } else {
+                tile[jn * pitch + in] = ext[v];
+            }
+        }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < tile_n; idx += 256) {

@@ -770,6 +770,230 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
     }
 }
 
+// Chained layered waves (single block, forward sweep, no kept fluxes): one
+// workgroup sweeps the K consecutive directions n0 .. n0 + K - 1 of one
+// octant of one right-hand side back to back.  Lane l of layer kp handles
+// the combined index pos = t - l - kp, slot d = pos / nx and reflected x
+// index pos mod nx: a lane that finishes direction d's row starts direction
+// d + 1's row on the next step, so the fill and drain of the wavefront
+// (ny + nz - 2 steps) are paid once per chain instead of once per direction.
+// Every upwind neighbour of a cell is in the same slot at the previous step,
+// exactly as in k_sweep_lw, so each cell's arithmetic (and result) is the same.
+//
+// q, psi and sigma_t use the chain layout: the K directions' x extents are
+// concatenated into a virtual grid of K nx columns, X = d nx + i (X = (K - 1
+// - d) nx + i when Omega_x < 0), rotated like the class layouts with period
+// K nx: element (k K nx + (X +- j) mod K nx) ny + j of the chain's block of K
+// C elements (+ in class A, - in class B).  The rotated row of a wave step
+// is then the same for every lane of every slot, so no per-lane slot offset
+// enters the addresses; sigma_t is stored K times over in the same layout.
+//
+// Per lane, the direction coefficients change when the lane starts a new
+// row (l == pos-phase of the step, one lane per step), together with the
+// reset of the x inflow.  The boundary outflows of each slot (particle
+// balance) are reduced when the last lane starts the next slot.
+template <typename T, int ZL, int PF>
+__global__ __launch_bounds__(1024 / ZL) void k_sweep_ch(SweepArgs a)
+{
+    constexpr unsigned TS = sizeof(T);
+    __shared__ T zbuf[2][17][64];                            // row w + 1: top layer of wave w; row 0: boundary
+    __shared__ T ctab[DCT_MAXCHAIN][4];                      // per slot: c_x, c_y, c_z and their sum
+    __shared__ double red[DCT_MAXCHAIN][16][3];              // per slot and z layer: x, y, z outflow sums
+    const int K = a.chainK;
+    const int cpb = a.N / K;                                 // chains per right-hand side
+    const int b = blockIdx.x / cpb;
+    const int n0 = (blockIdx.x - b * cpb) * K;
+    if (a.state[b].finished) return;
+    const int g = eff_group(a.state[b].g, a.G, a.reverse);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int Knx = K * nx;
+    const long C = a.C;
+    const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const double ox = a.dirs[3 * n0], oy = a.dirs[3 * n0 + 1], oz = a.dirs[3 * n0 + 2];
+    const bool sx = ox > 0, sy = oy > 0, sz = oz > 0;
+    const int cls = dir_class(ox, oy);
+    if ((int)threadIdx.x < K) {
+        const int n = n0 + threadIdx.x;
+        const T cx = (T)(2.0 * fabs(a.dirs[3 * n]) / a.dx), cy = (T)(2.0 * fabs(a.dirs[3 * n + 1]) / a.dy),
+                cz = (T)(2.0 * fabs(a.dirs[3 * n + 2]) / a.dz);
+        ctab[threadIdx.x][0] = cx;
+        ctab[threadIdx.x][1] = cy;
+        ctab[threadIdx.x][2] = cz;
+        ctab[threadIdx.x][3] = cx + cy + cz;
+    }
+    for (int i = threadIdx.x; i < DCT_MAXCHAIN * 16 * 3; i += blockDim.x) (&red[0][0][0])[i] = 0.0;
+    const bool lv = l < ny;                                  // one y block: ny <= 64
+    const int nl = min(ny, 64);
+    const int j = lv ? (sy ? l : ny - 1 - l) : 0;
+    const rsrc_t rq = mk_rsrc((const T *)a.q + ((long)b * a.N + n0) * C, (long)K * C * TS);
+    const rsrc_t rpsi = mk_rsrc((T *)a.psi + ((long)b * a.psi_bs + (long)g * a.psi_gs + n0) * C, (long)K * C * TS);
+    const rsrc_t rsg = mk_rsrc((const T *)a.sigch + ((long)cls * a.G + g) * K * C, (long)K * C * TS);
+    const T bc = a.inflow ? (T)a.inflow[g] : (T)0;
+    const int fixup = a.fixup;
+    // one step more than the wavefront needs: the last lane's slot change
+    // after the final row closes the last slot's outflow sums
+    const int NT = Knx + nl + nz - 1;
+    const int NTp = ((NT + PF - 1) / PF) * PF;
+    const int dr = sx ? 1 : -1;
+    const int dny = sx ? ny : -ny;
+    const int wrap_at_r = (sx ? Knx : -1) * ny, wrap_to_r = (sx ? 0 : Knx - 1) * ny;
+    // chain row of the lane's first cell (slot 0, first x of the sweep)
+    int rs = (sx ? 0 : Knx - 1) + (cls == 0 ? j : -j);
+    rs = ((rs % Knx) + Knx) % Knx;
+    bool vz[ZL];
+    int rowbase[ZL], t0[ZL], sre[ZL], Rz[ZL], Dz[ZL];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z) {
+        const int kp = w * ZL + z;
+        vz[z] = lv && kp < nz;
+        const int k = vz[z] ? (sz ? kp : nz - 1 - kp) : 0;
+        rowbase[z] = k * Knx * ny + j;
+        t0[z] = l + kp;
+        sre[z] = __builtin_amdgcn_readfirstlane((((rs - dr * (t0[z] + 1)) % Knx) + Knx) % Knx) * ny;
+        // phase of the compute step t = -PF (floor division by nx): the lane
+        // with l == Rz starts slot Dz's row at that step
+        const int sp = -PF - kp;
+        const int dfl = (sp >= 0) ? sp / nx : -((-sp + nx - 1) / nx);
+        Rz[z] = sp - dfl * nx;
+        Dz[z] = dfl;
+    }
+    if (w == 0) zbuf[0][0][l] = zbuf[1][0][l] = bc;
+    __syncthreads();
+    T qr[ZL][PF], sr[ZL][PF];
+    unsigned sbr[ZL][PF];
+    bool actr[ZL][PF];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z)
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            qr[z][u] = sr[z][u] = (T)0;
+            sbr[z][u] = DCT_OOB;
+            actr[z][u] = false;
+        }
+    T ycar[ZL], xo[ZL], yo[ZL], zo[ZL], lyv[ZL], lxv[ZL], cxl[ZL], cyl[ZL], czl[ZL], csl[ZL];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z) {
+        ycar[z] = xo[z] = lxv[z] = bc;
+        yo[z] = zo[z] = lyv[z] = (T)0;
+        cxl[z] = ctab[0][0];
+        cyl[z] = ctab[0][1];
+        czl[z] = ctab[0][2];
+        csl[z] = ctab[0][3];
+    }
+    T lzv = 0, lzp = 0;                                      // top layer: z outflows of the current / previous row
+    const int top_w = (nz - 1) / ZL, top_z = (nz - 1) - top_w * ZL;
+    for (int tb = -PF; tb < NTp; tb += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int t = tb + u;
+            T zin[ZL];
+            zin[0] = zbuf[(t + 1) & 1][w][l];
+#pragma unroll
+            for (int z = 1; z < ZL; ++z) zin[z] = zo[z - 1];
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                const int tp = t + PF - 1;
+                const int ps = (u + PF - 1) % PF;
+#pragma unroll
+                for (int z = 0; z < ZL; ++z) {
+                    const bool inp = vz[z] && (unsigned)(tp - t0[z]) < (unsigned)Knx;
+                    const unsigned pb = inp ? (unsigned)(rowbase[z] + sre[z]) * TS : DCT_OOB;
+                    sbr[z][ps] = pb;
+                    actr[z][ps] = inp;
+                    qr[z][ps] = bld<T>(rq, pb);
+                    sr[z][ps] = bld<T>(rsg, pb);
+                    sre[z] += dny;
+                    sre[z] = sre[z] == wrap_at_r ? wrap_to_r : sre[z];
+                }
+            }
+            // slot changes: the lane with l == Rz starts slot Dz's row now
+            // (its x inflow is the boundary value, its coefficients those of
+            // the new direction); its previous row's last x outflow is kept
+            // for the balance
+            bool start[ZL];
+            T n0v[ZL], y0[ZL], yin[ZL], xin[ZL];
+#pragma unroll
+            for (int z = 0; z < ZL; ++z) {
+                start[z] = l == Rz[z];
+                const int dc = min(max(Dz[z], 0), K - 1);
+                const T ncx = ctab[dc][0], ncy = ctab[dc][1], ncz = ctab[dc][2], ncs = ctab[dc][3];
+                cxl[z] = start[z] ? ncx : cxl[z];
+                cyl[z] = start[z] ? ncy : cyl[z];
+                czl[z] = start[z] ? ncz : czl[z];
+                csl[z] = start[z] ? ncs : csl[z];
+                lxv[z] = start[z] ? xo[z] : lxv[z];
+                xin[z] = start[z] ? bc : xo[z];
+                ycar[z] = dpp_shift_up_or<T>(yo[z], ycar[z]);
+                yin[z] = ycar[z];
+                y0[z] = rcp_nr(sr[z][u] + csl[z]);
+                n0v[z] = qr[z][u] + cxl[z] * xin[z] + cyl[z] * yin[z];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int z = 0; z < ZL; ++z) {
+                const int kp = w * ZL + z;
+                // the last lane starts slot Dz: every lane of this layer has
+                // finished slot Dz - 1, whose boundary outflows are summed now
+                if (Rz[z] == nl - 1 && Dz[z] >= 1 && Dz[z] <= K && kp < nz) {
+                    const bool top = w == top_w && z == top_z;
+                    if (top) lzp = start[z] ? lzv : lzp;
+                    double sx_ = vz[z] ? (double)lxv[z] : 0.0;
+                    double sz_ = (top && vz[z]) ? (double)lzp : 0.0;
+                    for (int o = 32; o > 0; o >>= 1) {
+                        sx_ += __shfl_down(sx_, o, 64);
+                        sz_ += __shfl_down(sz_, o, 64);
+                    }
+                    const double sy_ = (double)__shfl(lyv[z], nl - 1, 64);
+                    if (l == 0) {
+                        red[Dz[z] - 1][kp][0] = sx_;
+                        red[Dz[z] - 1][kp][1] = sy_;
+                        red[Dz[z] - 1][kp][2] = sz_;
+                    }
+                    lyv[z] = (T)0;
+                    if (top) {
+                        lzv = start[z] ? (T)0 : lzv;
+                        lzp = (T)0;
+                    }
+                } else if (w == top_w && z == top_z) {
+                    lzp = start[z] ? lzv : lzp;
+                    lzv = start[z] ? (T)0 : lzv;
+                }
+                const bool act = actr[z][u];
+                Cell4<T> c;
+                c.pc = fma(czl[z], zin[z], n0v[z]) * y0[z];
+                c.xo = c.pc + c.pc - xin[z];
+                c.yo = c.pc + c.pc - yin[z];
+                c.zo = c.pc + c.pc - zin[z];
+                c.fixed = 0;
+                if (fixup && act && fmin(c.xo, fmin(c.yo, c.zo)) < (T)0)
+                    c = dd_fixup<T>(qr[z][u], sr[z][u], cxl[z], cyl[z], czl[z], xin[z], yin[z], zin[z], c);
+                if (z == ZL - 1) zbuf[t & 1][w + 1][l] = c.zo;   // z handoff to the wave above
+                bst(rpsi, sbr[z][u], c.pc);
+                lyv[z] += act ? c.yo : (T)0;
+                if (w == top_w && z == top_z) lzv += act ? c.zo : (T)0;
+                xo[z] = act ? c.xo : xo[z];
+                yo[z] = c.yo;
+                zo[z] = c.zo;
+                // next step's phase
+                ++Rz[z];
+                if (Rz[z] == nx) {
+                    Rz[z] = 0;
+                    ++Dz[z];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // boundary outflow sums of every slot, summed over the z layers in order
+    if ((int)threadIdx.x < 3 * K) {
+        const int d = threadIdx.x / 3, cc = threadIdx.x - 3 * d;
+        double s = 0.0;
+        for (int kp = 0; kp < nz; ++kp) s += red[d][kp][cc];
+        a.leak_part[((long)b * a.N + n0 + d) * a.nblk * 3 + cc] = s;
+    }
+}
+
 hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
 {
     a.seq = seq;
@@ -786,6 +1010,24 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
         grid = dim3((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
     }
     const int mode = a.adjoint ? 2 : (a.mask ? 1 : 0);
+    if (a.chainK > 1) {
+        // chained directions: one block, forward sweep without kept fluxes,
+        // ny <= nx, K divides N (checked by the host)
+        if (multi || mode != 0 || a.ny > 64 || a.nz > 16 || a.ny > a.nx || a.N % a.chainK != 0 ||
+            a.chainK > DCT_MAXCHAIN)
+            return hipErrorInvalidValue;
+        const int zl = a.layers == 2 || a.layers == 4 ? a.layers : 1;
+        const int nwv = (a.nz + zl - 1) / zl;
+        const dim3 cgrid((unsigned)(a.B * (a.N / a.chainK))), cblock(64 * nwv);
+#define DCT_CH(T, ZL) hipLaunchKernelGGL((k_sweep_ch<T, ZL, 8>), cgrid, cblock, 0, s, a)
+        if (is_f64) {
+            if (zl == 4) DCT_CH(double, 4); else if (zl == 2) DCT_CH(double, 2); else DCT_CH(double, 1);
+        } else {
+            if (zl == 4) DCT_CH(float, 4); else if (zl == 2) DCT_CH(float, 2); else DCT_CH(float, 1);
+        }
+#undef DCT_CH
+        return hipGetLastError();
+    }
     if ((a.layers == 2 || a.layers == 4) && !multi && mode != 2 && a.ny <= 64 && a.nz <= 16) {
         const int nwv = (a.nz + a.layers - 1) / a.layers;
         const dim3 lgrid((unsigned)(a.B * a.N)), lblock(64 * nwv);

@@ -270,6 +270,31 @@ hipError_t launch_sigc(const Geo &g, const uint8_t *mat, const double *rho, cons
     return hipGetLastError();
 }
 
+// sigma_t in the chain layout of period K nx: chain row `row` of layer k holds
+// the cells of class-layout row row mod nx, so the table is K copies of each
+// layer's class rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sigch(Geo g, const T *sigc, int K, T *sigch)
+{
+    const long KC = (long)K * g.C;
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    const int cg = blockIdx.y;                           // class * G + group
+    if (p >= KC) return;
+    const long plane = (long)K * g.nx * g.ny;
+    const int k = (int)(p / plane);
+    const long rem = p - (long)k * plane;
+    const int row = (int)(rem / g.ny), j = (int)(rem - (long)row * g.ny);
+    sigch[(long)cg * KC + p] = sigc[(long)cg * g.C + ((long)k * g.nx + row % g.nx) * g.ny + j];
+}
+
+hipError_t launch_sigch(const Geo &g, const void *sigc, int G, int K, void *sigch, int is_f64, hipStream_t s)
+{
+    dim3 grid((unsigned)(((long)K * g.C + 255) / 256), 2 * G);
+    if (is_f64) hipLaunchKernelGGL(k_sigch<double>, grid, dim3(256), 0, s, g, (const double *)sigc, K, (double *)sigch);
+    else hipLaunchKernelGGL(k_sigch<float>, grid, dim3(256), 0, s, g, (const float *)sigc, K, (float *)sigch);
+    return hipGetLastError();
+}
+
 // Dose tally (Sec. II-A: collision kerma as absorbed dose; or, with per-group
 // factors hg, a fluence-to-dose conversion such as effective dose, Sec. III-A,
 // with the dose of flagged materials such as air neglected):

@@ -108,15 +108,27 @@ struct dct_ctx {
 
     // sweep schedules chosen by the autotuner, per problem shape
     struct Tuned {
-        int nx, ny, nz, N, B, prec, bk, sync;
+        int nx, ny, nz, N, B, prec, keep, bk, sync, chain;
     };
     std::vector<Tuned> tuned;
     int last_bk = 16, last_sync = 1;   // schedule of the last solve (reused by the adjoint)
+    int last_chain = 1;
+    bool last_fused = false;
+    bool last_warm = false;
+    // moments left in the "phi" buffer by the last completed solve (warm starts)
+    struct WarmState {
+        bool valid;
+        int B, G, Nm;
+        long C;
+        int prec;
+        void *phi;
+    } warm = {false, 0, 0, 0, 0, 0, nullptr};
+    size_t lds_max = 65536;            // LDS bytes one workgroup may allocate on the device
     bool pipe_clean = false;           // pipelined-block face buffers hold only the empty marker
     unsigned sweep_seq = 0;            // counts sweep launches (part of the pipelined blocks' launch tag)
     hipStream_t own_stream = nullptr;  // capture stream when the context's stream is the null stream
 
-    std::vector<hipEvent_t> evpool;
+    std::vector<hipEvent_t> evpool, evpool_m;   // event pairs around timed sweep / fused-map launches
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
     int *h_unf = nullptr;
@@ -197,6 +209,11 @@ int dct_create(dct_ctx **out, int device, void *stream)
         }
         e = hipSetDevice(device);
         if (e == hipSuccess && device < kMaxDevices) e = scratch_resolve(device);
+        if (e == hipSuccess) {
+            int lds = 0;
+            if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+                ctx->lds_max = (size_t)lds;
+        }
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[0]);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[1]);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_t0);
@@ -223,6 +240,7 @@ int dct_destroy(dct_ctx *ctx)
         for (auto &kv : ctx->bufs)
             if (kv.second.p) (void)hipFree(kv.second.p);
         for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ctx->evpool_m) (void)hipEventDestroy(e);
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
         for (hipEvent_t e : {ctx->ev_poll[0], ctx->ev_poll[1], ctx->ev_t0, ctx->ev_t1})
             if (e) (void)hipEventDestroy(e);
@@ -442,7 +460,7 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
         for (int a = 0; a < 3; ++a) inside = inside && p[a] >= ctx->org[a] && p[a] <= hi[a];
         if (inside) return fail(ctx, DCT_ESTATE, "solve: source " + std::to_string(b) + " lies inside the voxel grid");
     }
-    if (o.precision < DCT_FP64 || o.precision > DCT_FP32_BF16MAP) return fail(ctx, DCT_EINVAL, "solve: bad precision");
+    if (o.precision < DCT_FP64 || o.precision > DCT_FP32_BF16X3) return fail(ctx, DCT_EINVAL, "solve: bad precision");
     if (o.max_iter < 1) return fail(ctx, DCT_EINVAL, "solve: max_iter must be >= 1");
     if (!(o.tol >= 0) || !std::isfinite(o.tol)) return fail(ctx, DCT_EINVAL, "solve: tol must be finite and >= 0");
     if (o.fixed_iters)
@@ -495,13 +513,25 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
                                              std::to_string(std::max(pl.Nc[0], pl.Nc[1])) + ")");
     }
     if (o.sweep_bk < 0 || o.sweep_bk > 16) return fail(ctx, DCT_EINVAL, "solve: sweep_bk must be in [0, 16]");
-    if (o.sweep_sync < 0 || o.sweep_sync > 5) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 5]");
+    if (o.sweep_sync < 0 || o.sweep_sync > 8) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 8]");
+    if (o.accel_depth < 0 || o.accel_depth > DCT_AA_MAXM)
+        return fail(ctx, DCT_EINVAL, "solve: accel_depth must be in [0, " + std::to_string(DCT_AA_MAXM) + "]");
+    if (o.sweep_chain < -1 || o.sweep_chain > DCT_MAXCHAIN)
+        return fail(ctx, DCT_EINVAL, "solve: sweep_chain must be in [-1, " + std::to_string(DCT_MAXCHAIN) + "]");
     if (o.superpose < 0 || (o.superpose > 1 && ctx->B % o.superpose != 0))
         return fail(ctx, DCT_EINVAL, "solve: superpose must divide the number of sources (" + std::to_string(ctx->B) + ")");
     if (o.superpose > 1 && o.keep_adjoint)
         return fail(ctx, DCT_EINVAL, "solve: keep_adjoint is not supported with superposed sources");
     set_blocks(pl, o.sweep_bk > 0 ? o.sweep_bk : 16, ctx->ny, ctx->nz);
     return DCT_OK;
+}
+
+static float bf16_value(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
 }
 
 static uint16_t bf16_bits(double x)
@@ -542,7 +572,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     const int Nm = pl.Nm;
     const size_t ts = pl.tsz;
     const int is64 = o.precision == DCT_FP64;
-    const int mode = o.precision == DCT_FP64 ? 0 : (o.precision == DCT_FP32 ? 1 : 2);
+    const int mode = o.precision == DCT_FP64 ? 0 : (o.precision == DCT_FP32 ? 1 : (o.precision == DCT_FP32_BF16X3 ? 3 : 2));
 
     // ---------------- device buffers
     void *d_mat, *d_rho, *d_st, *d_ss, *d_kap, *d_pos, *d_axis, *d_gw, *d_dirs, *d_w, *d_cdir, *d_Mt, *d_Dt;
@@ -562,7 +592,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     HC(dbuf(ctx, "cdir", pl.cdir.size() * 4, &d_cdir));
     void *d_band;
     HC(dbuf(ctx, "band", (size_t)G * 4, &d_band));
-    const size_t tabsz = (size_t)2 * pl.NcP * pl.NmP * (mode == 2 ? 2 : ts);
+    // bf16 tables: both classes' high parts, then (split mode) both classes' remainders
+    const size_t tabsz = (size_t)2 * pl.NcP * pl.NmP * (mode >= 2 ? 2 * (mode == 3 ? 2 : 1) : ts);
     HC(dbuf(ctx, "Mt", tabsz, &d_Mt));
     HC(dbuf(ctx, "Dt", tabsz, &d_Dt));
     if (!ctx->iso.empty()) HC(dbuf(ctx, "iso", ctx->iso.size() * 8, &d_iso));
@@ -570,10 +601,29 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     if (o.fixed_iters) HC(dbuf(ctx, "fixed", (size_t)G * 4, &d_fixed));
     HC(dbuf(ctx, "phiu", (size_t)nsrc * G * C * 8, &d_phiu));
     HC(dbuf(ctx, "sigc", (size_t)2 * G * C * ts, &d_sigc));
+    const bool keep = o.keep_adjoint != 0;
+    // chain lengths K > 1 whose chains [c K, c K + K) each lie in one octant
+    // (chained sweeps: one block, ny <= nx, no kept fluxes)
+    std::vector<int> chain_ks;
+    if (ny <= 64 && nz <= 16 && !keep && ny <= nx) {
+        auto oct = [&](int n) {
+            return (ctx->dirs[3 * n] > 0 ? 0 : 1) + (ctx->dirs[3 * n + 1] > 0 ? 0 : 2) + (ctx->dirs[3 * n + 2] > 0 ? 0 : 4);
+        };
+        for (int K = 2; K <= std::min(N, DCT_MAXCHAIN); ++K) {
+            if (N % K) continue;
+            bool ok = true;
+            for (int n = 0; n < N && ok; ++n) ok = oct(n) == oct(n - n % K);
+            if (ok) chain_ks.push_back(K);
+        }
+    }
+    void *d_chn0, *d_chxo, *d_sigch = nullptr;
+    HC(dbuf(ctx, "chn0", (size_t)N * 4, &d_chn0));
+    HC(dbuf(ctx, "chxo", (size_t)N * 4, &d_chxo));
+    if (!chain_ks.empty())
+        HC(dbuf(ctx, "sigch", (size_t)2 * G * chain_ks.back() * C * ts, &d_sigch));
     HC(dbuf(ctx, "ext", (size_t)B * Nm * C * ts, &d_ext));
     HC(dbuf(ctx, "Qc", (size_t)2 * B * Nm * C * ts, &d_Qc));
     HC(dbuf(ctx, "q", (size_t)B * N * C * ts, &d_q));
-    const bool keep = o.keep_adjoint != 0;
     HC(dbuf(ctx, "psi", (size_t)B * (keep ? G : 1) * N * C * ts, &d_psi));
     void *d_mask = nullptr;
     if (keep) HC(dbuf(ctx, "mask", (size_t)B * G * N * C, &d_mask));
@@ -641,6 +691,11 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                     } else {
                         ((uint16_t *)Mt.data())[im] = bf16_bits(mv);
                         ((uint16_t *)Dt.data())[id] = bf16_bits(dv);
+                        if (mode == 3) {
+                            const size_t lo = (size_t)2 * pl.NcP * pl.NmP;
+                            ((uint16_t *)Mt.data())[lo + im] = bf16_bits((double)((float)mv - bf16_value(bf16_bits(mv))));
+                            ((uint16_t *)Dt.data())[lo + id] = bf16_bits((double)((float)dv - bf16_value(bf16_bits(dv))));
+                        }
                     }
                 }
             }
@@ -658,6 +713,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
             HC(hipMemcpyAsync(d_dirs, ctx->dirs.data(), ctx->dirs.size() * 8, hipMemcpyHostToDevice, s));
             HC(hipMemcpyAsync(d_w, ctx->w.data(), ctx->w.size() * 8, hipMemcpyHostToDevice, s));
             HC(hipMemcpyAsync(d_cdir, pl.cdir.data(), pl.cdir.size() * 4, hipMemcpyHostToDevice, s));
+
             // lowest group that scatters into each group in some material and order
             band.assign(G, 0);
             for (int g = 0; g < G; ++g) {
@@ -782,6 +838,52 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     tr.cnt_sub = (unsigned *)d_tsub;
     tr.nsub = tr_nsub;
     tr.part_bal = (double *)d_pbal;
+    // warm start: every group starts from the moments the last solve on this
+    // context left in the same buffer (same right-hand sides, groups, moments,
+    // grid and precision); otherwise from phi = 0
+    const bool warm = o.warm_start && ctx->warm.valid && ctx->warm.B == B && ctx->warm.G == G &&
+                      ctx->warm.Nm == Nm && ctx->warm.C == C && ctx->warm.prec == o.precision &&
+                      ctx->warm.phi == d_phi;
+    tr.warm = warm ? 1 : 0;
+    // Anderson acceleration of the within-group iteration (depth accel_depth)
+    const int aam = o.accel_depth;
+    AAArgs aa;
+    std::memset(&aa, 0, sizeof(aa));
+    tr.aa_phik = nullptr;
+    if (aam > 0) {
+        const int nblk_aa = (int)((C + 255) / 256), nsub_aa = (nblk_aa + 31) / 32;
+        void *t;
+        HC(dbuf(ctx, "aa_phik", (size_t)B * C * 8, &t));
+        aa.phik = (double *)t;
+        HC(dbuf(ctx, "aa_hG", (size_t)B * (aam + 1) * C * 8, &t));
+        aa.hG = (double *)t;
+        HC(dbuf(ctx, "aa_hF", (size_t)B * (aam + 1) * C * 8, &t));
+        aa.hF = (double *)t;
+        HC(dbuf(ctx, "aa_part", (size_t)B * nblk_aa * DCT_AA_NDOT * 8, &t));
+        aa.part = (double *)t;
+        HC(dbuf(ctx, "aa_sub", (size_t)B * nsub_aa * 128, &t));
+        aa.cnt_sub = (unsigned *)t;
+        HC(hipMemsetAsync(t, 0, (size_t)B * nsub_aa * 128, s));
+        HC(dbuf(ctx, "aa_top", (size_t)B * 128, &t));
+        aa.cnt_top = (unsigned *)t;
+        HC(hipMemsetAsync(t, 0, (size_t)B * 128, s));
+        aa.nsub = nsub_aa;
+        aa.geo = geo;
+        aa.G = G;
+        aa.Nm = Nm;
+        aa.L = L;
+        aa.B = B;
+        aa.m = aam;
+        aa.reverse = 0;
+        aa.state = (RhsState *)d_state;
+        aa.mat = (const uint8_t *)d_mat;
+        aa.rho = (const double *)d_rho;
+        aa.ss = (const double *)d_ss;
+        aa.phi_all = d_phi;
+        aa.ext = d_ext;
+        aa.Qc = d_Qc;
+        tr.aa_phik = aa.phik;
+    }
 
     MapArgs ma;
     ma.C = C;
@@ -804,6 +906,12 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     ma.reverse = 0;
     ma.part = d_part;
     ma.state = (const RhsState *)d_state;
+    ma.chainK = 1;
+    ma.nx = nx;
+    ma.ny = ny;
+    ma.chn0 = (const int *)d_chn0;
+    ma.chxo = (const int *)d_chxo;
+    ma.first_only = 0;
 
     SweepArgs sw;
     sw.nx = nx;
@@ -838,6 +946,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     sw.sync = o.sweep_sync == 2 ? 0 : 1;
     sw.pipe = 0;
     sw.layers = 0;
+    sw.chainK = 1;
+    sw.sigch = d_sigch;
     sw.yface_p = d_yfp;
     sw.zface_p = d_zfp;
     sw.hint = (unsigned long long *)d_hint;
@@ -870,6 +980,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     cb.max_iter = o.max_iter;
     cb.stall_window = o.precision == DCT_FP64 ? 0 : (o.stall_window == 0 ? 4 : (o.stall_window > 0 ? o.stall_window : 0));
     cb.reverse = 0;
+    cb.warm = warm ? 1 : 0;
 
     auto apply_blocks = [&](int bk) {
         set_blocks(pl, bk, ny, nz);
@@ -889,17 +1000,39 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     };
 
     // ---------------- sweep schedule: given, cached, or timed now
-    // schedule = (z layers per workgroup, coupling): coupling 1 = LDS progress
-    // counters between the waves of a workgroup, 2 = one barrier per step,
-    // 3 = as 2 with every block of a sweep in one launch (pipelined blocks),
-    // 4 / 5 = layered waves (every wave sweeps 4 / 2 z layers; one block,
-    // ny <= 64 and nz <= 16, forward sweeps)
+    // schedule = (z layers per workgroup, coupling, chain): coupling 1 = LDS
+    // progress counters between the waves of a workgroup, 2 = one barrier per
+    // step, 3 = as 2 with every block of a sweep in one launch (pipelined
+    // blocks), 4 / 5 = layered waves (every wave sweeps 4 / 2 z layers; one
+    // block, ny <= 64 and nz <= 16, forward sweeps), 6 / 7 / 8 = the K
+    // consecutive directions of one octant chained through one workgroup,
+    // with 1 / 2 / 4 z layers per wave (one block, ny <= nx, forward sweeps
+    // without kept fluxes; q and psi in the chain layout)
     double tune_ms = 0.0;
     const bool layered_ok = ny <= 64 && nz <= 16;
     auto set_coupling = [&](int cpl) {
         sw.sync = cpl == 1;
         sw.pipe = cpl == 3;
         sw.layers = (cpl == 4 && layered_ok) ? 4 : ((cpl == 5 && layered_ok) ? 2 : 0);
+        if (cpl >= 6) sw.layers = cpl == 6 ? 1 : (cpl == 7 ? 2 : 4);
+    };
+    // q and psi in the layout of chain length K (1 = class layouts), sigma_t
+    // copied into it
+    std::vector<int> chtab((size_t)2 * N);   // host staging of the chain tables (kept until the solve ends)
+    auto set_chain = [&](int K) -> hipError_t {
+        ma.chainK = K;
+        sw.chainK = K;
+        if (K <= 1) return hipSuccess;
+        for (int n = 0; n < N; ++n) {
+            const int d = n % K;
+            chtab[n] = n - d;
+            chtab[N + n] = (ctx->dirs[3 * n] > 0 ? d : K - 1 - d) * nx;
+        }
+        hipError_t e = hipMemcpyAsync(d_chn0, chtab.data(), (size_t)N * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_chxo, chtab.data() + N, (size_t)N * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // the staging vector is refilled by the next call
+        if (e != hipSuccess) return e;
+        return launch_sigch(geo, d_sigc, G, K, d_sigch, is64, s);
     };
     auto pipe_ready = [&]() -> int {
         // faces handed over inside a launch start out empty (all bits set)
@@ -910,16 +1043,24 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
         return DCT_OK;
     };
+    int chainK = 1;
     {
         int bk = o.sweep_bk > 0 ? o.sweep_bk : 16, cpl = o.sweep_sync > 0 ? o.sweep_sync : 1;
-        const bool free_bk = o.sweep_bk == 0, free_cpl = o.sweep_sync == 0;
-        if (o.autotune && (free_bk || free_cpl)) {
+        chainK = o.sweep_chain > 1 ? o.sweep_chain : ((cpl >= 6 && !chain_ks.empty()) ? chain_ks.back() : 1);
+        // chained candidates take part in tuning only when asked for (sweep_chain
+        // = -1): the tuner times sweeps alone, and the chain layout also costs
+        // the maps some address arithmetic
+        const bool free_bk = o.sweep_bk == 0, free_cpl = o.sweep_sync == 0, free_chain = o.sweep_chain < 0;
+        if (o.autotune && (free_bk || free_cpl || free_chain)) {
             const dct_ctx::Tuned *hit = nullptr;
             for (const auto &t : ctx->tuned)
-                if (t.nx == nx && t.ny == ny && t.nz == nz && t.N == N && t.B == B && t.prec == o.precision) hit = &t;
+                if (t.nx == nx && t.ny == ny && t.nz == nz && t.N == N && t.B == B && t.prec == o.precision &&
+                    t.keep == (int)keep)
+                    hit = &t;
             if (hit) {
                 if (free_bk) bk = hit->bk;
                 if (free_cpl) cpl = hit->sync;
+                if (free_chain) chainK = hit->chain;
             } else {
                 // first iteration set up to the sweep: the transition sets up
                 // group 0 (the first real set then finds nothing pending) and
@@ -933,7 +1074,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                     HC(hipEventCreate(&ev));
                     ctx->evpool.push_back(ev);
                 }
-                std::vector<std::pair<int, int>> cands;
+                struct Cand { int bk, cpl, K; };
+                std::vector<Cand> cands;
                 std::vector<int> bks;
                 if (free_bk) {
                     for (int c : {16, 8, 4, 2}) {
@@ -945,20 +1087,32 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 for (int cb : bks) {
                     const bool multi = (ny + 63) / 64 > 1 || (nz + cb - 1) / cb > 1;
-                    for (int cc : {1, 2, 3, 4, 5}) {
+                    for (int cc : {1, 2, 3, 4, 5, 6, 7, 8}) {
                         if (!free_cpl && cc != cpl) continue;
                         if (cc == 3 && (!multi || cb < 2)) continue;   // pipelining needs several blocks
                         if (cc >= 4 && (!layered_ok || cb != std::min(16, nz))) continue;   // one block of every layer
-                        cands.push_back({cb, cc});
+                        if (cc >= 6) {
+                            for (int K : chain_ks)
+                                if (free_chain || (K == chainK && o.sweep_chain > 1)) cands.push_back({cb, cc, K});
+                        } else if (free_chain || chainK == 1) {
+                            cands.push_back({cb, cc, 1});
+                        }
                     }
                 }
                 float best = 1e30f;
+                int cur_K = 1;
                 for (auto cand : cands) {
-                    apply_blocks(cand.first);
-                    set_coupling(cand.second);
-                    if (cand.second == 3) {
+                    apply_blocks(cand.bk);
+                    set_coupling(cand.cpl);
+                    if (cand.cpl == 3) {
                         int r = pipe_ready();
                         if (r != DCT_OK) return r;
+                    }
+                    if (cand.K != cur_K) {
+                        // q of the first sweep in this candidate's layout
+                        HC(set_chain(cand.K));
+                        HC(launch_mmap(ma, mode, s));
+                        cur_K = cand.K;
                     }
                     HC(sweep_all());   // warm-up
                     HC(hipEventRecord(ctx->evpool[0], s));
@@ -979,25 +1133,53 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                     tune_ms += ms * 4.0 / 3.0;
                     if (ms < best) {
                         best = ms;
-                        bk = cand.first;
-                        cpl = cand.second;
+                        bk = cand.bk;
+                        cpl = cand.cpl;
+                        chainK = cand.K;
                     }
                 }
                 if (best == 1e30f) return fail(ctx, DCT_EDEVICE, "solve: no sweep schedule completed during tuning");
-                ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, bk, cpl});
+                ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, (int)keep, bk, cpl, chainK});
             }
         }
         apply_blocks(bk);
         if (cpl == 3 && (pl.nblk == 1 || pl.BK < 2)) cpl = 1;   // one block (or 1-layer blocks): not pipelined
-        if (cpl >= 4 && (!layered_ok || pl.nblk != 1)) cpl = 2;   // layered waves need one block
+        if (cpl >= 4 && cpl <= 5 && (!layered_ok || pl.nblk != 1)) cpl = 2;   // layered waves need one block
+        if (cpl >= 6 && (pl.nblk != 1 || std::find(chain_ks.begin(), chain_ks.end(), chainK) == chain_ks.end())) {
+            cpl = 2;   // chains need one block and chains inside octants
+            chainK = 1;
+        }
+        if (cpl < 6) chainK = 1;
+        if (cpl >= 6 && chainK == 1) cpl = 2;
         set_coupling(cpl);
+        HC(set_chain(chainK));
         if (cpl == 3) {
             int r = pipe_ready();
             if (r != DCT_OK) return r;
         }
         ctx->last_bk = pl.BK;
         ctx->last_sync = cpl;
+        ctx->last_chain = chainK;
     }
+
+    // D map, combine and M map as one kernel (k_dcm): FP64 / FP32, the slab
+    // tile and tables within the workgroup's LDS, at most 32 DCT_MAXNM slabs
+    // (completion sub-counters); by default when there are enough slabs to
+    // fill the GPU (one or two workgroups per CU at a time)
+    bool fused = false;
+    {
+        const long nslab = (long)nz * ((ny + 15) / 16);
+        const size_t lds = dcm_lds_bytes(cb, ma, is64) + 1024;
+        const bool fuse_ok = mode <= 1 && lds <= ctx->lds_max && nslab <= 32L * DCT_MAXNM &&
+                             std::max(pl.Nc[0], pl.Nc[1]) <= 48;   // one round of psi loads per class
+        // by default: enough slabs to fill the GPU and two workgroups per CU
+        // (one workgroup of 8 waves per CU leaves too few loads in flight)
+        fused = fuse_ok && aam == 0 &&
+                (o.fuse_maps > 0 || (o.fuse_maps == 0 && nslab * B >= 1024 && 2 * lds <= ctx->lds_max));
+        ma.first_only = fused ? 1 : 0;
+    }
+    ctx->last_fused = fused;
+    ctx->last_warm = warm;
 
     // upper bound of iteration sets: every group at its cap plus one transition each
     long cap_sets = 2;
@@ -1005,8 +1187,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     const int chunk = o.chunk > 0 ? o.chunk : 4;
     const bool profile = o.profile && !o.use_graph;
     const int pevery = o.profile > 1 ? o.profile : 1;   // time every pevery-th sweep launch
-    int nprof = 0;
-    long nsweeps = 0;
+    int nprof = 0, nprof_m = 0;
+    long nsweeps = 0, nmaps = 0;
     auto enqueue_set = [&](hipStream_t es) -> hipError_t {
         hipError_t e = launch_transition(tr, is64, es);
         if (e != hipSuccess) return e;
@@ -1029,8 +1211,26 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 ++nprof;
             }
         }
+        if (fused) {
+            const bool timed = profile && nmaps++ % pevery == 0;
+            if (timed) {
+                while ((int)ctx->evpool_m.size() < 2 * (nprof_m + 1)) {
+                    hipEvent_t ev;
+                    if ((e = hipEventCreate(&ev)) != hipSuccess) return e;
+                    ctx->evpool_m.push_back(ev);
+                }
+                if ((e = hipEventRecord(ctx->evpool_m[2 * nprof_m], es)) != hipSuccess) return e;
+            }
+            if ((e = launch_dcm(cb, ma, is64, es)) != hipSuccess) return e;
+            if (timed) {
+                if ((e = hipEventRecord(ctx->evpool_m[2 * nprof_m + 1], es)) != hipSuccess) return e;
+                ++nprof_m;
+            }
+            return hipSuccess;
+        }
         if ((e = launch_dmap(ma, mode, es)) != hipSuccess) return e;
-        return launch_combine(cb, is64, es);
+        if ((e = launch_combine(cb, is64, es)) != hipSuccess) return e;
+        return aam > 0 ? launch_aa(aa, is64, es) : hipSuccess;
     };
 
     // ---------------- iteration sets: enqueued in chunks (or one captured
@@ -1141,13 +1341,25 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
         stats->sweep_ms = swms;
         stats->sweep_launches = nprof;
+        double mms = 0;
+        for (int i = 0; i < nprof_m; ++i) {
+            float t = 0;
+            HC(hipEventElapsedTime(&t, ctx->evpool_m[2 * i], ctx->evpool_m[2 * i + 1]));
+            mms += t;
+        }
+        stats->fused_ms = mms;
+        stats->fused_launches = nprof_m;
         stats->sweep_launches_all = (long long)sets * (sw.pipe ? 1 : pl.ndiag);
         stats->iteration_sets = (int)sets;
         stats->sweep_bk = pl.BK;
         stats->sweep_sync = ctx->last_sync;
+        stats->sweep_chain = ctx->last_chain;
+        stats->fused_maps = ctx->last_fused ? 1 : 0;
+        stats->warm_start = ctx->last_warm ? 1 : 0;
         stats->tune_ms = tune_ms;
     }
     ctx->solved = true;
+    ctx->warm = {!any_nan, B, G, Nm, C, o.precision, d_phi};
     ctx->solved_prec = o.precision;
     ctx->solved_Nm = Nm;
     ctx->solved_S = S;
@@ -1377,12 +1589,13 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     const int Nm = pl.Nm;
     const size_t ts = pl.tsz;
     const int is64 = o.precision == DCT_FP64;
-    const int mode = o.precision == DCT_FP64 ? 0 : (o.precision == DCT_FP32 ? 1 : 2);
+    const int mode = o.precision == DCT_FP64 ? 0 : (o.precision == DCT_FP32 ? 1 : (o.precision == DCT_FP32_BF16X3 ? 3 : 2));
     auto B_ = [&](const char *n) { return ctx->bufs[n].p; };
 
     void *d_roi, *d_amt, *d_adt, *d_lamc, *d_lam, *d_pbar, *d_pbu, *d_drho, *d_dray, *d_dgw, *d_ait, *d_aeps, *d_fix;
     HC(dbuf(ctx, "a_roi", (size_t)C * 8, &d_roi));
-    const size_t tabsz = (size_t)2 * pl.NcP * pl.NmP * (mode == 2 ? 2 : ts);
+    // bf16 tables: both classes' high parts, then (split mode) both classes' remainders
+    const size_t tabsz = (size_t)2 * pl.NcP * pl.NmP * (mode >= 2 ? 2 * (mode == 3 ? 2 : 1) : ts);
     HC(dbuf(ctx, "a_Mt", tabsz, &d_amt));
     HC(dbuf(ctx, "a_Dt", tabsz, &d_adt));
     HC(dbuf(ctx, "a_lamc", (size_t)B * N * C * ts, &d_lamc));
@@ -1421,6 +1634,11 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
                     } else {
                         ((uint16_t *)Mt.data())[im] = bf16_bits(dT);
                         ((uint16_t *)Dt.data())[id] = bf16_bits(mT);
+                        if (mode == 3) {
+                            const size_t lo = (size_t)2 * pl.NcP * pl.NmP;
+                            ((uint16_t *)Mt.data())[lo + im] = bf16_bits((double)((float)dT - bf16_value(bf16_bits(dT))));
+                            ((uint16_t *)Dt.data())[lo + id] = bf16_bits((double)((float)mT - bf16_value(bf16_bits(mT))));
+                        }
                     }
                 }
             }
@@ -1511,6 +1729,12 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     ma.reverse = 1;
     ma.part = B_("part");
     ma.state = (const RhsState *)B_("state");
+    ma.chainK = 1;
+    ma.nx = nx;
+    ma.ny = ny;
+    ma.chn0 = nullptr;
+    ma.chxo = nullptr;
+    ma.first_only = 0;
 
     SweepArgs sw;
     sw.nx = nx;
@@ -1545,6 +1769,8 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     sw.sync = ctx->last_sync == 1;
     sw.pipe = ctx->last_sync == 3;
     sw.layers = 0;                     // transposed sweeps run on k_sweep (barrier coupling for layered schedules)
+    sw.chainK = 1;
+    sw.sigch = nullptr;
     sw.yface_p = B_("yfp");
     sw.zface_p = B_("zfp");
     sw.hint = (unsigned long long *)B_("hint");
@@ -1575,6 +1801,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     cb.max_iter = o.max_iter;
     cb.stall_window = o.precision == DCT_FP64 ? 0 : (o.stall_window == 0 ? 4 : (o.stall_window > 0 ? o.stall_window : 0));
     cb.reverse = 1;
+    cb.warm = 0;
 
     long cap_sets = 2;
     for (int g = 0; g < G; ++g) cap_sets += (o.fixed_iters ? o.fixed_iters[g] : o.max_iter) + 1;

@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdctsn.so")
 
 DCT_OK, DCT_EINVAL, DCT_ESTATE, DCT_EDEVICE, DCT_ENOMEM, DCT_ENOTCONV, DCT_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
-DCT_FP64, DCT_FP32, DCT_FP32_BF16MAP = 0, 1, 2
-PRECISIONS = {"fp64": DCT_FP64, "fp32": DCT_FP32, "fp32_bf16map": DCT_FP32_BF16MAP}
+DCT_FP64, DCT_FP32, DCT_FP32_BF16MAP, DCT_FP32_BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": DCT_FP64, "fp32": DCT_FP32, "fp32_bf16map": DCT_FP32_BF16MAP, "fp32_bf16x3": DCT_FP32_BF16X3}
 STATUS_NAMES = {0: "DCT_OK", -1: "DCT_EINVAL", -2: "DCT_ESTATE", -3: "DCT_EDEVICE", -4: "DCT_ENOMEM",
                 -5: "DCT_ENOTCONV", -6: "DCT_ENUMERIC"}
 
@@ -40,7 +40,8 @@ class dct_opts(ct.Structure):
                 ("test_inflow", ct.POINTER(ct.c_double)), ("chunk", ct.c_int), ("use_graph", ct.c_int),
                 ("profile", ct.c_int), ("keep_adjoint", ct.c_int), ("autotune", ct.c_int),
                 ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int), ("superpose", ct.c_int),
-                ("stall_window", ct.c_int)]
+                ("stall_window", ct.c_int), ("sweep_chain", ct.c_int), ("fuse_maps", ct.c_int),
+                ("warm_start", ct.c_int), ("accel_depth", ct.c_int)]
 
 
 class dct_stats(ct.Structure):
@@ -48,7 +49,9 @@ class dct_stats(ct.Structure):
                 ("balance", ct.POINTER(ct.c_double)), ("sweep_updates", ct.c_longlong),
                 ("sweep_launches", ct.c_int), ("sweep_ms", ct.c_double), ("solve_ms", ct.c_double),
                 ("iteration_sets", ct.c_int), ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int),
-                ("tune_ms", ct.c_double), ("sweep_launches_all", ct.c_longlong)]
+                ("tune_ms", ct.c_double), ("sweep_launches_all", ct.c_longlong), ("sweep_chain", ct.c_int),
+                ("fused_maps", ct.c_int), ("warm_start", ct.c_int), ("fused_ms", ct.c_double),
+                ("fused_launches", ct.c_int)]
 
 
 _lib = None
@@ -168,11 +171,17 @@ class SolveStats:
     sweep_sync: int
     tune_ms: float
     sweep_launches_all: int = 0
+    sweep_chain: int = 1
+    fused_maps: int = 0
+    warm_start: int = 0
+    fused_ms: float = 0.0
+    fused_launches: int = 0
 
 
 def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=None, fixup=True,
           test_inflow=None, chunk=0, use_graph=False, profile=False, keep_adjoint=False, autotune=False,
-          sweep_bk=0, sweep_sync=0, superpose=1, stall_window=0, allow_notconv=False) -> SolveStats:
+          sweep_bk=0, sweep_sync=0, superpose=1, stall_window=0, sweep_chain=0, fuse_maps=0,
+          warm_start=False, accel_depth=0, allow_notconv=False) -> SolveStats:
     """B = number of sources; with superpose = S > 1 the per-right-hand-side
     outputs have B // S rows."""
     o = dct_opts()
@@ -193,6 +202,10 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     o.sweep_sync = int(sweep_sync)
     o.superpose = int(superpose)
     o.stall_window = int(stall_window)
+    o.sweep_chain = int(sweep_chain)
+    o.fuse_maps = int(fuse_maps)
+    o.warm_start = int(warm_start)
+    o.accel_depth = int(accel_depth)
     S = max(1, int(superpose))
     if B % S:
         raise ValueError(f"superpose={S} must divide the number of sources {B}")
@@ -207,7 +220,8 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     ok = (DCT_OK, DCT_ENOTCONV) if allow_notconv else (DCT_OK,)
     rc = _chk(h, lib().dct_solve(h, ct.byref(o), ct.byref(st)), ok)
     return SolveStats(rc, iters, eps, bal, st.sweep_updates, st.sweep_launches, st.sweep_ms, st.solve_ms,
-                      st.iteration_sets, st.sweep_bk, st.sweep_sync, st.tune_ms, st.sweep_launches_all)
+                      st.iteration_sets, st.sweep_bk, st.sweep_sync, st.tune_ms, st.sweep_launches_all,
+                      st.sweep_chain, st.fused_maps, st.warm_start, st.fused_ms, st.fused_launches)
 
 
 def dose(h, B, G, C, *, summed=False, want_phi=False):

@@ -235,3 +235,75 @@ def test_adjoint_other_schedules(bk, sync):
         s.close()
     _check(f"schedule {bk}:{sync} d_density", a.d_density, ref.d_density)
     _check(f"schedule {bk}:{sync} d_group_w", a.d_group_w, ref.d_group_w)
+
+
+def test_adjoint_c5_central_differences():
+    """64 x 64 x 16 abdomen (19 groups, S6, P3): central differences with the
+    absolute step h = 1e-3 (g/cm^3 for densities, photons per source photon for
+    group weights) of FP64 GPU solves at tol 1e-12 against the GPU adjoint, on
+    32 seeded voxels (8 in the 10 x 10 x 4 ROI, 8 on the beam path, 8 bone or
+    lung, 8 anywhere in the body) and every group weight.  The h = 1e-3
+    difference carries its O(h^2) truncation; with h / 2 as well, the
+    Richardson combination (4 d(h/2) - d(h)) / 3 removes it and matches the
+    adjoint to 1e-6 relative, up to the noise the tol 1e-12 stopping point
+    leaves in a difference quotient (about 1e-12 R / h, which dominates for the
+    voxels of small sensitivity).  Each perturbed solve starts from the
+    unperturbed moments (warm start) and converges to its own fixed point."""
+    prob = I.make_problem("c5")
+    ph = prob.phantom
+    roi3 = np.zeros((ph.nz, ph.ny, ph.nx))
+    roi3[6:10, 27:37, 27:37] = 1.0 / 400.0
+    roi = roi3.reshape(-1)
+    h = 1e-3
+    s = dctsn.Solver(prob)
+    try:
+        s.solve(precision="fp64", tol=1e-12, keep_adjoint=True)
+        pu = s.dose(want_phi=True)[1][0].sum(0)            # uncollided fluence summed over groups
+        a = s.adjoint(roi, tol=1e-12)
+        rng = np.random.default_rng(1811)
+        names = ph.material_names
+        body = np.nonzero(ph.material != names.index("air"))[0]
+        in_roi = np.nonzero(roi > 0)[0]
+        beam = body[pu[body] > np.quantile(pu[body], 0.75)]
+        hard = np.nonzero(np.isin(ph.material, [names.index("bone"), names.index("lung")]))[0]
+        picks = np.concatenate([rng.choice(in_roi, 8, replace=False), rng.choice(beam, 8, replace=False),
+                                rng.choice(hard, 8, replace=False), rng.choice(body, 8, replace=False)])
+
+        def R():
+            s.solve(precision="fp64", tol=1e-12, warm_start=True)
+            return float(np.dot(roi, s.dose(summed=True)))
+
+        def central(setter, base, idx, step):
+            x1, x2 = base.copy(), base.copy()
+            x1[idx] += step
+            x2[idx] -= step
+            setter(x1)
+            f1 = R()
+            setter(x2)
+            f2 = R()
+            setter(base)
+            return (f1 - f2) / (2 * step)
+
+        worst_h, worst_r = 0.0, 0.0
+        cases = [(s.set_density, ph.density, int(v), a.d_density[v], np.abs(a.d_density[picks]).max(), "voxel")
+                 for v in picks]
+        gw = np.asarray(prob.group_w, dtype=np.float64)
+        cases += [(s.set_group_weights, gw, g, a.d_group_w[g], np.abs(a.d_group_w).max(), "group")
+                  for g in range(prob.G)]
+        # the solves stop at tol 1e-12, so a difference quotient carries noise of
+        # about 1e-12 |R| / h: the bars add 10 times that to the relative ones
+        noise = 1e-11 * abs(a.R) / h
+        for setter, base, idx, adj, scale, kind in cases:
+            d1 = central(setter, base, idx, h)
+            d2 = central(setter, base, idx, h / 2)
+            rich = (4.0 * d2 - d1) / 3.0
+            e_h = abs(d1 - adj) / (2e-5 * abs(adj) + noise)
+            e_r = abs(rich - adj) / (1e-6 * abs(adj) + 2 * noise)
+            worst_h, worst_r = max(worst_h, e_h), max(worst_r, e_r)
+            assert e_h <= 1.0, (kind, idx, d1, adj, noise)
+            assert e_r <= 1.0, (kind, idx, rich, adj, noise)
+        _say(f"[adjoint c5 fd] 32 voxels + {prob.G} group weights, R = {a.R:.4e}: worst |fd - adjoint| as a "
+             f"fraction of its bar, central h = 1e-3 {worst_h:.2f} (bar 2e-5 relative + 1e-11 R / h), Richardson "
+             f"(h, h/2) {worst_r:.2f} (bar 1e-6 relative + 2e-11 R / h)")
+    finally:
+        s.close()

@@ -37,6 +37,27 @@ def l2rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
+def test_c3_abdomen_converged_fp32_vs_fp64():
+    """The whole 128x128x32 abdomen solve to tol 1e-6 per group: the FP32 dose
+    (FP32 sweeps and maps, FP64 optical depth, reductions and tally) within
+    1e-4 (L2, relative) of the converged FP64 solve on the GPU."""
+    prob = I.make_problem("c3")
+    s = dctsn.Solver(prob)
+    try:
+        _say("[c3] converged fp64")
+        st64 = s.solve(precision="fp64", tol=1e-6, autotune=True)
+        d64 = s.dose()
+        _say("[c3] converged fp32")
+        st32 = s.solve(precision="fp32", tol=1e-6, autotune=True)
+        d32 = s.dose()
+    finally:
+        s.close()
+    err = l2rel(d32, d64)
+    _say(f"[c3] converged: fp64 {int(st64.iters.sum())} iterations, fp32 {int(st32.iters.sum())}; "
+         f"dose L2 rel err {err:.3e}")
+    assert err <= 1e-4
+
+
 def test_c3_abdomen_fp32_vs_oracle_two_iterations():
     """128x128x32 abdomen (two y-blocks per sweep), 19 groups, S8, P3, FP32
     with FP64 reductions, two source iterations per group on both sides."""

@@ -247,6 +247,22 @@ def test_c2_bf16_maps_error(c2_ref):
     assert err <= 3e-4
 
 
+def test_c2_split_bf16_maps_error(c2_ref):
+    """Split bf16 map inputs (high part + remainder, three bf16 products per
+    term): the dose meets the 1e-4 bar that single bf16 inputs miss, and the
+    split solve converges at tol 1e-6 without fixed iteration counts."""
+    prob = I.make_problem("c2")
+    _say("[c2] GPU fp32 + split bf16 maps solve")
+    st, dose, pu, mom = gpu_solve(prob, precision="fp32_bf16x3", fixed_iters=c2_ref.iters[0])
+    err = l2rel(dose, c2_ref.dose)
+    _say(f"[c2] split-bf16-map dose L2 rel err = {err:.3e}")
+    assert err <= 1e-4
+    st2, dose2, _, _ = gpu_solve(prob, precision="fp32_bf16x3", tol=1e-6)
+    err2 = l2rel(dose2, c2_ref.dose)
+    _say(f"[c2] split-bf16-map converged: {int(st2.iters.sum())} iterations, dose L2 rel err = {err2:.3e}")
+    assert err2 <= 1e-4
+
+
 # ------------------------------------------------------------------ schedules, graphs, autotuning
 def _dose_with(prob, **kw):
     s = dctsn.Solver(prob)
