@@ -613,16 +613,26 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ double red[16];
     __shared__ double ssg[DCT_MAXMAT * (DCT_MAXL + 1)];
-    const int b = blockIdx.y;
+    const int nx = a.geo.nx, ny = a.geo.ny;
+    const int nslj = (ny + 15) >> 4;
+    // workgroup -> (right-hand side, slab).  Two slabs 16 rows apart share the
+    // 128-byte lines of psi (64 bytes each per row and direction in FP32), so
+    // they are paired on one XCD: workgroups h and h + 8 (same XCD, dispatched
+    // together) take slabs j and j + 1 of the same layer
+    const unsigned nsl = gridDim.x, lin = blockIdx.x + nsl * blockIdx.y;
+    unsigned W = lin;
+    if ((nslj & 1) == 0 && ((nsl * gridDim.y) & 15) == 0) {
+        const unsigned xcd = lin & 7, slot = lin >> 3;
+        W = 2 * ((slot >> 1) * 8 + xcd) + (slot & 1);
+    }
+    const int b = (int)(W / nsl), slab = (int)(W - (unsigned)b * nsl);
     RhsState *st = a.state + b;
     if (st->finished) return;
     const int gseq = st->g;
     const int g = eff_group(gseq, a.G, a.reverse);
-    const int nx = a.geo.nx, ny = a.geo.ny;
     const long C = a.geo.C;
     const int G = a.G, Nm = a.Nm, L = a.L, N = m.N;
-    const int nslj = (ny + 15) >> 4;
-    const int k = blockIdx.x / nslj, j0 = (blockIdx.x % nslj) * 16;
+    const int k = slab / nslj, j0 = (slab % nslj) * 16;
     const int pitch = (nx | 1) + 1;
     // moment stride of the tile: 16 rows plus 4 words, so that the 4 lane
     // groups of an MFMA output (moments 4 apart) fall in different banks
@@ -792,7 +802,7 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     if (threadIdx.x == 0) {
         atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
         atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
-        if (last_block(a.cnt_mom + (long)b * DCT_MAXNM * 32, &st->cnt_combine, blockIdx.x, gridDim.x))
+        if (last_block(a.cnt_mom + (long)b * DCT_MAXNM * 32, &st->cnt_combine, (unsigned)slab, nsl))
             close_iteration(a, st, b, gseq, g);
     }
 }
