@@ -108,7 +108,7 @@ def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=No
         parts = [int(x) for x in schedule.split(":")]
         kw.update(autotune=False, sweep_bk=parts[0], sweep_sync=parts[1])
         if len(parts) > 2:
-            kw.update(sweep_chain=parts[2])
+            kw["sweep_rhs_chain" if parts[1] >= 9 else "sweep_chain"] = parts[2]
     for _ in range(warmup):
         solver.solve(**kw)
         dctsn.dose_dev(solver.h, dose_dev, summed=True)
@@ -139,7 +139,8 @@ def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=No
         "iteration_sets": int(stats[-1].iteration_sets),
         "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
                            "wave_coupling": COUPLINGS.get(int(stats[-1].sweep_sync), str(stats[-1].sweep_sync)),
-                           "chained_directions": int(stats[-1].sweep_chain)},
+                           "chained_directions": int(stats[-1].sweep_chain),
+                           "chained_sources": int(stats[-1].sweep_rhs_chain)},
         "fused_maps": bool(stats[-1].fused_maps),
         "dose": dose,
     }
@@ -208,7 +209,8 @@ def main():
                     help="maps and combine as one kernel per iteration (auto: by shape)")
     ap.add_argument("--schedule", default=None, metavar="BK:SYNC",
                     help="pin the sweep schedule of the timed solves (z layers per workgroup : wave "
-                         "coupling [: chained directions]) instead of autotuning; for counter runs, where "
+                         "coupling [: chained directions, or chained sources for couplings 9 / 10]) instead "
+                         "of autotuning; for counter runs, where "
                          "the profiler's serialisation can change the tuner's choice")
     args = ap.parse_args()
     _ARGS_FUSE[0] = args.fuse
@@ -452,7 +454,8 @@ PROFILE_EVERY = 4
 # (about 10-20 s of host time)
 CPU_SOURCES = {"c4": 6}
 COUPLINGS = {1: "lds_counters", 2: "barrier", 3: "pipelined_blocks", 4: "layered_waves_4", 5: "layered_waves_2",
-             6: "chained_directions_1", 7: "chained_directions_2", 8: "chained_directions_4"}
+             6: "chained_directions_1", 7: "chained_directions_2", 8: "chained_directions_4",
+             9: "chained_sources_2", 10: "chained_sources_1"}
 FUSE = {"auto": 0, "on": 1, "off": -1}
 _ARGS_FUSE = ["auto"]
 SWEEP_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_sweep.hip")

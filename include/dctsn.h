@@ -90,8 +90,9 @@ typedef struct dct_opts {
                                  one barrier per step (needs one block: ny <= 64, nz <= 16,
                                  sweep_bk >= nz; otherwise runs as 2; the transposed sweeps
                                  of dct_adjoint then use 2); 6 / 7 / 8 = chained directions
-                                 (sweep_chain) with 1 / 2 / 4 z layers per wave; 0 = tuned
-                                 or 1 */
+                                 (sweep_chain) with 1 / 2 / 4 z layers per wave; 9 / 10 =
+                                 chained right-hand sides (sweep_rhs_chain) with 2 / 1 z
+                                 layers per wave; 0 = tuned or 1 */
     int superpose;            /* sources per right-hand side S (0 or 1: one each).  With
                                  S > 1 the B sources of dct_set_source form B / S right-hand
                                  sides of S consecutive sources; each is solved once with
@@ -142,6 +143,17 @@ typedef struct dct_opts {
                                  FP64); the higher moments keep G_k.  Converges to the same
                                  discrete solution; eps then measures max|f| / max|G|.  Uses
                                  the separate map and combine kernels (fuse_maps ignored). */
+    int sweep_rhs_chain;      /* right-hand sides chained through one sweep workgroup by
+                                 couplings 9 / 10 (2 / 1 z layers per wave): one direction of R
+                                 unfinished right-hand sides is swept back to back, so the
+                                 wavefront fills and drains once per R sources; q, psi and the
+                                 results are those of the other schedules.  Needs one block
+                                 (ny <= 64, nz <= 16), ny <= nx, keep_adjoint = 0, no
+                                 test_inflow, at least 2 right-hand sides and
+                                 B N C sizeof(real) <= 2^31; otherwise the solve runs
+                                 coupling 2.  R in [2, 8]; 0 = tuned among 2, 3, 4, 6, 8 (or
+                                 min(B, 4) when a chained coupling is asked for without
+                                 tuning); 1 = none. */
 } dct_opts;
 
 typedef struct dct_stats {
@@ -158,7 +170,8 @@ typedef struct dct_stats {
     int sweep_bk;             /* sweep schedule that ran: z layers per workgroup */
     int sweep_sync;           /* and coupling (1 LDS counters, 2 barriers, 3 pipelined blocks,
                                  4 / 5 layered waves of 4 / 2 z layers, 6 / 7 / 8 chained
-                                 directions with 1 / 2 / 4 z layers per wave) */
+                                 directions with 1 / 2 / 4 z layers per wave, 9 / 10 chained
+                                 right-hand sides with 2 / 1 z layers per wave) */
     double tune_ms;           /* device time spent timing candidate schedules in this call */
     long long sweep_launches_all; /* sweep kernel launches of the iteration sets (timed or not) */
     int sweep_chain;          /* directions per chained sweep workgroup that ran (1 = none) */
@@ -166,6 +179,7 @@ typedef struct dct_stats {
     int warm_start;           /* 1 when the solve started from the previous solve's moments */
     double fused_ms;          /* summed device time of the timed fused-map launches (profile > 0) */
     int fused_launches;       /* fused-map launches whose time is in fused_ms */
+    int sweep_rhs_chain;      /* right-hand sides per chained sweep workgroup that ran (1 = none) */
 } dct_stats;
 
 /* Create a context on HIP device `device` using `stream` (a hipStream_t; NULL

@@ -27,6 +27,7 @@
 #define DCT_MAXL 5
 #define DCT_MAXNM ((DCT_MAXL + 1) * (DCT_MAXL + 1))
 #define DCT_MAXCHAIN 16   // directions chained through one sweep workgroup
+#define DCT_MAXRC 8       // right-hand sides chained through one sweep workgroup
 #define DCT_PI 3.14159265358979323846
 
 namespace dct {
@@ -392,6 +393,8 @@ struct SweepArgs {
     int chainK;               // > 1: K consecutive directions of one octant per workgroup (k_sweep_ch);
                               //      q, psi in the chain layout, sigma_t from sigch
     const void *sigch;        // T [2][G][K C] sigma_t in the chain layout of period K nx
+    int rhsK;                 // > 1: one direction of up to rhsK unfinished right-hand sides per
+                              //      workgroup, swept back to back (k_sweep_rc)
 };
 
 struct AdjTransArgs {

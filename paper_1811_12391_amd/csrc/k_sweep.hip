@@ -994,6 +994,254 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_ch(SweepArgs a)
     }
 }
 
+// Source-chained layered waves (single block, forward sweep, no kept
+// fluxes): one workgroup sweeps direction n for up to K right-hand sides back
+// to back, the unfinished ones in order (chain c takes the c K-th to the
+// (c K + K - 1)-th of them).  As in k_sweep_lw, lane l of layer kp handles
+// the combined index pos = t - l - kp at step t; here slot d = pos / nx is the
+// d-th right-hand side of the chain and pos mod nx the reflected x index, so
+// a lane that finishes a source's row starts the next source's row on the
+// next step and the fill and drain of the wavefront (ny + nz - 2 steps) are
+// paid once per chain.  Every upwind neighbour of a cell is in the same slot
+// at the previous step, and each cell's arithmetic is that of k_sweep_lw, so
+// the angular fluxes are bitwise the same.
+//
+// All sources share the direction, hence its coefficients and its class
+// rotation: the rotated row of a wave step, (i +- j) mod nx, does not depend
+// on the slot, so q, psi and sigma_t keep their class layouts and a lane only
+// adds its slot's base offset (q and psi of (b, n); sigma_t of b's group),
+// switched when it starts a new row.  Offsets are 32-bit: the host launches
+// this kernel only while B N C sizeof(T) <= 2^31.  The boundary outflows of
+// each slot (particle balance) are reduced when the last lane starts the next
+// slot; the inflow boundary value is zero (no test inflow).
+template <typename T, int ZL, int PF>
+__global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
+{
+    constexpr unsigned TS = sizeof(T);
+    __shared__ T zbuf[2][17][64];                            // row w + 1: top layer of wave w; row 0: boundary
+    __shared__ double red[DCT_MAXRC][16][3];                 // per slot and z layer: x, y, z outflow sums
+    __shared__ int slot_b[DCT_MAXRC];                        // right-hand side of each slot
+    __shared__ unsigned tab_q[DCT_MAXRC], tab_s[DCT_MAXRC];  // byte offsets: q / psi of (b, n), sigma_t of b's group
+    __shared__ int kc_sh;
+    const int K = a.rhsK;
+    const int N = a.N;
+    const int c = blockIdx.x / N;
+    const int n = blockIdx.x - c * N;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const long C = a.C;
+    const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const double ox = a.dirs[3 * n], oy = a.dirs[3 * n + 1], oz = a.dirs[3 * n + 2];
+    const bool sx = ox > 0, sy = oy > 0, sz = oz > 0;
+    const int cls = dir_class(ox, oy);
+    if (w == 0) {
+        // the unfinished right-hand sides in order (ballot per 64)
+        int before = 0;
+        for (int base = 0; base < a.B; base += 64) {
+            const int b = base + l;
+            const bool act = b < a.B && !a.state[b].finished;
+            const unsigned long long m = __ballot(act);
+            const int s = before + __popcll(m & ((1ull << l) - 1ull)) - c * K;
+            if (act && s >= 0 && s < K) slot_b[s] = b;
+            before += __popcll(m);
+        }
+        if (l == 0) kc_sh = min(K, before - c * K);
+    }
+    for (int i = threadIdx.x; i < DCT_MAXRC * 16 * 3; i += blockDim.x) (&red[0][0][0])[i] = 0.0;
+    __syncthreads();
+    const int Kc = kc_sh;
+    if (Kc <= 0) return;
+    if ((int)threadIdx.x < Kc) {
+        const int b = slot_b[threadIdx.x];
+        const int g = eff_group(a.state[b].g, a.G, a.reverse);
+        tab_q[threadIdx.x] = (unsigned)(((long)b * N + n) * C * TS);
+        tab_s[threadIdx.x] = (unsigned)(((long)cls * a.G + g) * C * TS);
+    }
+    const T cx = (T)(2.0 * fabs(ox) / a.dx), cy = (T)(2.0 * fabs(oy) / a.dy), cz = (T)(2.0 * fabs(oz) / a.dz);
+    const T csum = cx + cy + cz;
+    const bool lv = l < ny;                                  // one y block: ny <= 64
+    const int nl = min(ny, 64);
+    const int j = lv ? (sy ? l : ny - 1 - l) : 0;
+    const int jm = j % nx;
+    const rsrc_t rq = mk_rsrc(a.q, (long)a.B * N * C * TS);
+    const rsrc_t rpsi = mk_rsrc(a.psi, (long)a.B * N * C * TS);
+    const rsrc_t rsg = mk_rsrc(a.sigc, 2L * a.G * C * TS);
+    const T bc = (T)0;
+    const int fixup = a.fixup;
+    // one step more than the wavefront needs: the last lane's slot change
+    // after the final row closes the last slot's outflow sums
+    const int Knx = Kc * nx;
+    const int NT = Knx + nl + nz - 1;
+    const int NTp = ((NT + PF - 1) / PF) * PF;
+    const int dr = sx ? 1 : -1;
+    const int dny = sx ? ny : -ny;
+    const int wrap_at_r = (sx ? nx : -1) * ny, wrap_to_r = (sx ? 0 : nx - 1) * ny;
+    const int rstart = rot_row(cls, sx ? 0 : nx - 1, jm, nx);
+    __syncthreads();
+    // per layer: validity, lane part of the offsets, start step, wave-uniform
+    // row offset of the prefetched step (step -1 first); the lane starting a
+    // row at the next load (Rl, slot Dl) and at the next compute step (Rz,
+    // slot Dz), with the slot bases the load switches to
+    bool vz[ZL];
+    int rowbase[ZL], t0[ZL], sre[ZL], Rl[ZL], Dl[ZL], Rz[ZL], Dz[ZL];
+    unsigned nq[ZL], ns[ZL], lq[ZL], ls[ZL];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z) {
+        const int kp = w * ZL + z;
+        vz[z] = lv && kp < nz;
+        const int k = vz[z] ? (sz ? kp : nz - 1 - kp) : 0;
+        rowbase[z] = k * nx * ny + j;
+        t0[z] = l + kp;
+        sre[z] = __builtin_amdgcn_readfirstlane((((rstart - dr * (t0[z] + 1)) % nx) + nx) % nx) * ny;
+        const int lp = -1 - kp, cp = -PF - kp;               // first load step -1, first compute step -PF
+        const int dl = (lp >= 0) ? lp / nx : -((-lp + nx - 1) / nx);
+        const int dc = (cp >= 0) ? cp / nx : -((-cp + nx - 1) / nx);
+        Rl[z] = lp - dl * nx;
+        Dl[z] = dl;
+        Rz[z] = cp - dc * nx;
+        Dz[z] = dc;
+        const int d0 = min(max(dl, 0), Kc - 1);
+        nq[z] = tab_q[d0];
+        ns[z] = tab_s[d0];
+        lq[z] = tab_q[0];
+        ls[z] = tab_s[0];
+    }
+    if (w == 0) zbuf[0][0][l] = zbuf[1][0][l] = bc;
+    __syncthreads();
+    T qr[ZL][PF], sr[ZL][PF];
+    unsigned sbr[ZL][PF];
+    bool actr[ZL][PF];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z)
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            qr[z][u] = sr[z][u] = (T)0;
+            sbr[z][u] = DCT_OOB;
+            actr[z][u] = false;
+        }
+    T ycar[ZL], xo[ZL], yo[ZL], zo[ZL], lyv[ZL], lxv[ZL];
+#pragma unroll
+    for (int z = 0; z < ZL; ++z) {
+        ycar[z] = xo[z] = lxv[z] = bc;
+        yo[z] = zo[z] = lyv[z] = (T)0;
+    }
+    T lzv = 0, lzp = 0;                                      // top layer: z outflows of the current / previous row
+    const int top_w = (nz - 1) / ZL, top_z = (nz - 1) - top_w * ZL;
+    for (int tb = -PF; tb < NTp; tb += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int t = tb + u;
+            T zin[ZL];
+            zin[0] = zbuf[(t + 1) & 1][w][l];
+#pragma unroll
+            for (int z = 1; z < ZL; ++z) zin[z] = zo[z - 1];
+            __builtin_amdgcn_sched_barrier(0);
+            // operands of step t + PF - 1 into the slot step t - 1 consumed;
+            // the lane starting a row there takes its slot's bases first
+            {
+                const int tp = t + PF - 1;
+                const int ps = (u + PF - 1) % PF;
+#pragma unroll
+                for (int z = 0; z < ZL; ++z) {
+                    const bool st = l == Rl[z];
+                    lq[z] = st ? nq[z] : lq[z];
+                    ls[z] = st ? ns[z] : ls[z];
+                    const bool inp = vz[z] && (unsigned)(tp - t0[z]) < (unsigned)Knx;
+                    const unsigned cell = (unsigned)(rowbase[z] + sre[z]) * TS;
+                    const unsigned pb = inp ? lq[z] + cell : DCT_OOB;
+                    const unsigned sb = inp ? ls[z] + cell : DCT_OOB;
+                    sbr[z][ps] = pb;
+                    actr[z][ps] = inp;
+                    qr[z][ps] = bld<T>(rq, pb);
+                    sr[z][ps] = bld<T>(rsg, sb);
+                    sre[z] += dny;
+                    sre[z] = sre[z] == wrap_at_r ? wrap_to_r : sre[z];
+                    if (++Rl[z] == nx) {
+                        Rl[z] = 0;
+                        ++Dl[z];
+                        const int dd = min(max(Dl[z], 0), Kc - 1);
+                        nq[z] = tab_q[dd];
+                        ns[z] = tab_s[dd];
+                    }
+                }
+            }
+            // a lane starting a row takes the boundary x inflow; its previous
+            // row's last x outflow is kept for the balance
+            bool start[ZL];
+            T n0v[ZL], y0[ZL], yin[ZL], xin[ZL];
+#pragma unroll
+            for (int z = 0; z < ZL; ++z) {
+                start[z] = l == Rz[z];
+                lxv[z] = start[z] ? xo[z] : lxv[z];
+                xin[z] = start[z] ? bc : xo[z];
+                ycar[z] = dpp_shift_up_or<T>(yo[z], ycar[z]);
+                yin[z] = ycar[z];
+                y0[z] = rcp_nr(sr[z][u] + csum);
+                n0v[z] = qr[z][u] + cx * xin[z] + cy * yin[z];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int z = 0; z < ZL; ++z) {
+                const int kp = w * ZL + z;
+                // the last lane starts slot Dz: every lane of this layer has
+                // finished slot Dz - 1, whose boundary outflows are summed now
+                if (Rz[z] == nl - 1 && Dz[z] >= 1 && Dz[z] <= Kc && kp < nz) {
+                    const bool top = w == top_w && z == top_z;
+                    if (top) lzp = start[z] ? lzv : lzp;
+                    double sx_ = vz[z] ? (double)lxv[z] : 0.0;
+                    double sz_ = (top && vz[z]) ? (double)lzp : 0.0;
+                    for (int o = 32; o > 0; o >>= 1) {
+                        sx_ += __shfl_down(sx_, o, 64);
+                        sz_ += __shfl_down(sz_, o, 64);
+                    }
+                    const double sy_ = (double)__shfl(lyv[z], nl - 1, 64);
+                    if (l == 0) {
+                        red[Dz[z] - 1][kp][0] = sx_;
+                        red[Dz[z] - 1][kp][1] = sy_;
+                        red[Dz[z] - 1][kp][2] = sz_;
+                    }
+                    lyv[z] = (T)0;
+                    if (top) {
+                        lzv = start[z] ? (T)0 : lzv;
+                        lzp = (T)0;
+                    }
+                } else if (w == top_w && z == top_z) {
+                    lzp = start[z] ? lzv : lzp;
+                    lzv = start[z] ? (T)0 : lzv;
+                }
+                const bool act = actr[z][u];
+                Cell4<T> cc;
+                cc.pc = fma(cz, zin[z], n0v[z]) * y0[z];
+                cc.xo = cc.pc + cc.pc - xin[z];
+                cc.yo = cc.pc + cc.pc - yin[z];
+                cc.zo = cc.pc + cc.pc - zin[z];
+                cc.fixed = 0;
+                if (fixup && act && fmin(cc.xo, fmin(cc.yo, cc.zo)) < (T)0)
+                    cc = dd_fixup<T>(qr[z][u], sr[z][u], cx, cy, cz, xin[z], yin[z], zin[z], cc);
+                if (z == ZL - 1) zbuf[t & 1][w + 1][l] = cc.zo;   // z handoff to the wave above
+                bst(rpsi, sbr[z][u], cc.pc);
+                lyv[z] += act ? cc.yo : (T)0;
+                if (w == top_w && z == top_z) lzv += act ? cc.zo : (T)0;
+                xo[z] = act ? cc.xo : xo[z];
+                yo[z] = cc.yo;
+                zo[z] = cc.zo;
+                if (++Rz[z] == nx) {
+                    Rz[z] = 0;
+                    ++Dz[z];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // boundary outflow sums of every slot, summed over the z layers in order
+    if ((int)threadIdx.x < 3 * Kc) {
+        const int d = threadIdx.x / 3, cc = threadIdx.x - 3 * d;
+        double s = 0.0;
+        for (int kp = 0; kp < nz; ++kp) s += red[d][kp][cc];
+        a.leak_part[((long)slot_b[d] * N + n) * a.nblk * 3 + cc] = s;
+    }
+}
+
 hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
 {
     a.seq = seq;
@@ -1026,6 +1274,24 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
             if (zl == 4) DCT_CH(float, 4); else if (zl == 2) DCT_CH(float, 2); else DCT_CH(float, 1);
         }
 #undef DCT_CH
+        return hipGetLastError();
+    }
+    if (a.rhsK > 1) {
+        // chained sources: one block, forward sweep without kept fluxes or test
+        // inflow, ny <= nx, 32-bit offsets (checked by the host)
+        if (multi || mode != 0 || a.ny > 64 || a.nz > 16 || a.ny > a.nx || a.rhsK > DCT_MAXRC || a.inflow ||
+            a.psi_bs != a.N || a.psi_gs != 0 || (long)a.B * a.N * a.C * (is_f64 ? 8 : 4) > (1L << 31))
+            return hipErrorInvalidValue;
+        const int zl = a.layers == 2 ? 2 : 1;
+        const int nwv = (a.nz + zl - 1) / zl;
+        const dim3 rgrid((unsigned)(a.N * ((a.B + a.rhsK - 1) / a.rhsK))), rblock(64 * nwv);
+#define DCT_RC(T, ZL) hipLaunchKernelGGL((k_sweep_rc<T, ZL, 8>), rgrid, rblock, 0, s, a)
+        if (is_f64) {
+            if (zl == 2) DCT_RC(double, 2); else DCT_RC(double, 1);
+        } else {
+            if (zl == 2) DCT_RC(float, 2); else DCT_RC(float, 1);
+        }
+#undef DCT_RC
         return hipGetLastError();
     }
     if ((a.layers == 2 || a.layers == 4) && !multi && mode != 2 && a.ny <= 64 && a.nz <= 16) {

@@ -108,11 +108,12 @@ struct dct_ctx {
 
     // sweep schedules chosen by the autotuner, per problem shape
     struct Tuned {
-        int nx, ny, nz, N, B, prec, keep, bk, sync, chain;
+        int nx, ny, nz, N, B, prec, keep, bk, sync, chain, rhs;
     };
     std::vector<Tuned> tuned;
     int last_bk = 16, last_sync = 1;   // schedule of the last solve (reused by the adjoint)
     int last_chain = 1;
+    int last_rhs = 1;
     bool last_fused = false;
     bool last_warm = false;
     // moments left in the "phi" buffer by the last completed solve (warm starts)
@@ -513,7 +514,9 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
                                              std::to_string(std::max(pl.Nc[0], pl.Nc[1])) + ")");
     }
     if (o.sweep_bk < 0 || o.sweep_bk > 16) return fail(ctx, DCT_EINVAL, "solve: sweep_bk must be in [0, 16]");
-    if (o.sweep_sync < 0 || o.sweep_sync > 8) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 8]");
+    if (o.sweep_sync < 0 || o.sweep_sync > 10) return fail(ctx, DCT_EINVAL, "solve: sweep_sync must be in [0, 10]");
+    if (o.sweep_rhs_chain < 0 || o.sweep_rhs_chain > DCT_MAXRC)
+        return fail(ctx, DCT_EINVAL, "solve: sweep_rhs_chain must be in [0, " + std::to_string(DCT_MAXRC) + "]");
     if (o.accel_depth < 0 || o.accel_depth > DCT_AA_MAXM)
         return fail(ctx, DCT_EINVAL, "solve: accel_depth must be in [0, " + std::to_string(DCT_AA_MAXM) + "]");
     if (o.sweep_chain < -1 || o.sweep_chain > DCT_MAXCHAIN)
@@ -616,6 +619,13 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
             if (ok) chain_ks.push_back(K);
         }
     }
+    // right-hand sides chained through one sweep workgroup (source-chained
+    // sweeps: one block, ny <= nx, no kept fluxes or test inflow, 32-bit offsets
+    // into q and psi)
+    std::vector<int> rhs_ks;
+    if (ny <= 64 && nz <= 16 && !keep && ny <= nx && !o.test_inflow && (size_t)B * N * C * ts <= ((size_t)1 << 31))
+        for (int K : {2, 3, 4, 6, 8})
+            if (K <= std::min(B, DCT_MAXRC)) rhs_ks.push_back(K);
     void *d_chn0, *d_chxo, *d_sigch = nullptr;
     HC(dbuf(ctx, "chn0", (size_t)N * 4, &d_chn0));
     HC(dbuf(ctx, "chxo", (size_t)N * 4, &d_chxo));
@@ -948,6 +958,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     sw.layers = 0;
     sw.chainK = 1;
     sw.sigch = d_sigch;
+    sw.rhsK = 1;
     sw.yface_p = d_yfp;
     sw.zface_p = d_zfp;
     sw.hint = (unsigned long long *)d_hint;
@@ -1007,14 +1018,17 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // block, ny <= 64 and nz <= 16, forward sweeps), 6 / 7 / 8 = the K
     // consecutive directions of one octant chained through one workgroup,
     // with 1 / 2 / 4 z layers per wave (one block, ny <= nx, forward sweeps
-    // without kept fluxes; q and psi in the chain layout)
+    // without kept fluxes; q and psi in the chain layout), 9 / 10 = one
+    // direction of R right-hand sides chained through one workgroup, with 2 / 1
+    // z layers per wave (same conditions, class layouts)
     double tune_ms = 0.0;
     const bool layered_ok = ny <= 64 && nz <= 16;
     auto set_coupling = [&](int cpl) {
         sw.sync = cpl == 1;
         sw.pipe = cpl == 3;
         sw.layers = (cpl == 4 && layered_ok) ? 4 : ((cpl == 5 && layered_ok) ? 2 : 0);
-        if (cpl >= 6) sw.layers = cpl == 6 ? 1 : (cpl == 7 ? 2 : 4);
+        if (cpl >= 6 && cpl <= 8) sw.layers = cpl == 6 ? 1 : (cpl == 7 ? 2 : 4);
+        if (cpl >= 9) sw.layers = cpl == 9 ? 2 : 1;
     };
     // q and psi in the layout of chain length K (1 = class layouts), sigma_t
     // copied into it
@@ -1043,10 +1057,13 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
         return DCT_OK;
     };
-    int chainK = 1;
+    int chainK = 1, rhsK = 1;
     {
         int bk = o.sweep_bk > 0 ? o.sweep_bk : 16, cpl = o.sweep_sync > 0 ? o.sweep_sync : 1;
-        chainK = o.sweep_chain > 1 ? o.sweep_chain : ((cpl >= 6 && !chain_ks.empty()) ? chain_ks.back() : 1);
+        chainK = o.sweep_chain > 1 ? o.sweep_chain :
+                 ((cpl >= 6 && cpl <= 8 && !chain_ks.empty()) ? chain_ks.back() : 1);
+        rhsK = o.sweep_rhs_chain > 0 ? o.sweep_rhs_chain : std::min(B, 4);
+        const bool free_rhs = o.sweep_rhs_chain == 0;
         // chained candidates take part in tuning only when asked for (sweep_chain
         // = -1): the tuner times sweeps alone, and the chain layout also costs
         // the maps some address arithmetic
@@ -1061,6 +1078,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 if (free_bk) bk = hit->bk;
                 if (free_cpl) cpl = hit->sync;
                 if (free_chain) chainK = hit->chain;
+                if (free_rhs) rhsK = hit->rhs;
             } else {
                 // first iteration set up to the sweep: the transition sets up
                 // group 0 (the first real set then finds nothing pending) and
@@ -1074,7 +1092,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                     HC(hipEventCreate(&ev));
                     ctx->evpool.push_back(ev);
                 }
-                struct Cand { int bk, cpl, K; };
+                struct Cand { int bk, cpl, K, R; };
                 std::vector<Cand> cands;
                 std::vector<int> bks;
                 if (free_bk) {
@@ -1087,15 +1105,18 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 for (int cb : bks) {
                     const bool multi = (ny + 63) / 64 > 1 || (nz + cb - 1) / cb > 1;
-                    for (int cc : {1, 2, 3, 4, 5, 6, 7, 8}) {
+                    for (int cc : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10}) {
                         if (!free_cpl && cc != cpl) continue;
                         if (cc == 3 && (!multi || cb < 2)) continue;   // pipelining needs several blocks
                         if (cc >= 4 && (!layered_ok || cb != std::min(16, nz))) continue;   // one block of every layer
-                        if (cc >= 6) {
+                        if (cc >= 9) {
+                            for (int R : rhs_ks)
+                                if (free_rhs || R == rhsK) cands.push_back({cb, cc, 1, R});
+                        } else if (cc >= 6) {
                             for (int K : chain_ks)
-                                if (free_chain || (K == chainK && o.sweep_chain > 1)) cands.push_back({cb, cc, K});
+                                if (free_chain || (K == chainK && o.sweep_chain > 1)) cands.push_back({cb, cc, K, 1});
                         } else if (free_chain || chainK == 1) {
-                            cands.push_back({cb, cc, 1});
+                            cands.push_back({cb, cc, 1, 1});
                         }
                     }
                 }
@@ -1104,6 +1125,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 for (auto cand : cands) {
                     apply_blocks(cand.bk);
                     set_coupling(cand.cpl);
+                    sw.rhsK = cand.R;
                     if (cand.cpl == 3) {
                         int r = pipe_ready();
                         if (r != DCT_OK) return r;
@@ -1136,22 +1158,28 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                         bk = cand.bk;
                         cpl = cand.cpl;
                         chainK = cand.K;
+                        rhsK = cand.R;
                     }
                 }
                 if (best == 1e30f) return fail(ctx, DCT_EDEVICE, "solve: no sweep schedule completed during tuning");
-                ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, (int)keep, bk, cpl, chainK});
+                ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, (int)keep, bk, cpl, chainK, rhsK});
             }
         }
         apply_blocks(bk);
         if (cpl == 3 && (pl.nblk == 1 || pl.BK < 2)) cpl = 1;   // one block (or 1-layer blocks): not pipelined
         if (cpl >= 4 && cpl <= 5 && (!layered_ok || pl.nblk != 1)) cpl = 2;   // layered waves need one block
-        if (cpl >= 6 && (pl.nblk != 1 || std::find(chain_ks.begin(), chain_ks.end(), chainK) == chain_ks.end())) {
+        if (cpl >= 6 && cpl <= 8 &&
+            (pl.nblk != 1 || std::find(chain_ks.begin(), chain_ks.end(), chainK) == chain_ks.end())) {
             cpl = 2;   // chains need one block and chains inside octants
             chainK = 1;
         }
-        if (cpl < 6) chainK = 1;
-        if (cpl >= 6 && chainK == 1) cpl = 2;
+        if (cpl < 6 || cpl > 8) chainK = 1;
+        if (cpl >= 6 && cpl <= 8 && chainK == 1) cpl = 2;
+        if (cpl >= 9 && (pl.nblk != 1 || rhs_ks.empty() || rhsK < 2 || rhsK > DCT_MAXRC))
+            cpl = 2;   // source chains need one block, several right-hand sides and 32-bit offsets
+        if (cpl < 9) rhsK = 1;
         set_coupling(cpl);
+        sw.rhsK = rhsK;
         HC(set_chain(chainK));
         if (cpl == 3) {
             int r = pipe_ready();
@@ -1160,6 +1188,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         ctx->last_bk = pl.BK;
         ctx->last_sync = cpl;
         ctx->last_chain = chainK;
+        ctx->last_rhs = rhsK;
     }
 
     // D map, combine and M map as one kernel (k_dcm): FP64 / FP32, the slab
@@ -1354,6 +1383,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         stats->sweep_bk = pl.BK;
         stats->sweep_sync = ctx->last_sync;
         stats->sweep_chain = ctx->last_chain;
+        stats->sweep_rhs_chain = ctx->last_rhs;
         stats->fused_maps = ctx->last_fused ? 1 : 0;
         stats->warm_start = ctx->last_warm ? 1 : 0;
         stats->tune_ms = tune_ms;
@@ -1770,6 +1800,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     sw.pipe = ctx->last_sync == 3;
     sw.layers = 0;                     // transposed sweeps run on k_sweep (barrier coupling for layered schedules)
     sw.chainK = 1;
+    sw.rhsK = 1;
     sw.sigch = nullptr;
     sw.yface_p = B_("yfp");
     sw.zface_p = B_("zfp");
