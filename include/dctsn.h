@@ -148,8 +148,8 @@ typedef struct dct_opts {
                                  unfinished right-hand sides is swept back to back, so the
                                  wavefront fills and drains once per R sources; q, psi and the
                                  results are those of the other schedules.  Needs one block
-                                 (ny <= 64, nz <= 16), ny <= nx, keep_adjoint = 0, no
-                                 test_inflow, at least 2 right-hand sides and
+                                 (ny <= 64, nz <= 16), ny <= nx, nx >= 8, keep_adjoint = 0,
+                                 no test_inflow, at least 2 right-hand sides and
                                  B N C sizeof(real) <= 2^31; otherwise the solve runs
                                  coupling 2.  R in [2, 8]; 0 = tuned among 2, 3, 4, 6, 8 (or
                                  min(B, 4) when a chained coupling is asked for without

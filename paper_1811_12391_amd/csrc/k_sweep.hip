@@ -1011,17 +1011,27 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_ch(SweepArgs a)
 // on the slot, so q, psi and sigma_t keep their class layouts and a lane only
 // adds its slot's base offset (q and psi of (b, n); sigma_t of b's group),
 // switched when it starts a new row.  Offsets are 32-bit: the host launches
-// this kernel only while B N C sizeof(T) <= 2^31.  The boundary outflows of
-// each slot (particle balance) are reduced when the last lane starts the next
-// slot; the inflow boundary value is zero (no test inflow).
+// this kernel only while B N C sizeof(T) <= 2^31 (and nx >= PF, ny <= nx).
+//
+// Step bookkeeping is per wave: with ph = (t - ZL w) mod nx and slot sl =
+// (t - ZL w) div nx at compute step t, the lane starting a row in layer z is
+// (ph - z) mod nx, in slot sl or sl - 1; the load of step t + PF - 1 is
+// PF - 1 further on, in slot sl or sl + 1, whose bases are kept
+// wave-uniform and refreshed when ph wraps.  The boundary
+// outflows of a row (its last x outflow; the y outflows of the last row; the
+// z outflows of the top layer) are written by its lane into an LDS table per
+// slot when the lane starts its next row, and summed in a fixed order at the
+// end (particle balance); the inflow boundary value is zero (no test inflow).
 template <typename T, int ZL, int PF>
 __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
 {
     constexpr unsigned TS = sizeof(T);
     __shared__ T zbuf[2][17][64];                            // row w + 1: top layer of wave w; row 0: boundary
-    __shared__ double red[DCT_MAXRC][16][3];                 // per slot and z layer: x, y, z outflow sums
+    __shared__ T ox_t[DCT_MAXRC + 1][16][64];                // per slot, z layer, lane: last x outflow of the row
+    __shared__ T oy_t[DCT_MAXRC + 1][16];                    // per slot, z layer: y outflows of the last row
+    __shared__ T oz_t[DCT_MAXRC + 1][64];                    // per slot, lane: z outflows of the top layer's row
     __shared__ int slot_b[DCT_MAXRC];                        // right-hand side of each slot
-    __shared__ unsigned tab_q[DCT_MAXRC], tab_s[DCT_MAXRC];  // byte offsets: q / psi of (b, n), sigma_t of b's group
+    __shared__ unsigned tab_q[DCT_MAXRC + 2], tab_s[DCT_MAXRC + 2];  // byte offsets (index d + 1 for slot d)
     __shared__ int kc_sh;
     const int K = a.rhsK;
     const int N = a.N;
@@ -1046,12 +1056,12 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
         }
         if (l == 0) kc_sh = min(K, before - c * K);
     }
-    for (int i = threadIdx.x; i < DCT_MAXRC * 16 * 3; i += blockDim.x) (&red[0][0][0])[i] = 0.0;
     __syncthreads();
     const int Kc = kc_sh;
     if (Kc <= 0) return;
-    if ((int)threadIdx.x < Kc) {
-        const int b = slot_b[threadIdx.x];
+    if ((int)threadIdx.x < Kc + 2) {
+        // slot d at index d + 1; the indices before and after repeat the ends
+        const int d = min(max((int)threadIdx.x - 1, 0), Kc - 1), b = slot_b[d];
         const int g = eff_group(a.state[b].g, a.G, a.reverse);
         tab_q[threadIdx.x] = (unsigned)(((long)b * N + n) * C * TS);
         tab_s[threadIdx.x] = (unsigned)(((long)cls * a.G + g) * C * TS);
@@ -1067,8 +1077,8 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
     const rsrc_t rsg = mk_rsrc(a.sigc, 2L * a.G * C * TS);
     const T bc = (T)0;
     const int fixup = a.fixup;
-    // one step more than the wavefront needs: the last lane's slot change
-    // after the final row closes the last slot's outflow sums
+    // one step more than the wavefront needs: every lane of every layer
+    // starts the (empty) slot after the last, which records its last row
     const int Knx = Kc * nx;
     const int NT = Knx + nl + nz - 1;
     const int NTp = ((NT + PF - 1) / PF) * PF;
@@ -1076,14 +1086,11 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
     const int dny = sx ? ny : -ny;
     const int wrap_at_r = (sx ? nx : -1) * ny, wrap_to_r = (sx ? 0 : nx - 1) * ny;
     const int rstart = rot_row(cls, sx ? 0 : nx - 1, jm, nx);
+    const int top_w = (nz - 1) / ZL, top_z = (nz - 1) - top_w * ZL;
     __syncthreads();
-    // per layer: validity, lane part of the offsets, start step, wave-uniform
-    // row offset of the prefetched step (step -1 first); the lane starting a
-    // row at the next load (Rl, slot Dl) and at the next compute step (Rz,
-    // slot Dz), with the slot bases the load switches to
     bool vz[ZL];
-    int rowbase[ZL], t0[ZL], sre[ZL], Rl[ZL], Dl[ZL], Rz[ZL], Dz[ZL];
-    unsigned nq[ZL], ns[ZL], lq[ZL], ls[ZL];
+    int rowbase[ZL], t0[ZL], sre[ZL];
+    unsigned lq[ZL], ls[ZL];
 #pragma unroll
     for (int z = 0; z < ZL; ++z) {
         const int kp = w * ZL + z;
@@ -1092,19 +1099,17 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
         rowbase[z] = k * nx * ny + j;
         t0[z] = l + kp;
         sre[z] = __builtin_amdgcn_readfirstlane((((rstart - dr * (t0[z] + 1)) % nx) + nx) % nx) * ny;
-        const int lp = -1 - kp, cp = -PF - kp;               // first load step -1, first compute step -PF
-        const int dl = (lp >= 0) ? lp / nx : -((-lp + nx - 1) / nx);
-        const int dc = (cp >= 0) ? cp / nx : -((-cp + nx - 1) / nx);
-        Rl[z] = lp - dl * nx;
-        Dl[z] = dl;
-        Rz[z] = cp - dc * nx;
-        Dz[z] = dc;
-        const int d0 = min(max(dl, 0), Kc - 1);
-        nq[z] = tab_q[d0];
-        ns[z] = tab_s[d0];
-        lq[z] = tab_q[0];
-        ls[z] = tab_s[0];
+        lq[z] = tab_q[1];
+        ls[z] = tab_s[1];
     }
+    // wave phase at the first compute step t = -PF
+    const int p0 = -PF - w * ZL;
+    int sl = (p0 >= 0) ? p0 / nx : -((-p0 + nx - 1) / nx);
+    int ph = p0 - sl * nx;
+    auto tabq = [&](int d) { return tab_q[min(max(d, -1), Kc) + 1]; };
+    auto tabs = [&](int d) { return tab_s[min(max(d, -1), Kc) + 1]; };
+    unsigned bq_0 = tabq(sl), bq_p = tabq(sl + 1);
+    unsigned bs_0 = tabs(sl), bs_p = tabs(sl + 1);
     if (w == 0) zbuf[0][0][l] = zbuf[1][0][l] = bc;
     __syncthreads();
     T qr[ZL][PF], sr[ZL][PF];
@@ -1118,14 +1123,13 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
             sbr[z][u] = DCT_OOB;
             actr[z][u] = false;
         }
-    T ycar[ZL], xo[ZL], yo[ZL], zo[ZL], lyv[ZL], lxv[ZL];
+    T ycar[ZL], xo[ZL], yo[ZL], zo[ZL], lyv[ZL];
 #pragma unroll
     for (int z = 0; z < ZL; ++z) {
-        ycar[z] = xo[z] = lxv[z] = bc;
+        ycar[z] = xo[z] = bc;
         yo[z] = zo[z] = lyv[z] = (T)0;
     }
-    T lzv = 0, lzp = 0;                                      // top layer: z outflows of the current / previous row
-    const int top_w = (nz - 1) / ZL, top_z = (nz - 1) - top_w * ZL;
+    T lzv = 0;                                               // top layer: z outflows of the lane's current row
     for (int tb = -PF; tb < NTp; tb += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -1138,14 +1142,19 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
             // operands of step t + PF - 1 into the slot step t - 1 consumed;
             // the lane starting a row there takes its slot's bases first
             {
-                const int tp = t + PF - 1;
                 const int ps = (u + PF - 1) % PF;
 #pragma unroll
                 for (int z = 0; z < ZL; ++z) {
-                    const bool st = l == Rl[z];
-                    lq[z] = st ? nq[z] : lq[z];
-                    ls[z] = st ? ns[z] : ls[z];
-                    const bool inp = vz[z] && (unsigned)(tp - t0[z]) < (unsigned)Knx;
+                    // layer z at the load: the starting lane is ph - z + PF - 1
+                    // (>= 0 as z < PF), in slot sl, or sl + 1 past nx (nx >= PF)
+                    const int x = ph - z + PF - 1;
+                    const bool hi = x >= nx;
+                    const unsigned nq = hi ? bq_p : bq_0;
+                    const unsigned ns = hi ? bs_p : bs_0;
+                    const bool st = l == (hi ? x - nx : x);
+                    lq[z] = st ? nq : lq[z];
+                    ls[z] = st ? ns : ls[z];
+                    const bool inp = vz[z] && (unsigned)(t + PF - 1 - t0[z]) < (unsigned)Knx;
                     const unsigned cell = (unsigned)(rowbase[z] + sre[z]) * TS;
                     const unsigned pb = inp ? lq[z] + cell : DCT_OOB;
                     const unsigned sb = inp ? ls[z] + cell : DCT_OOB;
@@ -1155,23 +1164,28 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
                     sr[z][ps] = bld<T>(rsg, sb);
                     sre[z] += dny;
                     sre[z] = sre[z] == wrap_at_r ? wrap_to_r : sre[z];
-                    if (++Rl[z] == nx) {
-                        Rl[z] = 0;
-                        ++Dl[z];
-                        const int dd = min(max(Dl[z], 0), Kc - 1);
-                        nq[z] = tab_q[dd];
-                        ns[z] = tab_s[dd];
-                    }
                 }
             }
-            // a lane starting a row takes the boundary x inflow; its previous
-            // row's last x outflow is kept for the balance
+            // a lane starting a row takes the boundary x inflow and records
+            // the outflows of its previous row (slot d - 1) for the balance
             bool start[ZL];
             T n0v[ZL], y0[ZL], yin[ZL], xin[ZL];
 #pragma unroll
             for (int z = 0; z < ZL; ++z) {
-                start[z] = l == Rz[z];
-                lxv[z] = start[z] ? xo[z] : lxv[z];
+                const int kp = w * ZL + z;
+                const bool lo = ph < z;
+                const int cph = lo ? ph - z + nx : ph - z;
+                const int d = lo ? sl - 1 : sl;              // slot of the starting lane
+                start[z] = l == cph;
+                const bool rec = start[z] && d >= 1 && d <= Kc && vz[z];
+                const int dd = rec ? d - 1 : DCT_MAXRC;      // row DCT_MAXRC takes the lanes that record nothing
+                ox_t[dd][kp][l] = xo[z];
+                if (l == nl - 1) oy_t[dd][kp] = lyv[z];
+                if (w == top_w && z == top_z) {
+                    oz_t[dd][l] = lzv;
+                    lzv = start[z] ? (T)0 : lzv;
+                }
+                lyv[z] = start[z] ? (T)0 : lyv[z];
                 xin[z] = start[z] ? bc : xo[z];
                 ycar[z] = dpp_shift_up_or<T>(yo[z], ycar[z]);
                 yin[z] = ycar[z];
@@ -1181,33 +1195,6 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int z = 0; z < ZL; ++z) {
-                const int kp = w * ZL + z;
-                // the last lane starts slot Dz: every lane of this layer has
-                // finished slot Dz - 1, whose boundary outflows are summed now
-                if (Rz[z] == nl - 1 && Dz[z] >= 1 && Dz[z] <= Kc && kp < nz) {
-                    const bool top = w == top_w && z == top_z;
-                    if (top) lzp = start[z] ? lzv : lzp;
-                    double sx_ = vz[z] ? (double)lxv[z] : 0.0;
-                    double sz_ = (top && vz[z]) ? (double)lzp : 0.0;
-                    for (int o = 32; o > 0; o >>= 1) {
-                        sx_ += __shfl_down(sx_, o, 64);
-                        sz_ += __shfl_down(sz_, o, 64);
-                    }
-                    const double sy_ = (double)__shfl(lyv[z], nl - 1, 64);
-                    if (l == 0) {
-                        red[Dz[z] - 1][kp][0] = sx_;
-                        red[Dz[z] - 1][kp][1] = sy_;
-                        red[Dz[z] - 1][kp][2] = sz_;
-                    }
-                    lyv[z] = (T)0;
-                    if (top) {
-                        lzv = start[z] ? (T)0 : lzv;
-                        lzp = (T)0;
-                    }
-                } else if (w == top_w && z == top_z) {
-                    lzp = start[z] ? lzv : lzp;
-                    lzv = start[z] ? (T)0 : lzv;
-                }
                 const bool act = actr[z][u];
                 Cell4<T> cc;
                 cc.pc = fma(cz, zin[z], n0v[z]) * y0[z];
@@ -1224,20 +1211,31 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
                 xo[z] = act ? cc.xo : xo[z];
                 yo[z] = cc.yo;
                 zo[z] = cc.zo;
-                if (++Rz[z] == nx) {
-                    Rz[z] = 0;
-                    ++Dz[z];
-                }
+            }
+            // next step's phase; the slot bases follow the slot
+            if (++ph == nx) {
+                ph = 0;
+                ++sl;
+                bq_0 = bq_p;
+                bq_p = tabq(sl + 1);
+                bs_0 = bs_p;
+                bs_p = tabs(sl + 1);
             }
             __syncthreads();
         }
     }
-    __syncthreads();
-    // boundary outflow sums of every slot, summed over the z layers in order
+    // boundary outflow sums of every slot, in a fixed order (layers, then lanes)
     if ((int)threadIdx.x < 3 * Kc) {
         const int d = threadIdx.x / 3, cc = threadIdx.x - 3 * d;
         double s = 0.0;
-        for (int kp = 0; kp < nz; ++kp) s += red[d][kp][cc];
+        if (cc == 0) {
+            for (int kp = 0; kp < nz; ++kp)
+                for (int q = 0; q < nl; ++q) s += (double)ox_t[d][kp][q];
+        } else if (cc == 1) {
+            for (int kp = 0; kp < nz; ++kp) s += (double)oy_t[d][kp];
+        } else {
+            for (int q = 0; q < nl; ++q) s += (double)oz_t[d][q];
+        }
         a.leak_part[((long)slot_b[d] * N + n) * a.nblk * 3 + cc] = s;
     }
 }
@@ -1279,7 +1277,7 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
     if (a.rhsK > 1) {
         // chained sources: one block, forward sweep without kept fluxes or test
         // inflow, ny <= nx, 32-bit offsets (checked by the host)
-        if (multi || mode != 0 || a.ny > 64 || a.nz > 16 || a.ny > a.nx || a.rhsK > DCT_MAXRC || a.inflow ||
+        if (multi || mode != 0 || a.ny > 64 || a.nz > 16 || a.ny > a.nx || a.nx < 8 || a.rhsK > DCT_MAXRC || a.inflow ||
             a.psi_bs != a.N || a.psi_gs != 0 || (long)a.B * a.N * a.C * (is_f64 ? 8 : 4) > (1L << 31))
             return hipErrorInvalidValue;
         const int zl = a.layers == 2 ? 2 : 1;

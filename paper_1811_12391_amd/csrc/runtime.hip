@@ -620,10 +620,11 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
     }
     // right-hand sides chained through one sweep workgroup (source-chained
-    // sweeps: one block, ny <= nx, no kept fluxes or test inflow, 32-bit offsets
-    // into q and psi)
+    // sweeps: one block, ny <= nx, nx >= 8, no kept fluxes or test inflow,
+    // 32-bit offsets into q and psi)
     std::vector<int> rhs_ks;
-    if (ny <= 64 && nz <= 16 && !keep && ny <= nx && !o.test_inflow && (size_t)B * N * C * ts <= ((size_t)1 << 31))
+    if (ny <= 64 && nz <= 16 && !keep && ny <= nx && nx >= 8 && !o.test_inflow &&
+        (size_t)B * N * C * ts <= ((size_t)1 << 31))
         for (int K : {2, 3, 4, 6, 8})
             if (K <= std::min(B, DCT_MAXRC)) rhs_ks.push_back(K);
     void *d_chn0, *d_chxo, *d_sigch = nullptr;
