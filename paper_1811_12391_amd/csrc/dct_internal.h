@@ -132,6 +132,16 @@ template <> __device__ inline int out_row<double>(int kr, int r) { return kr + 4
 // exactly the load a step consumes).
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 #define DCT_OOB 0x80000000u
+// A pointer the compiler cannot prove wave-uniform (e.g. computed from a
+// value loaded from memory) made wave-uniform, so that a buffer descriptor
+// built from it lives in scalar registers.
+__device__ inline const void *wave_ptr(const void *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (const void *)(((unsigned long long)hi << 32) | lo);
+}
 __device__ inline rsrc_t mk_rsrc(const void *p, long bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, p ? (int)bytes : 0, 0x00020000);
@@ -472,7 +482,9 @@ hipError_t launch_qinit(const CombArgs &a, int is_f64, hipStream_t s);
 // iterate phi_00 (and the moment-0 source in both class layouts)
 hipError_t launch_aa(const AAArgs &a, int is_f64, hipStream_t s);
 // D map + combine + M map of one iteration in one kernel (forward FP64 / FP32 solves)
-hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s);
+// first = 1: only the sources at the first iteration of a group, whose q the
+// kernel forms from ext alone (the work of k_qinit and the M map)
+hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s, int first = 0);
 size_t dcm_lds_bytes(const CombArgs &a, const MapArgs &m, int is_f64);   // Q = ext in the class layouts after a transition
 hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f64, 1 f32, 2 bf16
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);

@@ -606,9 +606,10 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
 // same bit for bit.  The last workgroup of the right-hand side applies the
 // stopping rule; when the group stops, the q written here is replaced after
 // the transition (the M map runs for the first iteration of a group).
-template <typename T, int NRB, int KC>
+template <typename T, int NRB, int KC, bool FIRST>
 __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
 {
+    constexpr bool first = FIRST;
     typedef typename acc4<T>::type A4;                        // KC: K-steps of 4 directions, covering a class
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ double red[16];
@@ -625,11 +626,14 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
         const unsigned xcd = lin & 7, slot = lin >> 3;
         W = 2 * ((slot >> 1) * 8 + xcd) + (slot & 1);
     }
-    const int b = (int)(W / nsl), slab = (int)(W - (unsigned)b * nsl);
+    const int b = __builtin_amdgcn_readfirstlane((int)(W / nsl));
+    const int slab = __builtin_amdgcn_readfirstlane((int)(W - (unsigned)b * nsl));
     RhsState *st = a.state + b;
     if (st->finished) return;
-    const int gseq = st->g;
-    const int g = eff_group(gseq, a.G, a.reverse);
+    // first iteration of a group: only the sources that start one
+    if (first && (st->pending || st->it != 0)) return;
+    const int gseq = __builtin_amdgcn_readfirstlane(st->g);   // wave-uniform: the buffer descriptors below stay scalar
+    const int g = __builtin_amdgcn_readfirstlane(eff_group(gseq, a.G, a.reverse));
     const long C = a.geo.C;
     const int G = a.G, Nm = a.Nm, L = a.L, N = m.N;
     const int k = slab / nslj, j0 = (slab % nslj) * 16;
@@ -642,6 +646,7 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     T *Dt = tile + (long)Nm * LMS;                            // [2][NmP][NcP + 1]
     T *Mt = Dt + 2 * NmP * DST;                               // [2][NcP][NmP + 1]
     int *cds = (int *)(Mt + 2 * NcP * MST);                   // [2][N] class-local -> global direction
+    unsigned *cdo = (unsigned *)(cds + 2 * N);                // [2][N] its byte offset n C sizeof(T)
     for (int i = threadIdx.x; i < 2 * NmP * NcP; i += blockDim.x) {
         const int c = i / (NmP * NcP), r = (i / NcP) % NmP, q = i % NcP;
         Dt[(c * NmP + r) * DST + q] = ((const T *)m.Dtab)[i];
@@ -650,7 +655,15 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
         const int c = i / (NcP * NmP), r = (i / NmP) % NcP, q = i % NmP;
         Mt[(c * NcP + r) * MST + q] = ((const T *)m.Mtab)[i];
     }
-    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) cds[i] = m.cdir[i];
+    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+        cds[i] = m.cdir[i];
+        cdo[i] = (unsigned)((long)m.cdir[i] * C * (long)sizeof(T));
+    }
+    // in the class layouts an element's offset is (direction part) + (cell
+    // part), both 32-bit (the host keeps N C sizeof(T) < 2^31); the chain
+    // layout goes through dir_elem
+    const bool fast = m.chainK <= 1;
+    const int Nc0 = m.Nc[0], Nc1 = m.Nc[1];
     if ((int)threadIdx.x < a.M * (L + 1)) {
         const int mm = threadIdx.x / (L + 1), ll = threadIdx.x - mm * (L + 1);
         ssg[threadIdx.x] = a.ss[(((long)mm * (L + 1) + ll) * G + g) * G + g];
@@ -667,9 +680,24 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     // pair of class B after the last of class A) before the matrix-core work
     // of the current one, so two pairs of loads are in flight.
     const T *psi = (const T *)m.psi + ((long)b * m.psi_bs + (long)g * m.psi_gs) * C;
+    const rsrc_t rps = mk_rsrc(wave_ptr(psi), (long)N * C * (long)sizeof(T));
     T bA[2][KC], bB[2][KC];
     auto load_pair = [&](int c, int r0, T (&bv)[2][KC]) __attribute__((always_inline)) {
-        const int Nc = m.Nc[c];
+        const int Nc = c == 0 ? Nc0 : Nc1;
+        if (fast) {
+            const unsigned *co = cdo + c * N;
+            unsigned o[KC];
+#pragma unroll
+            for (int u = 0; u < KC; ++u) o[u] = co[min(4 * u + kr, Nc - 1)];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = min(r0 + h * nwv, nx - 1);
+                const unsigned p4 = (unsigned)((((long)k * nx + r) * ny + jc) * (long)sizeof(T));
+#pragma unroll
+                for (int u = 0; u < KC; ++u) bv[h][u] = bld<T>(rps, o[u] + p4);
+            }
+            return;
+        }
         const int *cd = cds + c * N;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -681,8 +709,8 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
         }
     };
     bool have = false;                                        // bA holds the operands of the pair at hand
-    for (int c = 0; c < 2; ++c) {
-        const int Nc = m.Nc[c];
+    for (int c = 0; c < (first ? 0 : 2); ++c) {
+        const int Nc = c == 0 ? Nc0 : Nc1;
         if (!have && wv < nx) {
             load_pair(c, wv, bA);
             have = true;
@@ -743,7 +771,26 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
     const T *ext = (const T *)a.ext + (long)b * Nm * C;
     const int tile_n = 16 * nx;
-    for (int idx = threadIdx.x; idx < tile_n; idx += blockDim.x) {
+    // first iteration: the source is the group source ext (plus the
+    // within-group scatter of the moments a warm start begins from), laid
+    // into the tile as k_qinit lays it out
+    for (int idx = threadIdx.x; first && idx < tile_n; idx += blockDim.x) {
+        const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
+        if (jy >= ny) continue;
+        const long v = i + (long)nx * (jy + (long)ny * k);
+        const double rh = a.rho[v];
+        const int mt = a.mat[v];
+        for (int lm = 0; lm < Nm; ++lm) {
+            T *tp = &tile[lm * LMS + jl * pitch + i];
+            if (a.warm) {
+                const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
+                *tp = (T)((double)ext[(long)lm * C + v] + sc * (double)phib[(long)lm * C + v]);
+            } else {
+                *tp = ext[(long)lm * C + v];
+            }
+        }
+    }
+    for (int idx = threadIdx.x; !first && idx < tile_n; idx += blockDim.x) {
         const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
         if (jy >= ny) continue;
         const long v = i + (long)nx * (jy + (long)ny * k);
@@ -773,8 +820,42 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     // ---- 3. M map of each class from the tile
     T *q = (T *)m.q + (long)b * N * C;
     const int NS = (Nm + 3) / 4;                              // K-steps of 4 moments
-    for (int c = 0; c < 2; ++c) {
-        const int Nc = m.Nc[c];
+    if (fast) {
+        // q stored through a buffer descriptor: every lane stores, rows past
+        // the class's directions or the grid take an out-of-range offset
+        const rsrc_t rqq = mk_rsrc(wave_ptr(q), (long)N * C * (long)sizeof(T));
+        for (int c = 0; c < 2; ++c) {
+            const int Nc = c == 0 ? Nc0 : Nc1;
+            const unsigned *co = cdo + c * N;
+            unsigned qo[3][4];                                // up to 48 directions per class (host check)
+#pragma unroll
+            for (int rb = 0; rb < 3; ++rb)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int nl = rb * 16 + out_row<T>(kr, e);
+                    qo[rb][e] = (nl < Nc && jok) ? co[nl] : DCT_OOB;
+                }
+            for (int r = wv; r < nx; r += nwv) {
+                const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;
+                const unsigned p4 = (unsigned)((((long)k * nx + r) * ny + jc) * (long)sizeof(T));
+                T bq[4 * NRB];
+#pragma unroll
+                for (int s = 0; s < 4 * NRB; ++s) bq[s] = tile[min(4 * s + kr, Nm - 1) * LMS + col * pitch + i];
+#pragma unroll
+                for (int rb = 0; rb < 3; ++rb) {
+                    if (rb * 16 >= Nc) break;
+                    A4 acc = {0, 0, 0, 0};
+#pragma unroll
+                    for (int s = 0; s < 4 * NRB; ++s)
+                        if (s < NS) acc = mfma_k4(Mt[(c * NcP + rb * 16 + col) * MST + 4 * s + kr], bq[s], acc);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) bst(rqq, qo[rb][e] == DCT_OOB ? DCT_OOB : qo[rb][e] + p4, acc[e]);
+                }
+            }
+        }
+    }
+    for (int c = 0; c < (fast ? 0 : 2); ++c) {
+        const int Nc = c == 0 ? Nc0 : Nc1;
         const int *cd = cds + c * N;
         for (int r = wv; r < nx; r += nwv) {
             const long p = ((long)k * nx + r) * ny + jc;
@@ -797,6 +878,7 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
         }
     }
     // ---- 4. change of phi_00 and the end of the iteration
+    if (first) return;
     const double dm = block_max(dmax, red);
     const double fm = block_max(fmax_, red);
     if (threadIdx.x == 0) {
@@ -812,25 +894,29 @@ size_t dcm_lds_bytes(const CombArgs &a, const MapArgs &m, int is_f64)
     const size_t ts = is_f64 ? 8 : 4;
     const size_t pitch = (size_t)((a.geo.nx | 1) + 1);
     return (size_t)a.Nm * (16 * pitch + 4) * ts + (size_t)2 * m.NmP * (m.NcP + 1) * ts +
-           (size_t)2 * m.NcP * (m.NmP + 1) * ts + (size_t)2 * m.N * 4;
+           (size_t)2 * m.NcP * (m.NmP + 1) * ts + (size_t)4 * m.N * 4;
 }
 
-hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s)
+hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s, int first)
 {
     const int nslj = (a.geo.ny + 15) >> 4;
     const dim3 grid((unsigned)(a.geo.nz * nslj), a.B);
     const size_t shm = dcm_lds_bytes(a, m, is_f64);
     const int nrb = (a.Nm + 15) / 16;
-#define DCT_DCM(T, R, K)                                                                                  \
+#define DCT_DCM(T, R, K, F)                                                                               \
     do {                                                                                                  \
-        hipError_t e_ = hipFuncSetAttribute((const void *)k_dcm<T, R, K>,                                  \
+        hipError_t e_ = hipFuncSetAttribute((const void *)k_dcm<T, R, K, F>,                               \
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);        \
         if (e_ != hipSuccess) return e_;                                                                  \
-        hipLaunchKernelGGL((k_dcm<T, R, K>), grid, dim3(512), shm, s, a, m);                               \
+        hipLaunchKernelGGL((k_dcm<T, R, K, F>), grid, dim3(512), shm, s, a, m);                            \
     } while (0)
+    // the first-iteration form has no D map, so one K-step width serves it
 #define DCT_DCM_K(T, R)                                                                                   \
     do {                                                                                                  \
-        if (kc <= 4) DCT_DCM(T, R, 4); else if (kc <= 8) DCT_DCM(T, R, 8); else DCT_DCM(T, R, 12);          \
+        if (first) DCT_DCM(T, R, 4, true);                                                                 \
+        else if (kc <= 4) DCT_DCM(T, R, 4, false);                                                         \
+        else if (kc <= 8) DCT_DCM(T, R, 8, false);                                                         \
+        else DCT_DCM(T, R, 12, false);                                                                    \
     } while (0)
     const int kc = ((m.Nc[0] > m.Nc[1] ? m.Nc[0] : m.Nc[1]) + 3) / 4;   // K-steps of one class (<= 12)
     if (kc > 12) return hipErrorInvalidValue;

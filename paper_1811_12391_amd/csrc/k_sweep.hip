@@ -996,8 +996,8 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_ch(SweepArgs a)
 
 // Source-chained layered waves (single block, forward sweep, no kept
 // fluxes): one workgroup sweeps direction n for up to K right-hand sides back
-// to back, the unfinished ones in order (chain c takes the c K-th to the
-// (c K + K - 1)-th of them).  As in k_sweep_lw, lane l of layer kp handles
+// to back, the unfinished ones dealt to the ceil(B / K) chains of the
+// direction round robin (so a chain shortens as sources finish).  As in k_sweep_lw, lane l of layer kp handles
 // the combined index pos = t - l - kp at step t; here slot d = pos / nx is the
 // d-th right-hand side of the chain and pos mod nx the reflected x index, so
 // a lane that finishes a source's row starts the next source's row on the
@@ -1044,17 +1044,20 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
     const bool sx = ox > 0, sy = oy > 0, sz = oz > 0;
     const int cls = dir_class(ox, oy);
     if (w == 0) {
-        // the unfinished right-hand sides in order (ballot per 64)
+        // the unfinished right-hand sides in order (ballot per 64), dealt to
+        // the chains round robin: the s-th goes to chain s mod nch, slot
+        // s div nch, so every chain stays busy as sources finish
+        const int nch = gridDim.x / N;
         int before = 0;
         for (int base = 0; base < a.B; base += 64) {
             const int b = base + l;
             const bool act = b < a.B && !a.state[b].finished;
             const unsigned long long m = __ballot(act);
-            const int s = before + __popcll(m & ((1ull << l) - 1ull)) - c * K;
-            if (act && s >= 0 && s < K) slot_b[s] = b;
+            const int s = before + __popcll(m & ((1ull << l) - 1ull));
+            if (act && s % nch == c && s / nch < K) slot_b[s / nch] = b;
             before += __popcll(m);
         }
-        if (l == 0) kc_sh = min(K, before - c * K);
+        if (l == 0) kc_sh = min(K, (before - c + nch - 1) / nch);
     }
     __syncthreads();
     const int Kc = kc_sh;

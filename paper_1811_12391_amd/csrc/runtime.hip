@@ -1201,7 +1201,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         const long nslab = (long)nz * ((ny + 15) / 16);
         const size_t lds = dcm_lds_bytes(cb, ma, is64) + 1024;
         const bool fuse_ok = mode <= 1 && lds <= ctx->lds_max && nslab <= 32L * DCT_MAXNM &&
-                             std::max(pl.Nc[0], pl.Nc[1]) <= 48;   // one round of psi loads per class
+                             std::max(pl.Nc[0], pl.Nc[1]) <= 48 &&   // one round of psi loads per class
+                             (size_t)N * C * ts < ((size_t)1 << 31);  // 32-bit offsets of one source's q / psi
         // by default: enough slabs to fill the GPU and two workgroups per CU
         // (one workgroup of 8 waves per CU leaves too few loads in flight)
         fused = fuse_ok && aam == 0 &&
@@ -1222,8 +1223,13 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     auto enqueue_set = [&](hipStream_t es) -> hipError_t {
         hipError_t e = launch_transition(tr, is64, es);
         if (e != hipSuccess) return e;
-        if ((e = launch_qinit(cb, is64, es)) != hipSuccess) return e;
-        if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
+        if (fused) {
+            // first iteration of a group: q from ext in one pass over the slabs
+            if ((e = launch_dcm(cb, ma, is64, es, 1)) != hipSuccess) return e;
+        } else {
+            if ((e = launch_qinit(cb, is64, es)) != hipSuccess) return e;
+            if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
+        }
         for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
             sw.diag = d;
             const bool timed = profile && nsweeps++ % pevery == 0;
