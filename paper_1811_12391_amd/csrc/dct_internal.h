@@ -164,6 +164,25 @@ __device__ inline void bst(rsrc_t r, unsigned off, double v)
     typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) u64v;
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, off, 0, 0);
 }
+// The same with a wave-uniform byte offset soff added (scalar operand).
+template <typename T> __device__ inline T bld_s(rsrc_t r, unsigned off, unsigned soff);
+template <> __device__ inline float bld_s<float>(rsrc_t r, unsigned off, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+template <> __device__ inline double bld_s<double>(rsrc_t r, unsigned off, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+__device__ inline void bst_s(rsrc_t r, unsigned off, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 0);
+}
+__device__ inline void bst_s(rsrc_t r, unsigned off, unsigned soff, double v)
+{
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) u64v;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, off, soff, 0);
+}
 
 
 // Wait until this wave's own earlier memory operations (stores, atomics) have

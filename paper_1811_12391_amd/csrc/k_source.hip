@@ -771,35 +771,44 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
     const T *ext = (const T *)a.ext + (long)b * Nm * C;
     const int tile_n = 16 * nx;
+    // ext and phi of this source and group through buffer descriptors: the
+    // voxel's byte offset per lane, the moment's (lm C sizeof(T), below 2^31
+    // by a host check) as a scalar
+    const rsrc_t rex = mk_rsrc(wave_ptr(ext), (long)Nm * C * (long)sizeof(T));
+    const rsrc_t rph = mk_rsrc(wave_ptr(phib), (long)Nm * C * (long)sizeof(T));
+    const unsigned cst = (unsigned)(C * (long)sizeof(T));
     // first iteration: the source is the group source ext (plus the
     // within-group scatter of the moments a warm start begins from), laid
     // into the tile as k_qinit lays it out
     for (int idx = threadIdx.x; first && idx < tile_n; idx += blockDim.x) {
         const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
         if (jy >= ny) continue;
-        const long v = i + (long)nx * (jy + (long)ny * k);
+        const int v = i + nx * (jy + ny * k);
+        const unsigned v4 = (unsigned)v * (unsigned)sizeof(T);
         const double rh = a.rho[v];
         const int mt = a.mat[v];
         for (int lm = 0; lm < Nm; ++lm) {
             T *tp = &tile[lm * LMS + jl * pitch + i];
+            const T ex = bld_s<T>(rex, v4, lm * cst);
             if (a.warm) {
                 const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
-                *tp = (T)((double)ext[(long)lm * C + v] + sc * (double)phib[(long)lm * C + v]);
+                *tp = (T)((double)ex + sc * (double)bld_s<T>(rph, v4, lm * cst));
             } else {
-                *tp = ext[(long)lm * C + v];
+                *tp = ex;
             }
         }
     }
     for (int idx = threadIdx.x; !first && idx < tile_n; idx += blockDim.x) {
         const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
         if (jy >= ny) continue;
-        const long v = i + (long)nx * (jy + (long)ny * k);
+        const int v = i + nx * (jy + ny * k);
+        const unsigned v4 = (unsigned)v * (unsigned)sizeof(T);
         const double rh = a.rho[v];
         const int mt = a.mat[v];
-        const T po = phib[v];
+        const T po = bld_s<T>(rph, v4, 0);
         T ev[16 * NRB];
 #pragma unroll
-        for (int lm = 0; lm < 16 * NRB; ++lm) ev[lm] = ext[(long)min(lm, Nm - 1) * C + v];
+        for (int lm = 0; lm < 16 * NRB; ++lm) ev[lm] = bld_s<T>(rex, v4, min(lm, Nm - 1) * cst);
 #pragma unroll
         for (int lm = 0; lm < 16 * NRB; ++lm) {
             if (lm >= Nm) continue;
@@ -811,7 +820,7 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
                 dmax = (dn > dmax || dn != dn) ? dn : dmax;
                 fmax_ = (an > fmax_ || an != an) ? an : fmax_;
             }
-            phib[(long)lm * C + v] = pn;
+            bst_s(rph, v4, lm * cst, pn);
             const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
             *tp = (T)((double)ev[lm] + sc * (double)pn);
         }

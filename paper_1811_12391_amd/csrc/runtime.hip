@@ -1202,7 +1202,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         const size_t lds = dcm_lds_bytes(cb, ma, is64) + 1024;
         const bool fuse_ok = mode <= 1 && lds <= ctx->lds_max && nslab <= 32L * DCT_MAXNM &&
                              std::max(pl.Nc[0], pl.Nc[1]) <= 48 &&   // one round of psi loads per class
-                             (size_t)N * C * ts < ((size_t)1 << 31);  // 32-bit offsets of one source's q / psi
+                             (size_t)std::max(N, Nm) * C * ts < ((size_t)1 << 31);   // 32-bit offsets of one
+                                                                                      // source's q, psi, ext, phi
         // by default: enough slabs to fill the GPU and two workgroups per CU
         // (one workgroup of 8 waves per CU leaves too few loads in flight)
         fused = fuse_ok && aam == 0 &&
