@@ -503,7 +503,10 @@ hipError_t launch_aa(const AAArgs &a, int is_f64, hipStream_t s);
 // D map + combine + M map of one iteration in one kernel (forward FP64 / FP32 solves)
 // first = 1: only the sources at the first iteration of a group, whose q the
 // kernel forms from ext alone (the work of k_qinit and the M map)
-hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s, int first = 0);
+// max_wg > 0: at most that many (persistent) workgroups, each taking several
+// slabs in turn
+hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s, int first = 0,
+                      int max_wg = 0);
 size_t dcm_lds_bytes(const CombArgs &a, const MapArgs &m, int is_f64);   // Q = ext in the class layouts after a transition
 hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f64, 1 f32, 2 bf16
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);

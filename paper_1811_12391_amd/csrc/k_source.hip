@@ -592,10 +592,11 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
 
 // Fused direction->moment map, combine and moment->direction map of one
 // source iteration (eq. 2 with the Legendre-expanded scattering kernel as
-// M Sigma D; eq. 3 is row 0 of D).  One workgroup per slab (z layer k, 16 y
-// rows, all x) of one right-hand side.  A slab is closed under both class
-// rotations, so everything between reading psi and writing the next q stays
-// in LDS:
+// M Sigma D; eq. 3 is row 0 of D).  The work item is a slab (z layer k, 16 y
+// rows, all x) of one right-hand side; persistent workgroups (as many as the
+// device holds at once) take the items in turn, loading the map tables once.
+// A slab is closed under both class rotations, so everything between reading
+// psi and writing the next q stays in LDS:
 //   1. the D map of each class on the matrix cores, its moments scattered
 //      into a natural-layout tile (class A stores, class B adds);
 //   2. combine: the new moments phi (stored), the change of phi_00 and the
@@ -603,9 +604,11 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a)
 //   3. the M map of each class from the tile; q stored for the next sweep.
 // The class partials and Q never reach HBM.  Each step does the arithmetic
 // of k_dmap, k_combine and k_mmap in the same order, so the results are the
-// same bit for bit.  The last workgroup of the right-hand side applies the
-// stopping rule; when the group stops, the q written here is replaced after
-// the transition (the M map runs for the first iteration of a group).
+// same bit for bit.  The last slab of the right-hand side to finish applies
+// the stopping rule; when the group stops, the q written here is replaced
+// after the transition by the FIRST form of the kernel, which for the sources
+// starting a group lays Q = ext (plus a warm start's self-scatter) into the
+// tile and runs only step 3.
 template <typename T, int NRB, int KC, bool FIRST>
 __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
 {
@@ -616,27 +619,10 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     __shared__ double ssg[DCT_MAXMAT * (DCT_MAXL + 1)];
     const int nx = a.geo.nx, ny = a.geo.ny;
     const int nslj = (ny + 15) >> 4;
-    // workgroup -> (right-hand side, slab).  Two slabs 16 rows apart share the
-    // 128-byte lines of psi (64 bytes each per row and direction in FP32), so
-    // they are paired on one XCD: workgroups h and h + 8 (same XCD, dispatched
-    // together) take slabs j and j + 1 of the same layer
-    const unsigned nsl = gridDim.x, lin = blockIdx.x + nsl * blockIdx.y;
-    unsigned W = lin;
-    if ((nslj & 1) == 0 && ((nsl * gridDim.y) & 15) == 0) {
-        const unsigned xcd = lin & 7, slot = lin >> 3;
-        W = 2 * ((slot >> 1) * 8 + xcd) + (slot & 1);
-    }
-    const int b = __builtin_amdgcn_readfirstlane((int)(W / nsl));
-    const int slab = __builtin_amdgcn_readfirstlane((int)(W - (unsigned)b * nsl));
-    RhsState *st = a.state + b;
-    if (st->finished) return;
-    // first iteration of a group: only the sources that start one
-    if (first && (st->pending || st->it != 0)) return;
-    const int gseq = __builtin_amdgcn_readfirstlane(st->g);   // wave-uniform: the buffer descriptors below stay scalar
-    const int g = __builtin_amdgcn_readfirstlane(eff_group(gseq, a.G, a.reverse));
+    const unsigned nsl = (unsigned)(a.geo.nz * nslj);          // slabs of one right-hand side
+    const unsigned NW = nsl * (unsigned)a.B;
     const long C = a.geo.C;
     const int G = a.G, Nm = a.Nm, L = a.L, N = m.N;
-    const int k = slab / nslj, j0 = (slab % nslj) * 16;
     const int pitch = (nx | 1) + 1;
     // moment stride of the tile: 16 rows plus 4 words, so that the 4 lane
     // groups of an MFMA output (moments 4 apart) fall in different banks
@@ -664,237 +650,268 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     // layout goes through dir_elem
     const bool fast = m.chainK <= 1;
     const int Nc0 = m.Nc[0], Nc1 = m.Nc[1];
-    if ((int)threadIdx.x < a.M * (L + 1)) {
-        const int mm = threadIdx.x / (L + 1), ll = threadIdx.x - mm * (L + 1);
-        ssg[threadIdx.x] = a.ss[(((long)mm * (L + 1) + ll) * G + g) * G + g];
-    }
-    __syncthreads();
-    const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
-    const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-    const int jj = j0 + col;                                  // y row of this lane's column
-    const bool jok = jj < ny;
-    const int jc = jok ? jj : ny - 1;
-    const int jm = jc % nx;
-    // ---- 1. D map of each class into the natural tile.  A wave takes two
-    // rows at a time and loads the psi operands of its next pair (the first
-    // pair of class B after the last of class A) before the matrix-core work
-    // of the current one, so two pairs of loads are in flight.
-    const T *psi = (const T *)m.psi + ((long)b * m.psi_bs + (long)g * m.psi_gs) * C;
-    const rsrc_t rps = mk_rsrc(wave_ptr(psi), (long)N * C * (long)sizeof(T));
-    T bA[2][KC], bB[2][KC];
-    auto load_pair = [&](int c, int r0, T (&bv)[2][KC]) __attribute__((always_inline)) {
-        const int Nc = c == 0 ? Nc0 : Nc1;
-        if (fast) {
-            const unsigned *co = cdo + c * N;
-            unsigned o[KC];
-#pragma unroll
-            for (int u = 0; u < KC; ++u) o[u] = co[min(4 * u + kr, Nc - 1)];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = min(r0 + h * nwv, nx - 1);
-                const unsigned p4 = (unsigned)((((long)k * nx + r) * ny + jc) * (long)sizeof(T));
-#pragma unroll
-                for (int u = 0; u < KC; ++u) bv[h][u] = bld<T>(rps, o[u] + p4);
-            }
-            return;
+    // persistent workgroups (the tables above are loaded once): workgroup h
+    // takes work items h, h + gridDim.x, ...; item -> (right-hand side, slab).
+    // Two slabs 16 rows apart share the 128-byte lines of psi (64 bytes each
+    // per row and direction in FP32), so they are paired on one XCD: the items
+    // of workgroups h and h + 8 in the same round (same XCD, running together)
+    // are slabs j and j + 1 of the same layer
+    const bool pair = (nslj & 1) == 0 && (NW & 15) == 0 && (gridDim.x & 15) == 0;
+    for (unsigned lin = blockIdx.x; lin < NW; lin += gridDim.x) {
+        // the lane indices pass through an opaque zero, so that the per-lane
+        // address arithmetic of the item is formed inside the loop instead of
+        // being hoisted out of it and held in registers across items
+        int lz;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(lz));
+        const int tid = (int)threadIdx.x + lz;
+        const int l = tid & 63, col = l & 15, kr = l >> 4;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nwv = blockDim.x >> 6;
+        unsigned W = lin;
+        if (pair) {
+            const unsigned xcd = lin & 7, slot = lin >> 3;
+            W = 2 * ((slot >> 1) * 8 + xcd) + (slot & 1);
         }
-        const int *cd = cds + c * N;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = min(r0 + h * nwv, nx - 1);
-            const long p = ((long)k * nx + r) * ny + jc;
-            const CellKJI cc{k, jc, c == 0 ? (r - jm + nx) % nx : (r + jm) % nx};
-#pragma unroll
-            for (int u = 0; u < KC; ++u) bv[h][u] = psi[dir_elem(m, c, cd[min(4 * u + kr, Nc - 1)], p, cc)];
-        }
-    };
-    bool have = false;                                        // bA holds the operands of the pair at hand
-    for (int c = 0; c < (first ? 0 : 2); ++c) {
-        const int Nc = c == 0 ? Nc0 : Nc1;
-        if (!have && wv < nx) {
-            load_pair(c, wv, bA);
-            have = true;
-        }
-        for (int r0 = wv; r0 < nx; r0 += 2 * nwv) {
-            // operands of the next pair: this class's, or class B's first
-            int rn = r0 + 2 * nwv, cn = c;
-            if (rn >= nx && c == 0) {
-                rn = wv;
-                cn = 1;
-            }
-            const bool next = rn < nx;
-            if (next) load_pair(cn, rn, bB);
-            A4 acc[2][NRB];
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int rb = 0; rb < NRB; ++rb) acc[h][rb] = A4{0, 0, 0, 0};
-#pragma unroll
-            for (int u = 0; u < KC; ++u)
-                if (4 * u < Nc) {
-#pragma unroll
-                    for (int rb = 0; rb < NRB; ++rb) {
-                        const T av = Dt[(c * NmP + rb * 16 + col) * DST + 4 * u + kr];
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) acc[h][rb] = mfma_k4(av, bA[h][u], acc[h][rb]);
-                    }
-                }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = r0 + h * nwv;
-                if (jok && r < nx) {
-                    const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;   // natural x of (r, j)
-#pragma unroll
-                    for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int lm = rb * 16 + out_row<T>(kr, e);
-                            if (lm < Nm) {
-                                T *tp = &tile[lm * LMS + col * pitch + i];
-                                *tp = c == 0 ? acc[h][rb][e] : *tp + acc[h][rb][e];
-                            }
-                        }
-                }
-            }
-            have = next;
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int u = 0; u < KC; ++u) bA[h][u] = bB[h][u];
+        const int b = __builtin_amdgcn_readfirstlane((int)(W / nsl));
+        const int slab = __builtin_amdgcn_readfirstlane((int)(W - (unsigned)b * nsl));
+        RhsState *st = a.state + b;
+        if (st->finished) continue;
+        // first iteration of a group: only the sources that start one
+        if (first && (st->pending || st->it != 0)) continue;
+        const int gseq = __builtin_amdgcn_readfirstlane(st->g);   // wave-uniform: the buffer descriptors below stay scalar
+        const int g = __builtin_amdgcn_readfirstlane(eff_group(gseq, a.G, a.reverse));
+        const int k = slab / nslj, j0 = (slab % nslj) * 16;
+        if ((int)threadIdx.x < a.M * (L + 1)) {
+            const int mm = threadIdx.x / (L + 1), ll = threadIdx.x - mm * (L + 1);
+            ssg[threadIdx.x] = a.ss[(((long)mm * (L + 1) + ll) * G + g) * G + g];
         }
         __syncthreads();
-    }
-    // ---- 2. combine in natural order: a thread takes one voxel of the slab at
-    // a time (material, density and the old phi_00 read once) and all its
-    // moments, with the group source of every moment requested up front
-    double dmax = 0.0, fmax_ = 0.0;
-    T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
-    const T *ext = (const T *)a.ext + (long)b * Nm * C;
-    const int tile_n = 16 * nx;
-    // ext and phi of this source and group through buffer descriptors: the
-    // voxel's byte offset per lane, the moment's (lm C sizeof(T), below 2^31
-    // by a host check) as a scalar
-    const rsrc_t rex = mk_rsrc(wave_ptr(ext), (long)Nm * C * (long)sizeof(T));
-    const rsrc_t rph = mk_rsrc(wave_ptr(phib), (long)Nm * C * (long)sizeof(T));
-    const unsigned cst = (unsigned)(C * (long)sizeof(T));
-    // first iteration: the source is the group source ext (plus the
-    // within-group scatter of the moments a warm start begins from), laid
-    // into the tile as k_qinit lays it out
-    for (int idx = threadIdx.x; first && idx < tile_n; idx += blockDim.x) {
-        const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
-        if (jy >= ny) continue;
-        const int v = i + nx * (jy + ny * k);
-        const unsigned v4 = (unsigned)v * (unsigned)sizeof(T);
-        const double rh = a.rho[v];
-        const int mt = a.mat[v];
-        for (int lm = 0; lm < Nm; ++lm) {
-            T *tp = &tile[lm * LMS + jl * pitch + i];
-            const T ex = bld_s<T>(rex, v4, lm * cst);
-            if (a.warm) {
-                const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
-                *tp = (T)((double)ex + sc * (double)bld_s<T>(rph, v4, lm * cst));
-            } else {
-                *tp = ex;
-            }
-        }
-    }
-    for (int idx = threadIdx.x; !first && idx < tile_n; idx += blockDim.x) {
-        const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
-        if (jy >= ny) continue;
-        const int v = i + nx * (jy + ny * k);
-        const unsigned v4 = (unsigned)v * (unsigned)sizeof(T);
-        const double rh = a.rho[v];
-        const int mt = a.mat[v];
-        const T po = bld_s<T>(rph, v4, 0);
-        T ev[16 * NRB];
-#pragma unroll
-        for (int lm = 0; lm < 16 * NRB; ++lm) ev[lm] = bld_s<T>(rex, v4, min(lm, Nm - 1) * cst);
-#pragma unroll
-        for (int lm = 0; lm < 16 * NRB; ++lm) {
-            if (lm >= Nm) continue;
-            T *tp = &tile[lm * LMS + jl * pitch + i];
-            const T pn = *tp;
-            if (lm == 0) {
-                const double dn = fabs((double)pn - (double)po);
-                const double an = fabs((double)pn);
-                dmax = (dn > dmax || dn != dn) ? dn : dmax;
-                fmax_ = (an > fmax_ || an != an) ? an : fmax_;
-            }
-            bst_s(rph, v4, lm * cst, pn);
-            const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
-            *tp = (T)((double)ev[lm] + sc * (double)pn);
-        }
-    }
-    __syncthreads();
-    // ---- 3. M map of each class from the tile
-    T *q = (T *)m.q + (long)b * N * C;
-    const int NS = (Nm + 3) / 4;                              // K-steps of 4 moments
-    if (fast) {
-        // q stored through a buffer descriptor: every lane stores, rows past
-        // the class's directions or the grid take an out-of-range offset
-        const rsrc_t rqq = mk_rsrc(wave_ptr(q), (long)N * C * (long)sizeof(T));
-        for (int c = 0; c < 2; ++c) {
+        const int jj = j0 + col;                                  // y row of this lane's column
+        const bool jok = jj < ny;
+        const int jc = jok ? jj : ny - 1;
+        const int jm = jc % nx;
+        // ---- 1. D map of each class into the natural tile.  A wave takes two
+        // rows at a time and loads the psi operands of its next pair (the first
+        // pair of class B after the last of class A) before the matrix-core work
+        // of the current one, so two pairs of loads are in flight.
+        const T *psi = (const T *)m.psi + ((long)b * m.psi_bs + (long)g * m.psi_gs) * C;
+        const rsrc_t rps = mk_rsrc(wave_ptr(psi), (long)N * C * (long)sizeof(T));
+        T bA[2][KC], bB[2][KC];
+        auto load_pair = [&](int c, int r0, T (&bv)[2][KC]) __attribute__((always_inline)) {
             const int Nc = c == 0 ? Nc0 : Nc1;
-            const unsigned *co = cdo + c * N;
-            unsigned qo[3][4];                                // up to 48 directions per class (host check)
-#pragma unroll
-            for (int rb = 0; rb < 3; ++rb)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int nl = rb * 16 + out_row<T>(kr, e);
-                    qo[rb][e] = (nl < Nc && jok) ? co[nl] : DCT_OOB;
+            if (fast) {
+                const unsigned *co = cdo + c * N;
+                unsigned o[KC];
+    #pragma unroll
+                for (int u = 0; u < KC; ++u) o[u] = co[min(4 * u + kr, Nc - 1)];
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = min(r0 + h * nwv, nx - 1);
+                    const unsigned p4 = (unsigned)((((long)k * nx + r) * ny + jc) * (long)sizeof(T));
+    #pragma unroll
+                    for (int u = 0; u < KC; ++u) bv[h][u] = bld<T>(rps, o[u] + p4);
                 }
+                return;
+            }
+            const int *cd = cds + c * N;
+    #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = min(r0 + h * nwv, nx - 1);
+                const long p = ((long)k * nx + r) * ny + jc;
+                const CellKJI cc{k, jc, c == 0 ? (r - jm + nx) % nx : (r + jm) % nx};
+    #pragma unroll
+                for (int u = 0; u < KC; ++u) bv[h][u] = psi[dir_elem(m, c, cd[min(4 * u + kr, Nc - 1)], p, cc)];
+            }
+        };
+        bool have = false;                                        // bA holds the operands of the pair at hand
+        for (int c = 0; c < (first ? 0 : 2); ++c) {
+            const int Nc = c == 0 ? Nc0 : Nc1;
+            if (!have && wv < nx) {
+                load_pair(c, wv, bA);
+                have = true;
+            }
+            for (int r0 = wv; r0 < nx; r0 += 2 * nwv) {
+                // operands of the next pair: this class's, or class B's first
+                int rn = r0 + 2 * nwv, cn = c;
+                if (rn >= nx && c == 0) {
+                    rn = wv;
+                    cn = 1;
+                }
+                const bool next = rn < nx;
+                if (next) load_pair(cn, rn, bB);
+                A4 acc[2][NRB];
+    #pragma unroll
+                for (int h = 0; h < 2; ++h)
+    #pragma unroll
+                    for (int rb = 0; rb < NRB; ++rb) acc[h][rb] = A4{0, 0, 0, 0};
+    #pragma unroll
+                for (int u = 0; u < KC; ++u)
+                    if (4 * u < Nc) {
+    #pragma unroll
+                        for (int rb = 0; rb < NRB; ++rb) {
+                            const T av = Dt[(c * NmP + rb * 16 + col) * DST + 4 * u + kr];
+    #pragma unroll
+                            for (int h = 0; h < 2; ++h) acc[h][rb] = mfma_k4(av, bA[h][u], acc[h][rb]);
+                        }
+                    }
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = r0 + h * nwv;
+                    if (jok && r < nx) {
+                        const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;   // natural x of (r, j)
+    #pragma unroll
+                        for (int rb = 0; rb < NRB; ++rb)
+    #pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int lm = rb * 16 + out_row<T>(kr, e);
+                                if (lm < Nm) {
+                                    T *tp = &tile[lm * LMS + col * pitch + i];
+                                    *tp = c == 0 ? acc[h][rb][e] : *tp + acc[h][rb][e];
+                                }
+                            }
+                    }
+                }
+                have = next;
+    #pragma unroll
+                for (int h = 0; h < 2; ++h)
+    #pragma unroll
+                    for (int u = 0; u < KC; ++u) bA[h][u] = bB[h][u];
+            }
+            __syncthreads();
+        }
+        // ---- 2. combine in natural order: a thread takes one voxel of the slab at
+        // a time (material, density and the old phi_00 read once) and all its
+        // moments, with the group source of every moment requested up front
+        double dmax = 0.0, fmax_ = 0.0;
+        T *phib = (T *)a.phi_all + ((long)b * G + g) * Nm * C;
+        const T *ext = (const T *)a.ext + (long)b * Nm * C;
+        const int tile_n = 16 * nx;
+        // ext and phi of this source and group through buffer descriptors: the
+        // voxel's byte offset per lane, the moment's (lm C sizeof(T), below 2^31
+        // by a host check) as a scalar
+        const rsrc_t rex = mk_rsrc(wave_ptr(ext), (long)Nm * C * (long)sizeof(T));
+        const rsrc_t rph = mk_rsrc(wave_ptr(phib), (long)Nm * C * (long)sizeof(T));
+        const unsigned cst = (unsigned)(C * (long)sizeof(T));
+        // first iteration: the source is the group source ext (plus the
+        // within-group scatter of the moments a warm start begins from), laid
+        // into the tile as k_qinit lays it out
+        for (int idx = threadIdx.x; first && idx < tile_n; idx += blockDim.x) {
+            const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
+            if (jy >= ny) continue;
+            const int v = i + nx * (jy + ny * k);
+            const unsigned v4 = (unsigned)v * (unsigned)sizeof(T);
+            const double rh = a.rho[v];
+            const int mt = a.mat[v];
+            for (int lm = 0; lm < Nm; ++lm) {
+                T *tp = &tile[lm * LMS + jl * pitch + i];
+                const T ex = bld_s<T>(rex, v4, lm * cst);
+                if (a.warm) {
+                    const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
+                    *tp = (T)((double)ex + sc * (double)bld_s<T>(rph, v4, lm * cst));
+                } else {
+                    *tp = ex;
+                }
+            }
+        }
+        for (int idx = threadIdx.x; !first && idx < tile_n; idx += blockDim.x) {
+            const int jl = idx / nx, i = idx - jl * nx, jy = j0 + jl;
+            if (jy >= ny) continue;
+            const int v = i + nx * (jy + ny * k);
+            const unsigned v4 = (unsigned)v * (unsigned)sizeof(T);
+            const double rh = a.rho[v];
+            const int mt = a.mat[v];
+            const T po = bld_s<T>(rph, v4, 0);
+            T ev[16 * NRB];
+    #pragma unroll
+            for (int lm = 0; lm < 16 * NRB; ++lm) ev[lm] = bld_s<T>(rex, v4, min(lm, Nm - 1) * cst);
+    #pragma unroll
+            for (int lm = 0; lm < 16 * NRB; ++lm) {
+                if (lm >= Nm) continue;
+                T *tp = &tile[lm * LMS + jl * pitch + i];
+                const T pn = *tp;
+                if (lm == 0) {
+                    const double dn = fabs((double)pn - (double)po);
+                    const double an = fabs((double)pn);
+                    dmax = (dn > dmax || dn != dn) ? dn : dmax;
+                    fmax_ = (an > fmax_ || an != an) ? an : fmax_;
+                }
+                bst_s(rph, v4, lm * cst, pn);
+                const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
+                *tp = (T)((double)ev[lm] + sc * (double)pn);
+            }
+        }
+        __syncthreads();
+        // ---- 3. M map of each class from the tile
+        T *q = (T *)m.q + (long)b * N * C;
+        const int NS = (Nm + 3) / 4;                              // K-steps of 4 moments
+        if (fast) {
+            // q stored through a buffer descriptor: every lane stores, rows past
+            // the class's directions or the grid take an out-of-range offset
+            const rsrc_t rqq = mk_rsrc(wave_ptr(q), (long)N * C * (long)sizeof(T));
+            for (int c = 0; c < 2; ++c) {
+                const int Nc = c == 0 ? Nc0 : Nc1;
+                const unsigned *co = cdo + c * N;
+                unsigned qo[3][4];                                // up to 48 directions per class (host check)
+    #pragma unroll
+                for (int rb = 0; rb < 3; ++rb)
+    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int nl = rb * 16 + out_row<T>(kr, e);
+                        qo[rb][e] = (nl < Nc && jok) ? co[nl] : DCT_OOB;
+                    }
+                for (int r = wv; r < nx; r += nwv) {
+                    const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;
+                    const unsigned p4 = (unsigned)((((long)k * nx + r) * ny + jc) * (long)sizeof(T));
+                    T bq[4 * NRB];
+    #pragma unroll
+                    for (int s = 0; s < 4 * NRB; ++s) bq[s] = tile[min(4 * s + kr, Nm - 1) * LMS + col * pitch + i];
+    #pragma unroll
+                    for (int rb = 0; rb < 3; ++rb) {
+                        if (rb * 16 >= Nc) break;
+                        A4 acc = {0, 0, 0, 0};
+    #pragma unroll
+                        for (int s = 0; s < 4 * NRB; ++s)
+                            if (s < NS) acc = mfma_k4(Mt[(c * NcP + rb * 16 + col) * MST + 4 * s + kr], bq[s], acc);
+    #pragma unroll
+                        for (int e = 0; e < 4; ++e) bst(rqq, qo[rb][e] == DCT_OOB ? DCT_OOB : qo[rb][e] + p4, acc[e]);
+                    }
+                }
+            }
+        }
+        for (int c = 0; c < (fast ? 0 : 2); ++c) {
+            const int Nc = c == 0 ? Nc0 : Nc1;
+            const int *cd = cds + c * N;
             for (int r = wv; r < nx; r += nwv) {
+                const long p = ((long)k * nx + r) * ny + jc;
                 const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;
-                const unsigned p4 = (unsigned)((((long)k * nx + r) * ny + jc) * (long)sizeof(T));
+                const CellKJI cc{k, jc, i};
                 T bq[4 * NRB];
-#pragma unroll
+    #pragma unroll
                 for (int s = 0; s < 4 * NRB; ++s) bq[s] = tile[min(4 * s + kr, Nm - 1) * LMS + col * pitch + i];
-#pragma unroll
-                for (int rb = 0; rb < 3; ++rb) {
-                    if (rb * 16 >= Nc) break;
+                for (int rb = 0; rb * 16 < Nc; ++rb) {
                     A4 acc = {0, 0, 0, 0};
-#pragma unroll
+    #pragma unroll
                     for (int s = 0; s < 4 * NRB; ++s)
                         if (s < NS) acc = mfma_k4(Mt[(c * NcP + rb * 16 + col) * MST + 4 * s + kr], bq[s], acc);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) bst(rqq, qo[rb][e] == DCT_OOB ? DCT_OOB : qo[rb][e] + p4, acc[e]);
+    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int nl = rb * 16 + out_row<T>(kr, e);
+                        if (nl < Nc && jok) q[dir_elem(m, c, cd[nl], p, cc)] = acc[e];
+                    }
                 }
             }
         }
-    }
-    for (int c = 0; c < (fast ? 0 : 2); ++c) {
-        const int Nc = c == 0 ? Nc0 : Nc1;
-        const int *cd = cds + c * N;
-        for (int r = wv; r < nx; r += nwv) {
-            const long p = ((long)k * nx + r) * ny + jc;
-            const int i = c == 0 ? (r - jm + nx) % nx : (r + jm) % nx;
-            const CellKJI cc{k, jc, i};
-            T bq[4 * NRB];
-#pragma unroll
-            for (int s = 0; s < 4 * NRB; ++s) bq[s] = tile[min(4 * s + kr, Nm - 1) * LMS + col * pitch + i];
-            for (int rb = 0; rb * 16 < Nc; ++rb) {
-                A4 acc = {0, 0, 0, 0};
-#pragma unroll
-                for (int s = 0; s < 4 * NRB; ++s)
-                    if (s < NS) acc = mfma_k4(Mt[(c * NcP + rb * 16 + col) * MST + 4 * s + kr], bq[s], acc);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int nl = rb * 16 + out_row<T>(kr, e);
-                    if (nl < Nc && jok) q[dir_elem(m, c, cd[nl], p, cc)] = acc[e];
-                }
+        // ---- 4. change of phi_00 and the end of the iteration
+        if (!first) {
+            const double dm = block_max(dmax, red);
+            const double fm = block_max(fmax_, red);
+            if (threadIdx.x == 0) {
+                atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
+                atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
+                if (last_block(a.cnt_mom + (long)b * DCT_MAXNM * 32, &st->cnt_combine, (unsigned)slab, nsl))
+                    close_iteration(a, st, b, gseq, g);
             }
         }
-    }
-    // ---- 4. change of phi_00 and the end of the iteration
-    if (first) return;
-    const double dm = block_max(dmax, red);
-    const double fm = block_max(fmax_, red);
-    if (threadIdx.x == 0) {
-        atomicMax(&st->eps_num, (unsigned long long)__double_as_longlong(dm));
-        atomicMax(&st->eps_den, (unsigned long long)__double_as_longlong(fm));
-        if (last_block(a.cnt_mom + (long)b * DCT_MAXNM * 32, &st->cnt_combine, (unsigned)slab, nsl))
-            close_iteration(a, st, b, gseq, g);
+        __syncthreads();   // the tile and the scatter table are refilled for the next item
     }
 }
 
@@ -906,10 +923,11 @@ size_t dcm_lds_bytes(const CombArgs &a, const MapArgs &m, int is_f64)
            (size_t)2 * m.NcP * (m.NmP + 1) * ts + (size_t)4 * m.N * 4;
 }
 
-hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s, int first)
+hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s, int first, int max_wg)
 {
     const int nslj = (a.geo.ny + 15) >> 4;
-    const dim3 grid((unsigned)(a.geo.nz * nslj), a.B);
+    const long nw = (long)a.geo.nz * nslj * a.B;
+    const dim3 grid((unsigned)(max_wg > 0 && max_wg < nw ? max_wg : nw));
     const size_t shm = dcm_lds_bytes(a, m, is_f64);
     const int nrb = (a.Nm + 15) / 16;
 #define DCT_DCM(T, R, K, F)                                                                               \

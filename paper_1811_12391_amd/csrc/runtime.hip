@@ -125,6 +125,7 @@ struct dct_ctx {
         void *phi;
     } warm = {false, 0, 0, 0, 0, 0, nullptr};
     size_t lds_max = 65536;            // LDS bytes one workgroup may allocate on the device
+    int ncu = 256;                     // compute units of the device
     bool pipe_clean = false;           // pipelined-block face buffers hold only the empty marker
     unsigned sweep_seq = 0;            // counts sweep launches (part of the pipelined blocks' launch tag)
     hipStream_t own_stream = nullptr;  // capture stream when the context's stream is the null stream
@@ -214,6 +215,9 @@ int dct_create(dct_ctx **out, int device, void *stream)
             int lds = 0;
             if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
                 ctx->lds_max = (size_t)lds;
+            int ncu = 0;
+            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+                ctx->ncu = ncu;
         }
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[0]);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[1]);
@@ -1197,6 +1201,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // (completion sub-counters); by default when there are enough slabs to
     // fill the GPU (one or two workgroups per CU at a time)
     bool fused = false;
+    int dcm_wg = 0;
     {
         const long nslab = (long)nz * ((ny + 15) / 16);
         const size_t lds = dcm_lds_bytes(cb, ma, is64) + 1024;
@@ -1209,6 +1214,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         fused = fuse_ok && aam == 0 &&
                 (o.fuse_maps > 0 || (o.fuse_maps == 0 && nslab * B >= 1024 && 2 * lds <= ctx->lds_max));
         ma.first_only = fused ? 1 : 0;
+        // persistent workgroups: as many as fit the device at once
+        dcm_wg = (2 * lds <= ctx->lds_max ? 2 : 1) * ctx->ncu;
     }
     ctx->last_fused = fused;
     ctx->last_warm = warm;
@@ -1226,7 +1233,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         if (e != hipSuccess) return e;
         if (fused) {
             // first iteration of a group: q from ext in one pass over the slabs
-            if ((e = launch_dcm(cb, ma, is64, es, 1)) != hipSuccess) return e;
+            if ((e = launch_dcm(cb, ma, is64, es, 1, dcm_wg)) != hipSuccess) return e;
         } else {
             if ((e = launch_qinit(cb, is64, es)) != hipSuccess) return e;
             if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
@@ -1258,7 +1265,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 if ((e = hipEventRecord(ctx->evpool_m[2 * nprof_m], es)) != hipSuccess) return e;
             }
-            if ((e = launch_dcm(cb, ma, is64, es)) != hipSuccess) return e;
+            if ((e = launch_dcm(cb, ma, is64, es, 0, dcm_wg)) != hipSuccess) return e;
             if (timed) {
                 if ((e = hipEventRecord(ctx->evpool_m[2 * nprof_m + 1], es)) != hipSuccess) return e;
                 ++nprof_m;
