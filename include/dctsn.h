@@ -125,9 +125,9 @@ typedef struct dct_opts {
                                  per (z layer, 16 y rows) slab, with the moments and the next
                                  source kept in LDS (DCT_FP64 / DCT_FP32 only; needs the slab
                                  tile, about 16 (L+1)^2 nx words, within the workgroup LDS);
-                                 -1: separate kernels; 0: fused when eligible, there are at
-                                 least 1024 slabs over all right-hand sides and two such
-                                 workgroups fit one CU's LDS. */
+                                 -1: separate kernels; 0: fused when eligible and there are
+                                 at least as many slabs over all right-hand sides as the
+                                 device has compute units. */
     int warm_start;           /* 1: every group starts its source iteration from the moments
                                  the previous solve on this context left (same right-hand
                                  sides, groups, P_N order, grid and precision; e.g. the next

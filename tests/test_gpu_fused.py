@@ -82,6 +82,27 @@ def test_fused_c2_grid_s8():
         assert np.array_equal(d, d0)
 
 
+def test_fused_c4_persistent_items():
+    """The 36-source axial scan, two iterations per group: 2,304 slabs over
+    the persistent workgroups (several each, paired on XCDs), the
+    first-iteration form at every group start; bitwise the separate kernels,
+    FP32 and FP64, and the default picks the fused kernel."""
+    prob = I.make_problem("c4")
+    fi = np.full(prob.G, 2, dtype=np.int32)
+    for prec in ("fp32", "fp64"):
+        _say(f"[fused] c4 {prec}")
+        d0, d = [], []
+        for fm, out in ((-1, d0), (0, d)):
+            s = dctsn.Solver(prob)
+            try:
+                st = s.solve(precision=prec, fixed_iters=fi, fuse_maps=fm, sweep_bk=16, sweep_sync=5)
+                out.append(s.dose())
+            finally:
+                s.close()
+        assert st.fused_maps == 1
+        assert np.array_equal(d[0], d0[0])
+
+
 def test_fused_matches_oracle():
     import oracle
 
