@@ -801,14 +801,22 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
             const unsigned v4 = (unsigned)v * (unsigned)sizeof(T);
             const double rh = a.rho[v];
             const int mt = a.mat[v];
-            for (int lm = 0; lm < Nm; ++lm) {
+            // every moment's loads issued before the first is used
+            T ev[16 * NRB], pv[16 * NRB];
+#pragma unroll
+            for (int lm = 0; lm < 16 * NRB; ++lm) {
+                ev[lm] = bld_s<T>(rex, v4, min(lm, Nm - 1) * cst);
+                pv[lm] = a.warm ? bld_s<T>(rph, v4, min(lm, Nm - 1) * cst) : (T)0;
+            }
+#pragma unroll
+            for (int lm = 0; lm < 16 * NRB; ++lm) {
+                if (lm >= Nm) continue;
                 T *tp = &tile[lm * LMS + jl * pitch + i];
-                const T ex = bld_s<T>(rex, v4, lm * cst);
                 if (a.warm) {
                     const double sc = rh * ssg[mt * (L + 1) + l_of(lm)];
-                    *tp = (T)((double)ex + sc * (double)bld_s<T>(rph, v4, lm * cst));
+                    *tp = (T)((double)ev[lm] + sc * (double)pv[lm]);
                 } else {
-                    *tp = ex;
+                    *tp = ev[lm];
                 }
             }
         }
