@@ -300,6 +300,14 @@ int dct_effective_dose(dct_ctx *ctx, int n, const double *energy_keV, const doub
 int dct_effective_dose_noalloc(dct_ctx *ctx, int n, const double *energy_keV, const double *factor,
                                const uint8_t *zero_material, double *out_dev, int summed);
 
+/* The response R = sum_b sum_v roi[v] dose_b(v) of the last solve (the
+ * collision-kerma dose of Sec. II-A summed over the right-hand sides, weighted
+ * by roi), reduced on the device in FP64 in a fixed order: the value whose
+ * gradient dct_adjoint computes.
+ *   roi[C] host weights (finite, else EINVAL); R[1] host output.
+ * ESTATE if there is no valid solve. */
+int dct_roi_dose(dct_ctx *ctx, const double *roi, double *R);
+
 /* Gradient of the response R = sum_b sum_v roi[v] dose_b(v) with respect to
  * every voxel density and every source group weight, by the adjoint of the
  * discretised solve at the converged state of the last dct_solve (which must

@@ -9,10 +9,12 @@ and reverse-direction sweeps, ray back-projection of the uncollided flux).
 The dose itself is Sec. II-A's collision-kerma tally; the gradient is an
 addition built on the same discrete equations.
 
-Only argument marshalling happens here: the forward solve and the adjoint run
-in the HIP library.  The adjoint needs the kept state of the forward solve, so
-the solver must not be re-solved or modified between forward and backward
-(the library reports DCT_ESTATE if it was).
+Only argument marshalling happens here: the forward solve, the response R
+(``dct_roi_dose``) and the adjoint run in the HIP library; the densities and
+weights enter through the library's host-buffer setters.  The adjoint needs
+the kept state of the forward solve, so the solver must not be re-solved or
+modified between forward and backward (the library reports DCT_ESTATE if it
+was).
 """
 from __future__ import annotations
 
@@ -28,10 +30,10 @@ class _RoiDose(torch.autograd.Function):
         solver.set_density(density.detach().cpu().numpy().astype(np.float64))
         solver.set_group_weights(group_w.detach().cpu().numpy().astype(np.float64))
         solver.solve(keep_adjoint=True, **fwd_kw)
-        dose = solver.dose(summed=True)
         ctx.solver, ctx.roi, ctx.adj_kw = solver, np.asarray(roi, dtype=np.float64).reshape(-1), adj_kw
         ctx.dev = (density.device, group_w.device)
-        return torch.tensor(float(np.dot(ctx.roi, dose)), dtype=torch.float64)
+        R = dctsn.roi_dose(solver.h, solver.prob.phantom.C, ctx.roi)   # reduced in the library
+        return torch.tensor(R, dtype=torch.float64, device=density.device)
 
     @staticmethod
     def backward(ctx, gR):

@@ -512,6 +512,9 @@ hipError_t launch_mmap(const MapArgs &a, int mode, hipStream_t s);   // mode 0 f
 hipError_t launch_dmap(const MapArgs &a, int mode, hipStream_t s);
 hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq);
 hipError_t launch_dose(const DoseArgs &a, int is_f64, hipStream_t s);
+// sum_v w[v] x[v] (FP64, fixed order) into part[nb], nb = min(1024, ceil(n / 256));
+// part needs nb + 1 entries
+hipError_t launch_wdot(const double *w, const double *x, long n, double *part, hipStream_t s);
 hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t s);
 hipError_t launch_adj_ray(const AdjRayArgs &a, hipStream_t s);
 hipError_t launch_adj_init(long C, int G, int B, const uint8_t *mat, const double *kap, const double *roi,

@@ -10,6 +10,8 @@
 // optical depth is accumulated in FP64 as path length x density per material
 // (at most DCT_MAXMAT materials, kept in registers) and contracted with the
 // mass attenuation table at the end.
+#include <algorithm>
+
 #include "dct_internal.h"
 
 namespace dct {
@@ -331,6 +333,39 @@ hipError_t launch_dose(const DoseArgs &a, int is_f64, hipStream_t s)
     dim3 grid((unsigned)((a.C + 255) / 256));
     if (is_f64) hipLaunchKernelGGL(k_dose<double>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_dose<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Weighted sum R = sum_v w[v] x[v] in FP64, in a fixed order: each of the
+// (at most 1024) workgroups sums a grid-strided share and reduces it in the
+// workgroup; k_wsum then adds the partial sums in workgroup order.
+__global__ __launch_bounds__(256) void k_wdot(const double *w, const double *x, long n, double *part)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (long v = (long)blockIdx.x * 256 + threadIdx.x; v < n; v += (long)gridDim.x * 256) acc += w[v] * x[v];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_wsum(double *part, int nb)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) acc += part[q];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[nb] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_wdot(const double *w, const double *x, long n, double *part, hipStream_t s)
+{
+    const int nb = (int)std::min<long>(1024, std::max<long>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_wdot, dim3(nb), dim3(256), 0, s, w, x, n, part);
+    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(256), 0, s, part, nb);
     return hipGetLastError();
 }
 

@@ -1492,6 +1492,30 @@ extern "C" int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_
     return dose_common(ctx, dose, summed, phi_u, phi_c, true);
 }
 
+extern "C" int dct_roi_dose(dct_ctx *ctx, const double *roi, double *R)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!roi || !R) return fail(ctx, DCT_EINVAL, "roi_dose: NULL array");
+    if (!ctx->solved) return fail(ctx, DCT_ESTATE, "roi_dose: no valid solve since the last set_* call");
+    const long C = (long)ctx->nx * ctx->ny * ctx->nz;
+    if (!finite_all(roi, C)) return fail(ctx, DCT_EINVAL, "roi_dose: roi not finite");
+    HC(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    void *dd, *dr, *dp;
+    HC(dbuf(ctx, "r_dose", (size_t)C * 8, &dd));
+    HC(dbuf(ctx, "r_roi", (size_t)C * 8, &dr));
+    HC(dbuf(ctx, "r_part", (size_t)1025 * 8, &dp));
+    const int r = dose_common(ctx, (double *)dd, 1, nullptr, nullptr, true);
+    if (r != DCT_OK) return r;
+    HC(hipMemcpyAsync(dr, roi, (size_t)C * 8, hipMemcpyHostToDevice, s));
+    HC(launch_wdot((const double *)dr, (const double *)dd, C, (double *)dp, s));
+    const int nb = (int)std::min<long>(1024, std::max<long>(1, (C + 255) / 256));
+    HC(hipMemcpyAsync(R, (double *)dp + nb, 8, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    return DCT_OK;
+}
+
 // Checks of dct_effective_dose's table and its per-group factors: the table
 // at each group's mid energy, linear between points, the end value beyond
 // either end (Sec. III-A).

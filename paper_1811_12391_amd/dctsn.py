@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "DCT_OK", -1: "DCT_EINVAL", -2: "DCT_ESTATE", -3: "DCT_EDEVIC
 # every symbol include/dctsn.h declares
 EXPORTS = ["dct_create", "dct_destroy", "dct_last_error", "dct_set_geometry", "dct_set_xs",
            "dct_set_quadrature", "dct_set_source", "dct_set_volume_source", "dct_solve", "dct_dose",
-           "dct_dose_dev", "dct_effective_dose", "dct_effective_dose_noalloc", "dct_adjoint", "dct_moments"]
+           "dct_dose_dev", "dct_effective_dose", "dct_effective_dose_noalloc", "dct_adjoint", "dct_moments",
+           "dct_roi_dose"]
 
 
 class DctError(RuntimeError):
@@ -81,6 +82,7 @@ def lib():
         L.dct_solve.argtypes = [_vp, ct.POINTER(dct_opts), ct.POINTER(dct_stats)]
         L.dct_dose.argtypes = [_vp, _d, ct.c_int, _d, _d]
         L.dct_dose_dev.argtypes = [_vp, _vp, ct.c_int, _vp, _vp]
+        L.dct_roi_dose.argtypes = [_vp, _d, _d]
         L.dct_adjoint.argtypes = [_vp, _d, ct.POINTER(dct_opts), _d, _d, _d, ct.POINTER(dct_stats)]
         L.dct_moments.argtypes = [_vp, _d]
         L.dct_effective_dose.argtypes = [_vp, ct.c_int, _d, _d, _u8, _d, ct.c_int]
@@ -262,6 +264,16 @@ def effective_dose_noalloc(h, energy_keV, factor, out_t, *, zero_material=None, 
 def dose_dev(h, dose_t, summed=False, phi_u_t=None, phi_c_t=None):
     """Write results into device tensors (float64 torch tensors on the context's device)."""
     return _chk(h, lib().dct_dose_dev(h, _dev_ptr(dose_t), int(summed), _dev_ptr(phi_u_t), _dev_ptr(phi_c_t)))
+
+
+def roi_dose(h, C, roi) -> float:
+    """R = sum_b sum_v roi[v] dose_b(v) of the last solve, reduced on the device."""
+    roi = _f64(roi).reshape(-1)
+    if roi.size != C:
+        raise ValueError(f"roi has {roi.size} entries, expected {C}")
+    R = np.zeros(1)
+    _chk(h, lib().dct_roi_dose(h, _p(roi), _p(R)))
+    return float(R[0])
 
 
 @dataclass

@@ -185,6 +185,32 @@ def test_adjoint_needs_kept_solve():
         s.close()
 
 
+def test_roi_dose_matches_dose_and_adjoint():
+    """dct_roi_dose equals roi . summed dose (host) and the adjoint's R; it
+    needs a solve and a finite ROI."""
+    prob, roi, fi, fa, ref = _oracle_adjoint("ring2")
+    s = dctsn.Solver(prob)
+    try:
+        C = prob.phantom.C
+        with pytest.raises(dctsn.DctError) as e:
+            dctsn.roi_dose(s.h, C, roi)
+        assert e.value.code == dctsn.DCT_ESTATE
+        s.solve(precision="fp64", fixed_iters=fi, keep_adjoint=True)
+        R = dctsn.roi_dose(s.h, C, roi)
+        Rh = float(np.dot(roi, s.dose(summed=True)))
+        assert abs(R - Rh) <= 1e-13 * abs(Rh)
+        assert abs(R - ref.R) <= 1e-10 * abs(ref.R)
+        a = s.adjoint(roi, fixed_iters=fa)
+        assert abs(R - a.R) <= 1e-12 * abs(R)
+        bad = np.array(roi, dtype=np.float64)
+        bad[3] = np.nan
+        with pytest.raises(dctsn.DctError) as e:
+            dctsn.roi_dose(s.h, C, bad)
+        assert e.value.code == dctsn.DCT_EINVAL
+    finally:
+        s.close()
+
+
 def test_autograd_wrapper():
     """torch.autograd through roi_dose gives the adjoint gradients."""
     import torch
