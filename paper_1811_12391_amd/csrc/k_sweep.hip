@@ -1298,7 +1298,7 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
     if ((a.layers == 2 || a.layers == 4) && !multi && mode != 2 && a.ny <= 64 && a.nz <= 16) {
         const int nwv = (a.nz + a.layers - 1) / a.layers;
         const dim3 lgrid((unsigned)(a.B * a.N)), lblock(64 * nwv);
-#define DCT_LW(T, ZL, MD) hipLaunchKernelGGL((k_sweep_lw<T, ZL, 8, MD>), lgrid, lblock, 0, s, a)
+#define DCT_LW(T, ZL, MD) hipLaunchKernelGGL((k_sweep_lw<T, ZL, (ZL == 4 ? 4 : 8), MD>), lgrid, lblock, 0, s, a)
         if (is_f64) {
             if (a.layers == 4) { if (mode == 1) DCT_LW(double, 4, 1); else DCT_LW(double, 4, 0); }
             else { if (mode == 1) DCT_LW(double, 2, 1); else DCT_LW(double, 2, 0); }
