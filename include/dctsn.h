@@ -205,6 +205,17 @@ const char *dct_last_error(const dct_ctx *ctx);
 int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy, double dz,
                      const double *origin, const uint8_t *material, const double *density);
 
+/* New voxel densities (Sec. II-B: the density scales every macroscopic cross
+ * section) from a DEVICE buffer on the context's device, for callers whose
+ * densities already live there (a differentiable pipeline): density[C] FP64
+ * g/cm^3, C = nx ny nz of the last dct_set_geometry, whose grid and materials
+ * are kept.  The values are screened and copied on the context's stream; the
+ * call returns when the copy is done (the caller may then reuse the buffer),
+ * and it does not wait for work on other streams that writes the buffer.
+ * ESTATE without a geometry; EINVAL on a NULL pointer or a value that is not
+ * finite or is negative (the lowest such voxel is named). */
+int dct_set_density_dev(dct_ctx *ctx, const double *density);
+
 /* Multigroup cross sections per unit density (Sec. II-B / II-D: multigroup
  * library; eq. (2) with a Legendre expansion of the scattering kernel).
  *   G >= 1 groups, edges_keV[G+1] strictly descending (may be NULL);
@@ -319,11 +330,21 @@ int dct_roi_dose(dct_ctx *ctx, const double *roi, double *R);
  * built on the same discrete equations.)
  *   roi[C] host weights; opts: tol / max_iter / fixed_iters of the adjoint
  *   iterations (precision is that of the forward solve; NULL = tol 1e-6);
- *   outputs (host, caller-allocated, any may be NULL): R[1], d_density[C]
+ *   outputs (host, caller-allocated, any may be NULL): R[1] (the forward
+ *   solve's response, the value dct_roi_dose gives), d_density[C]
  *   (per g/cm^3), d_group_w[G].
- * ESTATE if there is no kept solve. */
+ * ESTATE if there is no kept solve; EINVAL if roi holds a non-finite value. */
 int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
                 double *d_group_w, dct_stats *stats);
+
+/* dct_adjoint with DEVICE buffers on the context's device: roi[C] input,
+ * d_density[C] and d_group_w[G] outputs (either may be NULL); R[1] and stats
+ * stay host.  The same R bit for bit and the same gradients up to the order
+ * of the FP64 atomic additions of the ray back-projection (which varies from
+ * run to run in both forms); the call returns when the outputs are written.  EINVAL if roi holds a value that is not finite (the lowest
+ * such voxel is named). */
+int dct_adjoint_dev(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
+                    double *d_group_w, dct_stats *stats);
 
 /* All collided flux moments of the last solve into a host buffer
  * phi[B][G][Nm][C] (B right-hand sides; FP64 whatever the precision). */

@@ -519,6 +519,11 @@ hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t 
 hipError_t launch_adj_ray(const AdjRayArgs &a, hipStream_t s);
 hipError_t launch_adj_init(long C, int G, int B, const uint8_t *mat, const double *kap, const double *roi,
                            double *pbu, hipStream_t s);
+// d_density[v] = dray[v] + sum_b drho[b][v]
+hipError_t launch_adj_gather(const double *drho, const double *dray, long C, int B, double *out, hipStream_t s);
+// lowest index of x[0, n) that is not finite (nonneg: or is negative) into *bad
+// (unchanged when every entry passes; the caller sets it to all ones first)
+hipError_t launch_screen(const double *x, long n, int nonneg, unsigned long long *bad, hipStream_t s);
 hipError_t launch_stage_consts(const StageConsts &c, double *dst_d, unsigned char *dst_b, hipStream_t s);
 hipError_t launch_moments_out(const void *phi_all, long n, double *out, int is_f64, hipStream_t s);
 

@@ -231,6 +231,42 @@ hipError_t launch_adj_init(long C, int G, int B, const uint8_t *mat, const doubl
     return hipGetLastError();
 }
 
+// Density gradient of the whole response: the ray back-projection's share
+// plus every right-hand side's share, added in that order (the order the
+// host-buffer form uses, so both give the same bits).
+__global__ __launch_bounds__(256) void k_adj_gather(const double *drho, const double *dray, long C, int B,
+                                                    double *out)
+{
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    if (v >= C) return;
+    double t = dray[v];
+    for (int b = 0; b < B; ++b) t += drho[(long)b * C + v];
+    out[v] = t;
+}
+
+hipError_t launch_adj_gather(const double *drho, const double *dray, long C, int B, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, s, drho, dray, C, B, out);
+    return hipGetLastError();
+}
+
+// Screening of a caller's device array: the lowest index whose value is not
+// finite (or, with nonneg, is negative) into *bad, which starts at all ones.
+__global__ __launch_bounds__(256) void k_screen(const double *x, long n, int nonneg, unsigned long long *bad)
+{
+    for (long v = (long)blockIdx.x * 256 + threadIdx.x; v < n; v += (long)gridDim.x * 256) {
+        const double t = x[v];
+        if (!__builtin_isfinite(t) || (nonneg && t < 0.0)) atomicMin(bad, (unsigned long long)v);
+    }
+}
+
+hipError_t launch_screen(const double *x, long n, int nonneg, unsigned long long *bad, hipStream_t s)
+{
+    const int nb = (int)std::min<long>(1024, std::max<long>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_screen, dim3(nb), dim3(256), 0, s, x, n, nonneg, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_ray(const AdjRayArgs &a, hipStream_t s)
 {
     dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);

@@ -87,6 +87,7 @@ struct dct_ctx {
     double dx = 0, dy = 0, dz = 0, org[3] = {0, 0, 0};
     std::vector<uint8_t> mat;
     std::vector<double> rho;
+    bool rho_dev = false;       // the densities were last set from a device buffer (no host copy)
     int G = 0, M = 0, L = 0;
     std::vector<double> st, ss, kap;
     std::vector<double> edges;  // group edges (keV, descending) when given
@@ -284,6 +285,7 @@ int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy,
     try {
         ctx->mat.assign(material, material + C);
         ctx->rho.assign(density, density + C);
+        ctx->rho_dev = false;
     } catch (const std::bad_alloc &) {
         return fail(ctx, DCT_ENOMEM, "set_geometry: out of host memory");
     }
@@ -296,6 +298,32 @@ int dct_set_geometry(dct_ctx *ctx, int nx, int ny, int nz, double dx, double dy,
     std::memcpy(ctx->org, origin, sizeof(ctx->org));
     ctx->has_geo = true;
     ctx->iso.clear();
+    invalidate(ctx);
+    return DCT_OK;
+}
+
+int dct_set_density_dev(dct_ctx *ctx, const double *density)
+{
+    if (!ctx) return DCT_EINVAL;
+    ctx->err.clear();
+    if (!ctx->has_geo) return fail(ctx, DCT_ESTATE, "set_density_dev: no geometry (call dct_set_geometry first)");
+    if (!density) return fail(ctx, DCT_EINVAL, "set_density_dev: NULL array");
+    const long C = (long)ctx->nx * ctx->ny * ctx->nz;
+    HC(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    void *d_rho, *d_bad;
+    HC(dbuf(ctx, "scr_bad", 8, &d_bad));
+    HC(hipMemsetAsync(d_bad, 0xff, 8, s));
+    HC(launch_screen(density, C, 1, (unsigned long long *)d_bad, s));
+    unsigned long long bad = 0;
+    HC(hipMemcpyAsync(&bad, d_bad, 8, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    if (bad != ~0ULL)
+        return fail(ctx, DCT_EINVAL, "set_density_dev: density must be finite and >= 0 (voxel " + std::to_string(bad) + ")");
+    HC(dbuf(ctx, "rho", (size_t)C * 8, &d_rho));
+    HC(hipMemcpyAsync(d_rho, density, (size_t)C * 8, hipMemcpyDeviceToDevice, s));
+    HC(hipStreamSynchronize(s));
+    ctx->rho_dev = true;
     invalidate(ctx);
     return DCT_OK;
 }
@@ -718,7 +746,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         HC(hipMemcpyAsync(d_Dt, Dt.data(), tabsz, hipMemcpyHostToDevice, s));
         if (ctx->dev_dirty) {
             HC(hipMemcpyAsync(d_mat, ctx->mat.data(), C, hipMemcpyHostToDevice, s));
-            HC(hipMemcpyAsync(d_rho, ctx->rho.data(), C * 8, hipMemcpyHostToDevice, s));
+            if (!ctx->rho_dev) HC(hipMemcpyAsync(d_rho, ctx->rho.data(), C * 8, hipMemcpyHostToDevice, s));
             HC(hipMemcpyAsync(d_st, ctx->st.data(), ctx->st.size() * 8, hipMemcpyHostToDevice, s));
             HC(hipMemcpyAsync(d_ss, ctx->ss.data(), ctx->ss.size() * 8, hipMemcpyHostToDevice, s));
             HC(hipMemcpyAsync(d_kap, ctx->kap.data(), ctx->kap.size() * 8, hipMemcpyHostToDevice, s));
@@ -1492,6 +1520,25 @@ extern "C" int dct_dose_dev(dct_ctx *ctx, double *dose, int summed, double *phi_
     return dose_common(ctx, dose, summed, phi_u, phi_c, true);
 }
 
+// R = sum_b sum_v roi[v] dose_b(v) of the last solve from ROI weights already
+// on the device: the summed dose tally, then a fixed-order FP64 dot product;
+// returns with R written.
+static int roi_response(dct_ctx *ctx, const double *d_roi, double *R)
+{
+    const long C = (long)ctx->nx * ctx->ny * ctx->nz;
+    hipStream_t s = ctx->stream;
+    void *dd, *dp;
+    HC(dbuf(ctx, "r_dose", (size_t)C * 8, &dd));
+    HC(dbuf(ctx, "r_part", (size_t)1025 * 8, &dp));
+    const int r = dose_common(ctx, (double *)dd, 1, nullptr, nullptr, true);
+    if (r != DCT_OK) return r;
+    HC(launch_wdot(d_roi, (const double *)dd, C, (double *)dp, s));
+    const int nb = (int)std::min<long>(1024, std::max<long>(1, (C + 255) / 256));
+    HC(hipMemcpyAsync(R, (double *)dp + nb, 8, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    return DCT_OK;
+}
+
 extern "C" int dct_roi_dose(dct_ctx *ctx, const double *roi, double *R)
 {
     if (!ctx) return DCT_EINVAL;
@@ -1501,19 +1548,10 @@ extern "C" int dct_roi_dose(dct_ctx *ctx, const double *roi, double *R)
     const long C = (long)ctx->nx * ctx->ny * ctx->nz;
     if (!finite_all(roi, C)) return fail(ctx, DCT_EINVAL, "roi_dose: roi not finite");
     HC(hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
-    void *dd, *dr, *dp;
-    HC(dbuf(ctx, "r_dose", (size_t)C * 8, &dd));
+    void *dr;
     HC(dbuf(ctx, "r_roi", (size_t)C * 8, &dr));
-    HC(dbuf(ctx, "r_part", (size_t)1025 * 8, &dp));
-    const int r = dose_common(ctx, (double *)dd, 1, nullptr, nullptr, true);
-    if (r != DCT_OK) return r;
-    HC(hipMemcpyAsync(dr, roi, (size_t)C * 8, hipMemcpyHostToDevice, s));
-    HC(launch_wdot((const double *)dr, (const double *)dd, C, (double *)dp, s));
-    const int nb = (int)std::min<long>(1024, std::max<long>(1, (C + 255) / 256));
-    HC(hipMemcpyAsync(R, (double *)dp + nb, 8, hipMemcpyDeviceToHost, s));
-    HC(hipStreamSynchronize(s));
-    return DCT_OK;
+    HC(hipMemcpyAsync(dr, roi, (size_t)C * 8, hipMemcpyHostToDevice, ctx->stream));
+    return roi_response(ctx, (const double *)dr, R);
 }
 
 // Checks of dct_effective_dose's table and its per-group factors: the table
@@ -1625,8 +1663,9 @@ extern "C" int dct_moments(dct_ctx *ctx, double *phi)
 }
 
 // ---------------------------------------------------------------- adjoint
-extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
-                           double *d_group_w, dct_stats *stats)
+// The adjoint solve; dev: roi, d_density and d_group_w are device buffers.
+static int adjoint_common(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
+                          double *d_group_w, dct_stats *stats, bool dev)
 {
     if (!ctx) return DCT_EINVAL;
     ctx->err.clear();
@@ -1635,7 +1674,18 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     if (!roi) return fail(ctx, DCT_EINVAL, "adjoint: roi is NULL");
     const int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz, G = ctx->G, M = ctx->M, L = ctx->L, N = ctx->N, B = ctx->B;
     const long C = (long)nx * ny * nz;
-    if (!finite_all(roi, C)) return fail(ctx, DCT_EINVAL, "adjoint: roi not finite");
+    if (!dev && !finite_all(roi, C)) return fail(ctx, DCT_EINVAL, "adjoint: roi not finite");
+    if (dev) {
+        HC(hipSetDevice(ctx->device));
+        void *d_bad;
+        HC(dbuf(ctx, "scr_bad", 8, &d_bad));
+        HC(hipMemsetAsync(d_bad, 0xff, 8, ctx->stream));
+        HC(launch_screen(roi, C, 0, (unsigned long long *)d_bad, ctx->stream));
+        unsigned long long bad = 0;
+        HC(hipMemcpyAsync(&bad, d_bad, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HC(hipStreamSynchronize(ctx->stream));
+        if (bad != ~0ULL) return fail(ctx, DCT_EINVAL, "adjoint: roi not finite (voxel " + std::to_string(bad) + ")");
+    }
     dct_opts o;
     std::memset(&o, 0, sizeof(o));
     o.tol = 1e-6;
@@ -1717,7 +1767,7 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
         hst[b].pending = 1;
     }
     int h_unf0 = B;
-    HC(hipMemcpyAsync(d_roi, roi, (size_t)C * 8, hipMemcpyHostToDevice, s));
+    HC(hipMemcpyAsync(d_roi, roi, (size_t)C * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(d_amt, Mt.data(), tabsz, hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(d_adt, Dt.data(), tabsz, hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(B_("state"), hst.data(), (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
@@ -1735,6 +1785,11 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     HC(launch_adj_init(C, G, B, (const uint8_t *)B_("mat"), (const double *)B_("kap"), (const double *)d_roi,
                        (double *)d_pbu, s));
     HC(hipStreamSynchronize(s));   // host tables must outlive the copies
+    if (R) {
+        // the response of the forward solve, reduced as dct_roi_dose does
+        const int r = roi_response(ctx, (const double *)d_roi, R);
+        if (r != DCT_OK) return r;
+    }
 
     Geo geo;
     geo.nx = nx;
@@ -1931,22 +1986,21 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
     }
     if (unfinished != 0) return fail(ctx, DCT_ENOTCONV, "adjoint: iteration-set cap reached");
 
-    std::vector<double> drho((size_t)B * C), dray(C), dose((size_t)B * C);
-    HC(hipMemcpy(drho.data(), d_drho, drho.size() * 8, hipMemcpyDeviceToHost));
-    HC(hipMemcpy(dray.data(), d_dray, dray.size() * 8, hipMemcpyDeviceToHost));
-    HC(hipMemcpy(dose.data(), B_("dose"), dose.size() * 8, hipMemcpyDeviceToHost));
-    if (d_density)
-        for (long v = 0; v < C; ++v) {
-            double t = dray[v];
-            for (int b = 0; b < B; ++b) t += drho[(size_t)b * C + v];
-            d_density[v] = t;
-        }
-    if (d_group_w) HC(hipMemcpy(d_group_w, d_dgw, (size_t)G * 8, hipMemcpyDeviceToHost));
-    if (R) {
-        double acc = 0.0;
-        for (int b = 0; b < B; ++b)
-            for (long v = 0; v < C; ++v) acc += roi[v] * dose[(size_t)b * C + v];
-        *R = acc;
+    if (dev) {
+        if (d_density) HC(launch_adj_gather((const double *)d_drho, (const double *)d_dray, C, B, d_density, s));
+        if (d_group_w) HC(hipMemcpyAsync(d_group_w, d_dgw, (size_t)G * 8, hipMemcpyDeviceToDevice, s));
+        HC(hipStreamSynchronize(s));
+    } else if (d_density || d_group_w) {
+        std::vector<double> drho((size_t)B * C), dray(C);
+        HC(hipMemcpy(drho.data(), d_drho, drho.size() * 8, hipMemcpyDeviceToHost));
+        HC(hipMemcpy(dray.data(), d_dray, dray.size() * 8, hipMemcpyDeviceToHost));
+        if (d_density)
+            for (long v = 0; v < C; ++v) {
+                double t = dray[v];
+                for (int b = 0; b < B; ++b) t += drho[(size_t)b * C + v];
+                d_density[v] = t;
+            }
+        if (d_group_w) HC(hipMemcpy(d_group_w, d_dgw, (size_t)G * 8, hipMemcpyDeviceToHost));
     }
     if (stats) {
         if (stats->iters) HC(hipMemcpy(stats->iters, d_ait, (size_t)B * G * 4, hipMemcpyDeviceToHost));
@@ -1957,4 +2011,16 @@ extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts
         stats->iteration_sets = (int)sets;
     }
     return DCT_OK;
+}
+
+extern "C" int dct_adjoint(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
+                           double *d_group_w, dct_stats *stats)
+{
+    return adjoint_common(ctx, roi, opts, R, d_density, d_group_w, stats, false);
+}
+
+extern "C" int dct_adjoint_dev(dct_ctx *ctx, const double *roi, const dct_opts *opts, double *R, double *d_density,
+                               double *d_group_w, dct_stats *stats)
+{
+    return adjoint_common(ctx, roi, opts, R, d_density, d_group_w, stats, true);
 }

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "DCT_OK", -1: "DCT_EINVAL", -2: "DCT_ESTATE", -3: "DCT_EDEVIC
 EXPORTS = ["dct_create", "dct_destroy", "dct_last_error", "dct_set_geometry", "dct_set_xs",
            "dct_set_quadrature", "dct_set_source", "dct_set_volume_source", "dct_solve", "dct_dose",
            "dct_dose_dev", "dct_effective_dose", "dct_effective_dose_noalloc", "dct_adjoint", "dct_moments",
-           "dct_roi_dose"]
+           "dct_roi_dose", "dct_set_density_dev", "dct_adjoint_dev"]
 
 
 class DctError(RuntimeError):
@@ -84,6 +84,8 @@ def lib():
         L.dct_dose_dev.argtypes = [_vp, _vp, ct.c_int, _vp, _vp]
         L.dct_roi_dose.argtypes = [_vp, _d, _d]
         L.dct_adjoint.argtypes = [_vp, _d, ct.POINTER(dct_opts), _d, _d, _d, ct.POINTER(dct_stats)]
+        L.dct_adjoint_dev.argtypes = [_vp, _vp, ct.POINTER(dct_opts), _d, _vp, _vp, ct.POINTER(dct_stats)]
+        L.dct_set_density_dev.argtypes = [_vp, _vp]
         L.dct_moments.argtypes = [_vp, _d]
         L.dct_effective_dose.argtypes = [_vp, ct.c_int, _d, _d, _u8, _d, ct.c_int]
         L.dct_effective_dose_noalloc.argtypes = [_vp, ct.c_int, _d, _d, _u8, _vp, ct.c_int]
@@ -106,6 +108,20 @@ def _dev_ptr(t):
     """Device pointer of a torch tensor (or None)."""
     if t is None:
         return None
+    return ct.c_void_p(t.data_ptr())
+
+
+def _dev_f64(t, n, what):
+    """Device pointer of a contiguous float64 GPU tensor of n elements (or None),
+    after the work queued on torch's current stream has finished."""
+    if t is None:
+        return None
+    import torch
+
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{what}: expected a contiguous float64 GPU tensor of {n} elements, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+    torch.cuda.current_stream(t.device).synchronize()
     return ct.c_void_p(t.data_ptr())
 
 
@@ -279,8 +295,8 @@ def roi_dose(h, C, roi) -> float:
 @dataclass
 class AdjointResult:
     R: float
-    d_density: np.ndarray     # [C]
-    d_group_w: np.ndarray     # [G]
+    d_density: np.ndarray     # [C] (from adjoint_dev: the caller's GPU tensor)
+    d_group_w: np.ndarray     # [G] (likewise)
     iters: np.ndarray         # [B][G] adjoint iterations
     eps: np.ndarray
     solve_ms: float
@@ -309,6 +325,35 @@ def adjoint(h, B, G, C, roi, *, tol=1e-6, max_iter=1000, fixed_iters=None, chunk
     st.eps = _p(eps)
     _chk(h, lib().dct_adjoint(h, _p(roi), ct.byref(o), _p(R), _p(dd), _p(dg), ct.byref(st)))
     return AdjointResult(float(R[0]), dd, dg, iters, eps, st.solve_ms)
+
+
+def set_density_dev(h, C, density_t):
+    """New voxel densities from a float64 GPU tensor of C elements (grid and
+    materials of the last set_geometry kept)."""
+    return _chk(h, lib().dct_set_density_dev(h, _dev_f64(density_t, C, "density")))
+
+
+def adjoint_dev(h, B, G, C, roi_t, d_density_t=None, d_group_w_t=None, *, tol=1e-6, max_iter=1000,
+                fixed_iters=None, chunk=0, stall_window=0) -> AdjointResult:
+    """As adjoint, with the ROI weights read from and the gradients written into
+    float64 GPU tensors; d_density / d_group_w of the result are those tensors."""
+    o = dct_opts()
+    o.tol = tol
+    o.max_iter = max_iter
+    fi = None if fixed_iters is None else np.ascontiguousarray(fixed_iters, dtype=np.int32)
+    o.fixed_iters = _p(fi, ct.POINTER(ct.c_int)) if fi is not None else None
+    o.chunk = int(chunk)
+    o.stall_window = int(stall_window)
+    R = np.zeros(1)
+    iters = np.zeros((B, G), dtype=np.int32)
+    eps = np.zeros((B, G))
+    st = dct_stats()
+    st.iters = iters.ctypes.data_as(ct.POINTER(ct.c_int))
+    st.eps = _p(eps)
+    _chk(h, lib().dct_adjoint_dev(h, _dev_f64(roi_t, C, "roi"), ct.byref(o), _p(R),
+                                  _dev_f64(d_density_t, C, "d_density"), _dev_f64(d_group_w_t, G, "d_group_w"),
+                                  ct.byref(st)))
+    return AdjointResult(float(R[0]), d_density_t, d_group_w_t, iters, eps, st.solve_ms)
 
 
 def moments(h, B, G, Nm, C):
@@ -346,9 +391,17 @@ class Solver:
         return adjoint(self.h, self.prob.B, self.prob.G, self.prob.phantom.C, roi, **kw)
 
     def set_density(self, density):
-        """Replace the voxel densities (same grid and materials)."""
+        """Replace the voxel densities (same grid and materials): a host array,
+        or a float64 GPU tensor, which the library copies on the device."""
         ph = self.prob.phantom
-        set_geometry(self.h, ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, ph.origin, ph.material, density)
+        if getattr(density, "is_cuda", False):
+            set_density_dev(self.h, ph.C, density.reshape(-1))
+        else:
+            set_geometry(self.h, ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, ph.origin, ph.material, density)
+
+    def adjoint_dev(self, roi_t, d_density_t=None, d_group_w_t=None, **kw) -> AdjointResult:
+        return adjoint_dev(self.h, self.prob.B, self.prob.G, self.prob.phantom.C, roi_t, d_density_t,
+                           d_group_w_t, **kw)
 
     def set_group_weights(self, group_w):
         p = self.prob

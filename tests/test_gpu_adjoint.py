@@ -231,6 +231,101 @@ def test_autograd_wrapper():
         s.close()
 
 
+def test_device_buffer_density_and_adjoint():
+    """dct_set_density_dev and dct_adjoint_dev: densities taken from a GPU
+    buffer give the dose of the host setter bit for bit; the device-buffer
+    adjoint gives the host adjoint's R bit for bit and its gradients to 1e-12
+    (the ray back-projection adds into each voxel with FP64 atomics, whose
+    order varies between runs), the oracle adjoint's to 1e-10; bad values are
+    rejected with the voxel named."""
+    import torch
+
+    prob, roi, fi, fa, ref = _oracle_adjoint("ring2")
+    C, G = prob.phantom.C, prob.G
+    _say(f"[adjoint dev buffers] ring2 C={C} G={G} B={prob.B}")
+    fresh = dctsn.create(0)
+    try:
+        with pytest.raises(dctsn.DctError) as e:
+            dctsn.set_density_dev(fresh, C, torch.ones(C, dtype=torch.float64, device="cuda"))
+        assert e.value.code == dctsn.DCT_ESTATE
+    finally:
+        dctsn.destroy(fresh)
+    s = dctsn.Solver(prob)
+    try:
+        s.solve(precision="fp64", fixed_iters=fi, keep_adjoint=True)
+        dose_h = s.dose()
+        ah = s.adjoint(roi, fixed_iters=fa)
+        # scale the density on the device and back: the same values, set from a GPU buffer
+        rho_t = torch.tensor(prob.phantom.density, dtype=torch.float64, device="cuda") * 2.0 * 0.5
+        s.set_density(rho_t)
+        s.solve(precision="fp64", fixed_iters=fi, keep_adjoint=True)
+        assert np.array_equal(s.dose(), dose_h)
+        roi_t = torch.tensor(roi, dtype=torch.float64, device="cuda")
+        dd = torch.full((C,), np.nan, dtype=torch.float64, device="cuda")
+        dg = torch.full((G,), np.nan, dtype=torch.float64, device="cuda")
+        ad = s.adjoint_dev(roi_t, dd, dg, fixed_iters=fa)
+        assert ad.R == ah.R
+        assert rel(dd.cpu().numpy(), ah.d_density) <= 1e-12
+        assert rel(dg.cpu().numpy(), ah.d_group_w) <= 1e-12
+        assert np.array_equal(ad.iters, ah.iters)
+        _check("dev-buffer d_density vs oracle", dd.cpu().numpy(), ref.d_density)
+        # either output may be omitted
+        dd2 = torch.zeros(C, dtype=torch.float64, device="cuda")
+        s.adjoint_dev(roi_t, dd2, None, fixed_iters=fa)
+        assert rel(dd2.cpu().numpy(), ah.d_density) <= 1e-12
+        bad = roi_t.clone()
+        bad[7] = float("inf")
+        with pytest.raises(dctsn.DctError) as e:
+            s.adjoint_dev(bad, dd, dg, fixed_iters=fa)
+        assert e.value.code == dctsn.DCT_EINVAL and "voxel 7" in str(e.value)
+        neg = rho_t.clone()
+        neg[11] = -1.0
+        neg[40] = float("nan")
+        with pytest.raises(dctsn.DctError) as e:
+            s.set_density(neg)
+        assert e.value.code == dctsn.DCT_EINVAL and "voxel 11" in str(e.value)
+        # a rejected density leaves the previous one in place
+        s.solve(precision="fp64", fixed_iters=fi)
+        assert np.array_equal(s.dose(), dose_h)
+        # a host density after a device one is taken again
+        rho2 = prob.phantom.density * 1.25
+        s.set_density(rho2)
+        s.solve(precision="fp64", fixed_iters=fi)
+        d2 = s.dose()
+        s.set_density(torch.tensor(rho2, dtype=torch.float64, device="cuda"))
+        s.solve(precision="fp64", fixed_iters=fi)
+        assert np.array_equal(s.dose(), d2)
+        with pytest.raises(ValueError):
+            s.set_density(torch.ones(C, dtype=torch.float32, device="cuda"))
+    finally:
+        s.close()
+
+
+def test_autograd_wrapper_gpu_tensors():
+    """torch.autograd through roi_dose with GPU tensors: the density and its
+    gradient stay on the device and match the oracle adjoint."""
+    import torch
+
+    from paper_1811_12391_amd.autograd import roi_dose
+
+    prob, roi, fi, fa, ref = _oracle_adjoint("tiny_abd")
+    ph = prob.phantom
+    s = dctsn.Solver(prob)
+    try:
+        rho = torch.tensor(ph.density.reshape(ph.nz, ph.ny, ph.nx), dtype=torch.float64, device="cuda",
+                           requires_grad=True)
+        gw = torch.tensor(prob.group_w, dtype=torch.float64, device="cuda", requires_grad=True)
+        R = roi_dose(s, rho, gw, roi, fwd={"precision": "fp64", "fixed_iters": fi}, adj={"fixed_iters": fa})
+        assert R.is_cuda
+        (2.0 * R).backward()
+        assert rho.grad.is_cuda and rho.grad.shape == rho.shape and gw.grad.is_cuda
+        assert abs(float(R) - ref.R) <= 1e-10 * abs(ref.R)
+        _check("autograd gpu d_density", rho.grad.cpu().numpy().reshape(-1) / 2.0, ref.d_density)
+        _check("autograd gpu d_group_w", gw.grad.cpu().numpy() / 2.0, ref.d_group_w)
+    finally:
+        s.close()
+
+
 def test_adjoint_after_layered_forward():
     """A forward solve on layered waves keeps the same fixup sets, and the
     adjoint that follows (transposed sweeps on the barrier coupling) matches
