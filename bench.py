@@ -68,7 +68,8 @@ def sweep_roofline(res, C, workload):
     avg_launch_ms = res["sweep_ms_timed_per_solve"] / res["sweep_launches_timed_per_solve"]
     achieved = bytes_per_solve / launches / (avg_launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, res["precision"]),
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(workload, res["precision"], streams=res.get("rhs_streams", 1)),
             "kernel": "k_sweep", "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_solve / launches}
 
 
@@ -84,12 +85,13 @@ def fused_roofline(res, prob, workload):
     s = 8 if res["precision"] == "fp64" else 4
     N, Nm = prob.N, (prob.L + 1) ** 2
     cell_iters = res["sweep_updates_per_solve"] / N
-    launches = res["iteration_sets"]                     # one fused launch per iteration set
+    launches = res["iteration_sets"] * res.get("rhs_streams", 1)   # one fused launch per set and stream
     bytes_per_solve = cell_iters * ((2 * N + 2 * Nm + 1) * s + 9)
     avg_launch_ms = res["fused_ms_timed_per_solve"] / res["fused_launches_timed_per_solve"]
     achieved = bytes_per_solve / launches / (avg_launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, res["precision"], "k_dcm"),
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(workload, res["precision"], "k_dcm", res.get("rhs_streams", 1)),
             "kernel": "k_dcm", "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_solve / launches}
 
 
@@ -140,7 +142,9 @@ def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=No
         "sweep_schedule": {"z_layers_per_workgroup": int(stats[-1].sweep_bk),
                            "wave_coupling": COUPLINGS.get(int(stats[-1].sweep_sync), str(stats[-1].sweep_sync)),
                            "chained_directions": int(stats[-1].sweep_chain),
-                           "chained_sources": int(stats[-1].sweep_rhs_chain)},
+                           "chained_sources": int(stats[-1].sweep_rhs_chain),
+                           "streams": int(stats[-1].rhs_streams)},
+        "rhs_streams": int(stats[-1].rhs_streams),
         "fused_maps": bool(stats[-1].fused_maps),
         "dose": dose,
     }
@@ -175,19 +179,38 @@ def run_workload(name, precisions, steps, warmup, schedule=None):
                 fixed = (np.array(src["iters_per_group_max_over_sources"], dtype=np.int32) if src
                          else np.full(G, 12, np.int32))
             results[p] = timed_solves(solver, prob, p, steps, warmup, f"{name} {p}", dose_dev, fixed, schedule)
+            if results[p]["rhs_streams"] == 2:
+                # the same solve on one stream: the kernels' own rates, without the
+                # other half's launches beside them
+                results[p]["one_stream"] = timed_solves(solver, prob, p, steps, warmup, f"{name} {p} one stream",
+                                                        dose_dev, fixed, schedule, rhs_streams=1)
     finally:
         solver.close()
     ref = results["fp64"]["dose"] if "fp64" in results else None
     for r in results.values():
         if ref is not None:
             r["dose_l2_rel_err_vs_fp64"] = float(np.linalg.norm(r["dose"] - ref) / np.linalg.norm(ref))
-        kernels = [sweep_roofline(r, C, name)]
-        fr = fused_roofline(r, prob, name)
-        if fr is not None:
-            kernels.append(fr)
-        # the dominant kernel: the largest device time per solve
-        r["roofline_kernels"] = kernels
-        r["roofline"] = max(kernels, key=lambda k: k["avg_launch_ms"])
+        for rr in [r] + ([r["one_stream"]] if "one_stream" in r else []):
+            kernels = [sweep_roofline(rr, C, name)]
+            fr = fused_roofline(rr, prob, name)
+            if fr is not None:
+                kernels.append(fr)
+            for k in kernels:
+                k["streams"] = rr["rhs_streams"]
+            # the dominant kernel: the longest average launch
+            rr["roofline_kernels"] = kernels
+            rr["roofline"] = max(kernels, key=lambda k: k["avg_launch_ms"])
+        if "one_stream" in r:
+            r["one_stream"].pop("dose", None)
+            # both kernels' algorithmic bytes over the device time of the solve: what
+            # the two streams move together
+            tot = sum(k["bytes_per_launch"] * n for k, n in
+                      zip(r["roofline_kernels"], (r["sweep_launches_per_solve"],
+                                                  r["iteration_sets"] * r["rhs_streams"])))
+            ach = tot / (r["device_ms_per_solve"] * 1e-3) / 1e9
+            r["roofline_aggregate"] = {"kernels": "k_sweep + k_dcm", "bytes_per_solve": tot,
+                                       "device_ms_per_solve": r["device_ms_per_solve"], "achieved": ach,
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
     return prob, results
 
 
@@ -253,6 +276,10 @@ def main():
                    "precision": best},
         "roofline": hb["roofline"],
         "roofline_kernels": hb["roofline_kernels"],
+        # with the sources in two halves on two streams the launches above overlap the
+        # other half's; the same solve on one stream gives the kernels' own rates
+        "roofline_one_stream": hb.get("one_stream", {}).get("roofline"),
+        "roofline_aggregate": hb.get("roofline_aggregate"),
         "variants": {p: {k: v for k, v in r.items() if k != "dose"} for p, r in results.items()},
     }
     if not args.no_forms:
@@ -462,11 +489,13 @@ SWEEP_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_sweep.hip")
 FUSED_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_source.hip")
 
 
-def measured_traffic(workload, precision, kernel="k_sweep"):
+def measured_traffic(workload, precision, kernel="k_sweep", streams=1):
     """HBM bytes per sweep launch (FETCH_SIZE + WRITE_SIZE, scaled by the
     same counters on a plain copy of known size) from the committed counter
-    summary of that workload, or None when there is none for this precision
-    or the sweep source has changed since the counters were taken."""
+    summary of that workload, or None when there is none for this precision,
+    the kernel's source has changed since the counters were taken, or they
+    were taken with launches over a different share of the right-hand sides
+    (one or two streams)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
@@ -481,7 +510,7 @@ def measured_traffic(workload, precision, kernel="k_sweep"):
     src = SWEEP_SRC if kernel == "k_sweep" else FUSED_SRC
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if kv.get(f"{kernel}_sha256") != sha:
+    if kv.get(f"{kernel}_sha256") != sha or int(kv.get("streams", "1")) != streams:
         return None
     v = kv.get(f"bytes_per_launch_{precision}")
     return float(v) if v is not None else None

@@ -154,6 +154,13 @@ typedef struct dct_opts {
                                  coupling 2.  R in [2, 8]; 0 = tuned among 2, 3, 4, 6, 8 (or
                                  min(B, 4) when a chained coupling is asked for without
                                  tuning); 1 = none. */
+    int rhs_streams;          /* right-hand sides split in two halves whose iteration sets run
+                                 on two streams, so that one half's sweep overlaps the other
+                                 half's fused map kernel (the halves are independent; results
+                                 are those of one stream bit for bit).  Needs the fused maps,
+                                 layered waves (coupling 4 / 5), B >= 2 and graph off;
+                                 otherwise one stream.  0 = two streams when B N >= 4 x the
+                                 compute units, 1 = one stream, 2 = two streams. */
 } dct_opts;
 
 typedef struct dct_stats {
@@ -180,6 +187,7 @@ typedef struct dct_stats {
     double fused_ms;          /* summed device time of the timed fused-map launches (profile > 0) */
     int fused_launches;       /* fused-map launches whose time is in fused_ms */
     int sweep_rhs_chain;      /* right-hand sides per chained sweep workgroup that ran (1 = none) */
+    int rhs_streams;          /* streams the iteration sets ran on (1 or 2) */
 } dct_stats;
 
 /* Create a context on HIP device `device` using `stream` (a hipStream_t; NULL

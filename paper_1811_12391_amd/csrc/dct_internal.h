@@ -307,6 +307,8 @@ struct TransArgs {
     unsigned *cnt_sub;        // [B][nsub][32] completion sub-counters (zero between launches)
     int nsub;                 // ceil(workgroups per right-hand side / 32)
     double *part_bal;         // [B][workgroups][2] per-workgroup removal and production sums
+    int b0 = 0;               // the launch covers right-hand sides b0 .. b0 + nb - 1
+    int nb = 0;               // (0: all B); B stays the stride of every [B] array
 };
 
 struct CombArgs {
@@ -330,6 +332,8 @@ struct CombArgs {
     int reverse;              // groups run from G-1 down to 0
     unsigned *cnt_mom;        // [B][Nm][32] completion counters of the moment groups, one per 128-byte line
     int mpw;                  // moments per workgroup (>= 1)
+    int b0 = 0;               // the launch covers right-hand sides b0 .. b0 + nb - 1
+    int nb = 0;               // (0: all B); B stays the stride of every [B] array
     int warm;                 // 1: the first source of a group includes the self-scatter of
                               //    the starting moments (warm start), not Q = ext
 };
@@ -422,6 +426,8 @@ struct SweepArgs {
     int chainK;               // > 1: K consecutive directions of one octant per workgroup (k_sweep_ch);
                               //      q, psi in the chain layout, sigma_t from sigch
     const void *sigch;        // T [2][G][K C] sigma_t in the chain layout of period K nx
+    int b0 = 0;               // the launch covers right-hand sides b0 .. b0 + nb - 1 (layered
+    int nb = 0;               // waves only; 0: all B); B stays the stride of every [B] array
     int rhsK;                 // > 1: one direction of up to rhsK unfinished right-hand sides per
                               //      workgroup, swept back to back (k_sweep_rc)
 };

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_transition(TransArgs a)
 {
     constexpr int NM = (LT + 1) * (LT + 1);
     __shared__ double red[8];
-    const int b = blockIdx.y;
+    const int b = a.b0 + (int)blockIdx.y;
     RhsState *st = a.state + b;
     if (!st->pending) return;
     const int g = st->g;
@@ -331,7 +331,9 @@ hipError_t launch_adj_transition(const AdjTransArgs &a, int is_f64, hipStream_t 
 
 hipError_t launch_transition(const TransArgs &a, int is_f64, hipStream_t s)
 {
-    dim3 grid((unsigned)((a.geo.C + 255) / 256), a.B);
+    const int nb = a.nb > 0 ? a.nb : a.B;
+    if (a.b0 < 0 || a.b0 + nb > a.B) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((a.geo.C + 255) / 256), nb);
     if (a.L < 0 || a.L > DCT_MAXL) return hipErrorInvalidValue;
     if (is_f64) DCT_BY_ORDER(k_transition, double, a.L, grid, dim3(256), 0, s, a);
     else DCT_BY_ORDER(k_transition, float, a.L, grid, dim3(256), 0, s, a);
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
     const int nx = a.geo.nx, ny = a.geo.ny;
     const int nslj = (ny + 15) >> 4;
     const unsigned nsl = (unsigned)(a.geo.nz * nslj);          // slabs of one right-hand side
-    const unsigned NW = nsl * (unsigned)a.B;
+    const unsigned NW = nsl * (unsigned)(a.nb > 0 ? a.nb : a.B);   // items of this launch's right-hand sides
     const long C = a.geo.C;
     const int G = a.G, Nm = a.Nm, L = a.L, N = m.N;
     const int pitch = (nx | 1) + 1;
@@ -671,8 +673,9 @@ __global__ __launch_bounds__(512) void k_dcm(CombArgs a, MapArgs m)
             const unsigned xcd = lin & 7, slot = lin >> 3;
             W = 2 * ((slot >> 1) * 8 + xcd) + (slot & 1);
         }
-        const int b = __builtin_amdgcn_readfirstlane((int)(W / nsl));
-        const int slab = __builtin_amdgcn_readfirstlane((int)(W - (unsigned)b * nsl));
+        const int bl = __builtin_amdgcn_readfirstlane((int)(W / nsl));
+        const int slab = __builtin_amdgcn_readfirstlane((int)(W - (unsigned)bl * nsl));
+        const int b = a.b0 + bl;
         RhsState *st = a.state + b;
         if (st->finished) continue;
         // first iteration of a group: only the sources that start one
@@ -934,7 +937,9 @@ size_t dcm_lds_bytes(const CombArgs &a, const MapArgs &m, int is_f64)
 hipError_t launch_dcm(const CombArgs &a, const MapArgs &m, int is_f64, hipStream_t s, int first, int max_wg)
 {
     const int nslj = (a.geo.ny + 15) >> 4;
-    const long nw = (long)a.geo.nz * nslj * a.B;
+    const int nb = a.nb > 0 ? a.nb : a.B;
+    if (a.b0 < 0 || a.b0 + nb > a.B) return hipErrorInvalidValue;
+    const long nw = (long)a.geo.nz * nslj * nb;
     const dim3 grid((unsigned)(max_wg > 0 && max_wg < nw ? max_wg : nw));
     const size_t shm = dcm_lds_bytes(a, m, is_f64);
     const int nrb = (a.Nm + 15) / 16;

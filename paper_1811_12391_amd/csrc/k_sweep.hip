@@ -614,7 +614,7 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_lw(SweepArgs a)
     constexpr unsigned TS = sizeof(T);
     __shared__ T zbuf[2][17][64];                            // row w + 1: top layer of wave w; row 0: boundary
     __shared__ double red[3][16];
-    const int item = blockIdx.x;
+    const int item = a.b0 * a.N + (int)blockIdx.x;          // this launch's right-hand sides start at b0
     const int b = item / a.N;
     const int n = item - b * a.N;
     if (a.state[b].finished) return;
@@ -1259,6 +1259,11 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
         grid = dim3((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
     }
     const int mode = a.adjoint ? 2 : (a.mask ? 1 : 0);
+    // a launch over a subset of the right-hand sides: layered waves only
+    const int nb = a.nb > 0 ? a.nb : a.B;
+    const bool layered = (a.layers == 2 || a.layers == 4) && !multi && mode != 2 && a.ny <= 64 && a.nz <= 16;
+    if (a.b0 < 0 || a.b0 + nb > a.B || ((a.b0 != 0 || nb != a.B) && (!layered || a.chainK > 1 || a.rhsK > 1)))
+        return hipErrorInvalidValue;
     if (a.chainK > 1) {
         // chained directions: one block, forward sweep without kept fluxes,
         // ny <= nx, K divides N (checked by the host)
@@ -1295,9 +1300,9 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
 #undef DCT_RC
         return hipGetLastError();
     }
-    if ((a.layers == 2 || a.layers == 4) && !multi && mode != 2 && a.ny <= 64 && a.nz <= 16) {
+    if (layered) {
         const int nwv = (a.nz + a.layers - 1) / a.layers;
-        const dim3 lgrid((unsigned)(a.B * a.N)), lblock(64 * nwv);
+        const dim3 lgrid((unsigned)(nb * a.N)), lblock(64 * nwv);
 #define DCT_LW(T, ZL, MD) hipLaunchKernelGGL((k_sweep_lw<T, ZL, (ZL == 4 ? 4 : 8), MD>), lgrid, lblock, 0, s, a)
         if (is_f64) {
             if (a.layers == 4) { if (mode == 1) DCT_LW(double, 4, 1); else DCT_LW(double, 4, 0); }

@@ -130,6 +130,9 @@ struct dct_ctx {
     bool pipe_clean = false;           // pipelined-block face buffers hold only the empty marker
     unsigned sweep_seq = 0;            // counts sweep launches (part of the pipelined blocks' launch tag)
     hipStream_t own_stream = nullptr;  // capture stream when the context's stream is the null stream
+    hipStream_t half_stream = nullptr; // second stream of the split iteration sets (default priority)
+    hipEvent_t ev_half[3] = {nullptr, nullptr, nullptr};   // fork, and the second stream's chunk ends
+    int last_streams = 1;              // streams the last solve's iteration sets ran on
 
     std::vector<hipEvent_t> evpool, evpool_m;   // event pairs around timed sweep / fused-map launches
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
@@ -248,6 +251,9 @@ int dct_destroy(dct_ctx *ctx)
         for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
         for (hipEvent_t e : ctx->evpool_m) (void)hipEventDestroy(e);
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+        if (ctx->half_stream) (void)hipStreamDestroy(ctx->half_stream);
+        for (hipEvent_t e : ctx->ev_half)
+            if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : {ctx->ev_poll[0], ctx->ev_poll[1], ctx->ev_t0, ctx->ev_t1})
             if (e) (void)hipEventDestroy(e);
         if (ctx->h_unf) (void)hipHostFree(ctx->h_unf);
@@ -551,6 +557,7 @@ static int check_consistency(dct_ctx *ctx, const dct_opts &o, Plan &pl)
         return fail(ctx, DCT_EINVAL, "solve: sweep_rhs_chain must be in [0, " + std::to_string(DCT_MAXRC) + "]");
     if (o.accel_depth < 0 || o.accel_depth > DCT_AA_MAXM)
         return fail(ctx, DCT_EINVAL, "solve: accel_depth must be in [0, " + std::to_string(DCT_AA_MAXM) + "]");
+    if (o.rhs_streams < 0 || o.rhs_streams > 2) return fail(ctx, DCT_EINVAL, "solve: rhs_streams must be in [0, 2]");
     if (o.sweep_chain < -1 || o.sweep_chain > DCT_MAXCHAIN)
         return fail(ctx, DCT_EINVAL, "solve: sweep_chain must be in [-1, " + std::to_string(DCT_MAXCHAIN) + "]");
     if (o.superpose < 0 || (o.superpose > 1 && ctx->B % o.superpose != 0))
@@ -1255,18 +1262,32 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     const int pevery = o.profile > 1 ? o.profile : 1;   // time every pevery-th sweep launch
     int nprof = 0, nprof_m = 0;
     long nsweeps = 0, nmaps = 0;
-    auto enqueue_set = [&](hipStream_t es) -> hipError_t {
-        hipError_t e = launch_transition(tr, is64, es);
+    // right-hand sides in two halves on two streams: one half's sweep (issue-
+    // and latency-bound) runs beside the other half's fused kernel (memory-
+    // bound); the halves share no data, so each keeps its own order
+    int nstreams = 1;
+    if (!o.use_graph && fused && (ctx->last_sync == 4 || ctx->last_sync == 5) && B >= 2 &&
+        (o.rhs_streams == 2 || (o.rhs_streams == 0 && (long)B * N >= 4L * ctx->ncu)))
+        nstreams = 2;
+    ctx->last_streams = nstreams;
+    const int hb = nstreams == 2 ? B / 2 : B;   // first half: right-hand sides 0 .. hb - 1
+    auto enqueue_set = [&](hipStream_t es, int b0, int nb) -> hipError_t {
+        TransArgs trh = tr;
+        CombArgs cbh = cb;
+        SweepArgs swh = sw;
+        trh.b0 = cbh.b0 = swh.b0 = b0;
+        trh.nb = cbh.nb = swh.nb = nb;
+        hipError_t e = launch_transition(trh, is64, es);
         if (e != hipSuccess) return e;
         if (fused) {
             // first iteration of a group: q from ext in one pass over the slabs
-            if ((e = launch_dcm(cb, ma, is64, es, 1, dcm_wg)) != hipSuccess) return e;
+            if ((e = launch_dcm(cbh, ma, is64, es, 1, dcm_wg)) != hipSuccess) return e;
         } else {
             if ((e = launch_qinit(cb, is64, es)) != hipSuccess) return e;
             if ((e = launch_mmap(ma, mode, es)) != hipSuccess) return e;
         }
-        for (int d = 0; d < (sw.pipe ? 1 : pl.ndiag); ++d) {
-            sw.diag = d;
+        for (int d = 0; d < (swh.pipe ? 1 : pl.ndiag); ++d) {
+            swh.diag = d;
             const bool timed = profile && nsweeps++ % pevery == 0;
             if (timed) {
                 while ((int)ctx->evpool.size() < 2 * (nprof + 1)) {
@@ -1276,7 +1297,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 if ((e = hipEventRecord(ctx->evpool[2 * nprof], es)) != hipSuccess) return e;
             }
-            if ((e = launch_sweep(sw, is64, es, ctx->sweep_seq++)) != hipSuccess) return e;
+            if ((e = launch_sweep(swh, is64, es, ctx->sweep_seq++)) != hipSuccess) return e;
             if (timed) {
                 if ((e = hipEventRecord(ctx->evpool[2 * nprof + 1], es)) != hipSuccess) return e;
                 ++nprof;
@@ -1292,7 +1313,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 if ((e = hipEventRecord(ctx->evpool_m[2 * nprof_m], es)) != hipSuccess) return e;
             }
-            if ((e = launch_dcm(cb, ma, is64, es, 0, dcm_wg)) != hipSuccess) return e;
+            if ((e = launch_dcm(cbh, ma, is64, es, 0, dcm_wg)) != hipSuccess) return e;
             if (timed) {
                 if ((e = hipEventRecord(ctx->evpool_m[2 * nprof_m + 1], es)) != hipSuccess) return e;
                 ++nprof_m;
@@ -1329,11 +1350,21 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
         HC(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
-        for (int c = 0; c < chunk && ce == hipSuccess; ++c) ce = enqueue_set(ls);
+        for (int c = 0; c < chunk && ce == hipSuccess; ++c) ce = enqueue_set(ls, 0, B);
         hipError_t ee = hipStreamEndCapture(ls, &graph);
         HC(ce);
         HC(ee);
         HC(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
+    hipStream_t hs = nullptr;   // the second half's stream
+    if (nstreams == 2) {
+        if (!ctx->half_stream) HC(hipStreamCreateWithFlags(&ctx->half_stream, hipStreamNonBlocking));
+        for (hipEvent_t &e : ctx->ev_half)
+            if (!e) HC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        hs = ctx->half_stream;
+        // it starts after everything enqueued on the context's stream so far
+        HC(hipEventRecord(ctx->ev_half[0], ls));
+        HC(hipStreamWaitEvent(hs, ctx->ev_half[0], 0));
     }
     long sets = 0;
     int kpoll = 0;
@@ -1343,7 +1374,20 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
             HC(hipGraphLaunch(gexec, ls));
             sets += chunk;
         } else {
-            for (int c = 0; c < chunk && sets < cap_sets; ++c, ++sets) HC(enqueue_set(ls));
+            for (int c = 0; c < chunk && sets < cap_sets; ++c, ++sets) {
+                if (hs) {
+                    HC(enqueue_set(ls, 0, hb));
+                    HC(enqueue_set(hs, hb, B - hb));
+                } else {
+                    HC(enqueue_set(ls, 0, B));
+                }
+            }
+        }
+        if (hs) {
+            // the count polled below then covers the second stream up to its
+            // previous chunk (the streams stay within a chunk of each other)
+            HC(hipEventRecord(ctx->ev_half[1 + (kpoll & 1)], hs));
+            if (kpoll > 0) HC(hipStreamWaitEvent(ls, ctx->ev_half[1 + ((kpoll - 1) & 1)], 0));
         }
         HC(hipMemcpyAsync(&ctx->h_unf[kpoll & 1], d_unf, 4, hipMemcpyDeviceToHost, ls));
         HC(hipEventRecord(ctx->ev_poll[kpoll & 1], ls));
@@ -1351,6 +1395,14 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
             HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
             if (ctx->h_unf[(kpoll - 1) & 1] == 0) done = true;
         }
+        ++kpoll;
+    }
+    if (hs) {
+        // join the second stream and take the count once more with both done
+        HC(hipEventRecord(ctx->ev_half[0], hs));
+        HC(hipStreamWaitEvent(ls, ctx->ev_half[0], 0));
+        HC(hipMemcpyAsync(&ctx->h_unf[kpoll & 1], d_unf, 4, hipMemcpyDeviceToHost, ls));
+        HC(hipEventRecord(ctx->ev_poll[kpoll & 1], ls));
         ++kpoll;
     }
     if (ls != s) HC(hipStreamWaitEvent(s, ctx->ev_poll[(kpoll - 1) & 1], 0));
@@ -1420,12 +1472,13 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         }
         stats->fused_ms = mms;
         stats->fused_launches = nprof_m;
-        stats->sweep_launches_all = (long long)sets * (sw.pipe ? 1 : pl.ndiag);
+        stats->sweep_launches_all = (long long)sets * (sw.pipe ? 1 : pl.ndiag) * nstreams;
         stats->iteration_sets = (int)sets;
         stats->sweep_bk = pl.BK;
         stats->sweep_sync = ctx->last_sync;
         stats->sweep_chain = ctx->last_chain;
         stats->sweep_rhs_chain = ctx->last_rhs;
+        stats->rhs_streams = ctx->last_streams;
         stats->fused_maps = ctx->last_fused ? 1 : 0;
         stats->warm_start = ctx->last_warm ? 1 : 0;
         stats->tune_ms = tune_ms;

@@ -42,7 +42,8 @@ class dct_opts(ct.Structure):
                 ("profile", ct.c_int), ("keep_adjoint", ct.c_int), ("autotune", ct.c_int),
                 ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int), ("superpose", ct.c_int),
                 ("stall_window", ct.c_int), ("sweep_chain", ct.c_int), ("fuse_maps", ct.c_int),
-                ("warm_start", ct.c_int), ("accel_depth", ct.c_int), ("sweep_rhs_chain", ct.c_int)]
+                ("warm_start", ct.c_int), ("accel_depth", ct.c_int), ("sweep_rhs_chain", ct.c_int),
+                ("rhs_streams", ct.c_int)]
 
 
 class dct_stats(ct.Structure):
@@ -52,7 +53,7 @@ class dct_stats(ct.Structure):
                 ("iteration_sets", ct.c_int), ("sweep_bk", ct.c_int), ("sweep_sync", ct.c_int),
                 ("tune_ms", ct.c_double), ("sweep_launches_all", ct.c_longlong), ("sweep_chain", ct.c_int),
                 ("fused_maps", ct.c_int), ("warm_start", ct.c_int), ("fused_ms", ct.c_double),
-                ("fused_launches", ct.c_int), ("sweep_rhs_chain", ct.c_int)]
+                ("fused_launches", ct.c_int), ("sweep_rhs_chain", ct.c_int), ("rhs_streams", ct.c_int)]
 
 
 _lib = None
@@ -195,12 +196,13 @@ class SolveStats:
     fused_ms: float = 0.0
     fused_launches: int = 0
     sweep_rhs_chain: int = 1
+    rhs_streams: int = 1
 
 
 def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=None, fixup=True,
           test_inflow=None, chunk=0, use_graph=False, profile=False, keep_adjoint=False, autotune=False,
           sweep_bk=0, sweep_sync=0, superpose=1, stall_window=0, sweep_chain=0, fuse_maps=0,
-          warm_start=False, accel_depth=0, sweep_rhs_chain=0, allow_notconv=False) -> SolveStats:
+          warm_start=False, accel_depth=0, sweep_rhs_chain=0, rhs_streams=0, allow_notconv=False) -> SolveStats:
     """B = number of sources; with superpose = S > 1 the per-right-hand-side
     outputs have B // S rows."""
     o = dct_opts()
@@ -226,6 +228,7 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     o.warm_start = int(warm_start)
     o.accel_depth = int(accel_depth)
     o.sweep_rhs_chain = int(sweep_rhs_chain)
+    o.rhs_streams = int(rhs_streams)
     S = max(1, int(superpose))
     if B % S:
         raise ValueError(f"superpose={S} must divide the number of sources {B}")
@@ -242,7 +245,7 @@ def solve(h, B, G, *, precision="fp64", tol=1e-6, max_iter=1000, fixed_iters=Non
     return SolveStats(rc, iters, eps, bal, st.sweep_updates, st.sweep_launches, st.sweep_ms, st.solve_ms,
                       st.iteration_sets, st.sweep_bk, st.sweep_sync, st.tune_ms, st.sweep_launches_all,
                       st.sweep_chain, st.fused_maps, st.warm_start, st.fused_ms, st.fused_launches,
-                      st.sweep_rhs_chain)
+                      st.sweep_rhs_chain, st.rhs_streams)
 
 
 def dose(h, B, G, C, *, summed=False, want_phi=False):
