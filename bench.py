@@ -69,7 +69,8 @@ def sweep_roofline(res, C, workload):
     achieved = bytes_per_solve / launches / (avg_launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(workload, res["precision"], streams=res.get("rhs_streams", 1)),
+            "traffic": measured_traffic(workload, res["precision"], streams=res.get("rhs_streams", 1),
+                                        coupling=res.get("sweep_sync")),
             "kernel": "k_sweep", "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_solve / launches}
 
 
@@ -145,6 +146,7 @@ def timed_solves(solver, prob, precision, steps, warmup, tag, dose_dev, fixed=No
                            "chained_sources": int(stats[-1].sweep_rhs_chain),
                            "streams": int(stats[-1].rhs_streams)},
         "rhs_streams": int(stats[-1].rhs_streams),
+        "sweep_sync": int(stats[-1].sweep_sync),
         "fused_maps": bool(stats[-1].fused_maps),
         "dose": dose,
     }
@@ -489,13 +491,13 @@ SWEEP_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_sweep.hip")
 FUSED_SRC = os.path.join(ROOT, "paper_1811_12391_amd", "csrc", "k_source.hip")
 
 
-def measured_traffic(workload, precision, kernel="k_sweep", streams=1):
+def measured_traffic(workload, precision, kernel="k_sweep", streams=1, coupling=None):
     """HBM bytes per sweep launch (FETCH_SIZE + WRITE_SIZE, scaled by the
     same counters on a plain copy of known size) from the committed counter
     summary of that workload, or None when there is none for this precision,
     the kernel's source has changed since the counters were taken, or they
     were taken with launches over a different share of the right-hand sides
-    (one or two streams)."""
+    (one or two streams) or, for the sweep, another wave coupling."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
@@ -511,6 +513,8 @@ def measured_traffic(workload, precision, kernel="k_sweep", streams=1):
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if kv.get(f"{kernel}_sha256") != sha or int(kv.get("streams", "1")) != streams:
+        return None
+    if coupling is not None and "coupling" in kv and int(kv["coupling"]) != coupling:
         return None
     v = kv.get(f"bytes_per_launch_{precision}")
     return float(v) if v is not None else None

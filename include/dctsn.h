@@ -158,7 +158,10 @@ typedef struct dct_opts {
                                  on two streams, so that one half's sweep overlaps the other
                                  half's fused map kernel (the halves are independent; results
                                  are those of one stream bit for bit).  Needs the fused maps,
-                                 layered waves (coupling 4 / 5), B >= 2 and graph off;
+                                 graph off and layered waves (coupling 4 / 5, B >= 2) or
+                                 chained sources (9 / 10, B >= 4: a half's launch keeps the
+                                 ceil(B / R) chains per direction of one stream, with
+                                 ceil(B_half / ceil(B / R)) sources each, at least 2);
                                  otherwise one stream.  0 = two streams when B N >= 4 x the
                                  compute units, 1 = one stream, 2 = two streams. */
 } dct_opts;
@@ -186,7 +189,8 @@ typedef struct dct_stats {
     int warm_start;           /* 1 when the solve started from the previous solve's moments */
     double fused_ms;          /* summed device time of the timed fused-map launches (profile > 0) */
     int fused_launches;       /* fused-map launches whose time is in fused_ms */
-    int sweep_rhs_chain;      /* right-hand sides per chained sweep workgroup that ran (1 = none) */
+    int sweep_rhs_chain;      /* right-hand sides per chained sweep workgroup (1 = none); R of a
+                                 one-stream launch, also with two streams (see rhs_streams) */
     int rhs_streams;          /* streams the iteration sets ran on (1 or 2) */
 } dct_stats;
 

@@ -427,7 +427,7 @@ struct SweepArgs {
                               //      q, psi in the chain layout, sigma_t from sigch
     const void *sigch;        // T [2][G][K C] sigma_t in the chain layout of period K nx
     int b0 = 0;               // the launch covers right-hand sides b0 .. b0 + nb - 1 (layered
-    int nb = 0;               // waves only; 0: all B); B stays the stride of every [B] array
+    int nb = 0;               // waves and chained sources; 0: all B); B stays the stride of every [B] array
     int rhsK;                 // > 1: one direction of up to rhsK unfinished right-hand sides per
                               //      workgroup, swept back to back (k_sweep_rc)
 };

@@ -1048,10 +1048,11 @@ __global__ __launch_bounds__(1024 / ZL) void k_sweep_rc(SweepArgs a)
         // the chains round robin: the s-th goes to chain s mod nch, slot
         // s div nch, so every chain stays busy as sources finish
         const int nch = gridDim.x / N;
+        const int bend = a.b0 + (a.nb > 0 ? a.nb : a.B);      // this launch's right-hand sides: b0 .. bend - 1
         int before = 0;
-        for (int base = 0; base < a.B; base += 64) {
+        for (int base = a.b0; base < bend; base += 64) {
             const int b = base + l;
-            const bool act = b < a.B && !a.state[b].finished;
+            const bool act = b < bend && !a.state[b].finished;
             const unsigned long long m = __ballot(act);
             const int s = before + __popcll(m & ((1ull << l) - 1ull));
             if (act && s % nch == c && s / nch < K) slot_b[s / nch] = b;
@@ -1259,10 +1260,10 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
         grid = dim3((unsigned)(a.B * a.N), (unsigned)(hi - lo + 1));
     }
     const int mode = a.adjoint ? 2 : (a.mask ? 1 : 0);
-    // a launch over a subset of the right-hand sides: layered waves only
+    // a launch over a subset of the right-hand sides: layered waves or chained sources
     const int nb = a.nb > 0 ? a.nb : a.B;
     const bool layered = (a.layers == 2 || a.layers == 4) && !multi && mode != 2 && a.ny <= 64 && a.nz <= 16;
-    if (a.b0 < 0 || a.b0 + nb > a.B || ((a.b0 != 0 || nb != a.B) && (!layered || a.chainK > 1 || a.rhsK > 1)))
+    if (a.b0 < 0 || a.b0 + nb > a.B || ((a.b0 != 0 || nb != a.B) && (a.chainK > 1 || !(a.rhsK > 1 || layered))))
         return hipErrorInvalidValue;
     if (a.chainK > 1) {
         // chained directions: one block, forward sweep without kept fluxes,
@@ -1290,7 +1291,7 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
             return hipErrorInvalidValue;
         const int zl = a.layers == 2 ? 2 : 1;
         const int nwv = (a.nz + zl - 1) / zl;
-        const dim3 rgrid((unsigned)(a.N * ((a.B + a.rhsK - 1) / a.rhsK))), rblock(64 * nwv);
+        const dim3 rgrid((unsigned)(a.N * ((nb + a.rhsK - 1) / a.rhsK))), rblock(64 * nwv);
 #define DCT_RC(T, ZL) hipLaunchKernelGGL((k_sweep_rc<T, ZL, 8>), rgrid, rblock, 0, s, a)
         if (is_f64) {
             if (zl == 2) DCT_RC(double, 2); else DCT_RC(double, 1);

@@ -1266,17 +1266,23 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
     // and latency-bound) runs beside the other half's fused kernel (memory-
     // bound); the halves share no data, so each keeps its own order
     int nstreams = 1;
-    if (!o.use_graph && fused && (ctx->last_sync == 4 || ctx->last_sync == 5) && B >= 2 &&
+    const bool lw_cpl = ctx->last_sync == 4 || ctx->last_sync == 5;
+    const bool rc_cpl = (ctx->last_sync == 9 || ctx->last_sync == 10) && sw.rhsK > 1;
+    if (!o.use_graph && fused && ((lw_cpl && B >= 2) || (rc_cpl && B >= 4)) &&
         (o.rhs_streams == 2 || (o.rhs_streams == 0 && (long)B * N >= 4L * ctx->ncu)))
         nstreams = 2;
     ctx->last_streams = nstreams;
     const int hb = nstreams == 2 ? B / 2 : B;   // first half: right-hand sides 0 .. hb - 1
+    // chained sources on two streams: a half's launch keeps the chains per
+    // direction of a one-stream launch, ceil(B / R), with fewer sources each
+    const int rc_nch = sw.rhsK > 1 ? (B + sw.rhsK - 1) / sw.rhsK : 1;
     auto enqueue_set = [&](hipStream_t es, int b0, int nb) -> hipError_t {
         TransArgs trh = tr;
         CombArgs cbh = cb;
         SweepArgs swh = sw;
         trh.b0 = cbh.b0 = swh.b0 = b0;
         trh.nb = cbh.nb = swh.nb = nb;
+        if (swh.rhsK > 1 && nb != B) swh.rhsK = std::max(2, std::min(DCT_MAXRC, (nb + rc_nch - 1) / rc_nch));
         hipError_t e = launch_transition(trh, is64, es);
         if (e != hipSuccess) return e;
         if (fused) {
