@@ -37,14 +37,15 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, sources=None):
+def cpu_baseline(prob, sources=None, threads=None):
     """FP64 oracle on the first `sources` sources of the same workload (every
     source's solve is independent of the others, so a prefix of the sources
-    is a prefix of the whole job), all host threads it is given."""
+    is a prefix of the whole job), on `threads` host threads (default: all
+    it is given)."""
     import oracle
 
     k = prob.B if sources is None else min(sources, prob.B)
-    threads = oracle.default_threads()
+    threads = threads or oracle.default_threads()
     oracle.lib()
     t0 = time.perf_counter()
     r = oracle.solve(prob.phantom, prob.xs, prob.dirs, prob.weights, prob.L, prob.src_pos[:k], prob.src_axis[:k],
@@ -55,7 +56,7 @@ def cpu_baseline(prob, sources=None):
             "sample": (f"whole solves of the first {k} of the {prob.B} sources" if k < prob.B else
                        f"the whole solve, all {prob.B} source(s)")
                       + f" ({int(r.iters.sum())} source iterations, {dt:.1f} s wall, FP64 C oracle, "
-                        f"OpenMP over directions/voxels)"}
+                        + ("OpenMP over directions/voxels)" if threads > 1 else "one thread)")}
 
 
 def sweep_roofline(res, C, workload):
@@ -289,6 +290,10 @@ def main():
     if not args.no_cpu_baseline:
         _log("[bench] timing the FP64 CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(prob, CPU_SOURCES.get(args.workload))
+        if args.workload in CPU_SOURCES_1T:
+            # the same oracle on one core: the single-threaded form of the baseline
+            _log("[bench] timing the FP64 CPU oracle on one thread")
+            line["cpu_baseline_single_thread"] = cpu_baseline(prob, CPU_SOURCES_1T[args.workload], threads=1)
     print(json.dumps(line), flush=True)
 
 
@@ -482,6 +487,7 @@ PROFILE_EVERY = 4
 # sources of the headline workload the CPU oracle solves for its baseline
 # (about 10-20 s of host time)
 CPU_SOURCES = {"c4": 6}
+CPU_SOURCES_1T = {"c4": 1}   # about 25 s of one core
 COUPLINGS = {1: "lds_counters", 2: "barrier", 3: "pipelined_blocks", 4: "layered_waves_4", 5: "layered_waves_2",
              6: "chained_directions_1", 7: "chained_directions_2", 8: "chained_directions_4",
              9: "chained_sources_2", 10: "chained_sources_1"}

@@ -1363,6 +1363,15 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         HC(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     }
     hipStream_t hs = nullptr;   // the second half's stream
+    // on an early return (a failed call) the second stream may still run sets
+    // on the context's buffers: wait for it, so no later call overlaps them
+    struct HalfGuard {
+        hipStream_t &h;
+        ~HalfGuard()
+        {
+            if (h) (void)hipStreamSynchronize(h);
+        }
+    } half_guard{hs};
     if (nstreams == 2) {
         if (!ctx->half_stream) HC(hipStreamCreateWithFlags(&ctx->half_stream, hipStreamNonBlocking));
         for (hipEvent_t &e : ctx->ev_half)
@@ -1410,6 +1419,7 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         HC(hipMemcpyAsync(&ctx->h_unf[kpoll & 1], d_unf, 4, hipMemcpyDeviceToHost, ls));
         HC(hipEventRecord(ctx->ev_poll[kpoll & 1], ls));
         ++kpoll;
+        hs = nullptr;   // joined
     }
     if (ls != s) HC(hipStreamWaitEvent(s, ctx->ev_poll[(kpoll - 1) & 1], 0));
     HC(hipEventSynchronize(ctx->ev_poll[(kpoll - 1) & 1]));
