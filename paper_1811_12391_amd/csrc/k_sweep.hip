@@ -1304,7 +1304,11 @@ hipError_t launch_sweep(SweepArgs a, int is_f64, hipStream_t s, unsigned seq)
     if (layered) {
         const int nwv = (a.nz + a.layers - 1) / a.layers;
         const dim3 lgrid((unsigned)(nb * a.N)), lblock(64 * nwv);
-#define DCT_LW(T, ZL, MD) hipLaunchKernelGGL((k_sweep_lw<T, ZL, (ZL == 4 ? 4 : 8), MD>), lgrid, lblock, 0, s, a)
+        // operands prefetched 4 steps ahead: at 2 layers per wave that holds 69
+        // VGPRs instead of 110 with 8 steps, so three workgroups fit a CU instead
+        // of two, and the sweep of the 36-source scan runs 4% faster (332 against
+        // 346 us); 2 steps (49 VGPRs) and 6 (89) were slower
+#define DCT_LW(T, ZL, MD) hipLaunchKernelGGL((k_sweep_lw<T, ZL, 4, MD>), lgrid, lblock, 0, s, a)
         if (is_f64) {
             if (a.layers == 4) { if (mode == 1) DCT_LW(double, 4, 1); else DCT_LW(double, 4, 0); }
             else { if (mode == 1) DCT_LW(double, 2, 1); else DCT_LW(double, 2, 0); }
