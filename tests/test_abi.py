@@ -98,6 +98,10 @@ def test_validation_codes(host_ctx):
     rc = lib.dct_dose(h, out.ctypes.data_as(ct.POINTER(ct.c_double)), 1, None, None)
     assert rc == dctsn.DCT_ESTATE
     assert "no valid solve" in dctsn.last_error(h)
+    # device-buffer forms: a NULL density is rejected before any device call,
+    # the adjoint needs a kept solve
+    assert lib.dct_set_density_dev(h, None) == dctsn.DCT_EINVAL
+    assert lib.dct_adjoint_dev(h, None, None, None, None, None, None) == dctsn.DCT_ESTATE
 
 
 def test_null_context():
