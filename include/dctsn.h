@@ -194,6 +194,15 @@ typedef struct dct_stats {
     int rhs_streams;          /* streams the iteration sets ran on (1 or 2) */
 } dct_stats;
 
+/* Environment read by the library:
+ *   DCT_LOG = 0..3      messages to stderr: 1 schedule choices and tuning
+ *                       results, 2 also one line per solve, 3 also every
+ *                       tuning candidate (read once per process);
+ *   DCT_TUNE_CACHE = p  text file of tuned sweep schedules: every tuning
+ *                       result is appended to it, and dct_create loads the
+ *                       entries made on a device of the same architecture and
+ *                       compute-unit count (the last entry of a shape wins). */
+
 /* Create a context on HIP device `device` using `stream` (a hipStream_t; NULL
  * means the device's default stream).  device = -1 creates a host-only
  * context that validates inputs but cannot solve (DCT_EDEVICE from solve). */

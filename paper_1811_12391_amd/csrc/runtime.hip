@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -43,6 +45,34 @@ static __device__ __align__(256) unsigned char scratch[DCT_NOALLOC_ZOFF + 256];
 namespace {
 
 thread_local std::string g_create_error;
+
+// DCT_LOG = 0..3: messages up to that level go to stderr (1: schedule choices
+// and tuning results, 2: one line per solve, 3: every tuning candidate)
+int log_level()
+{
+    static const int lv = [] {
+        const char *e = std::getenv("DCT_LOG");
+        return e ? std::atoi(e) : 0;
+    }();
+    return lv;
+}
+
+__attribute__((format(printf, 2, 3))) void dlog(int level, const char *fmt, ...)
+{
+    if (log_level() < level) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[dctsn] %s\n", buf);
+}
+
+// Persisted sweep schedules: with DCT_TUNE_CACHE = path, every tuning result
+// is appended to that text file as one line, and a new context on a device of
+// the same architecture and compute-unit count starts from the file's entries
+// (the last entry of a shape wins), so a new process need not tune again.
+constexpr const char *kTuneTag = "dctsn-tune-1";
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -127,6 +157,7 @@ struct dct_ctx {
     } warm = {false, 0, 0, 0, 0, 0, nullptr};
     size_t lds_max = 65536;            // LDS bytes one workgroup may allocate on the device
     int ncu = 256;                     // compute units of the device
+    std::string arch;                  // the device's architecture name (tune-cache key)
     bool pipe_clean = false;           // pipelined-block face buffers hold only the empty marker
     unsigned sweep_seq = 0;            // counts sweep launches (part of the pipelined blocks' launch tag)
     hipStream_t own_stream = nullptr;  // capture stream when the context's stream is the null stream
@@ -179,6 +210,45 @@ static bool finite_all(const double *p, size_t n)
     return true;
 }
 
+static void tune_cache_load(dct_ctx *ctx)
+{
+    const char *path = std::getenv("DCT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512], tag[32], arch[128];
+    int n = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        dct_ctx::Tuned t;
+        int ncu = 0;
+        if (std::sscanf(line, "%31s %127s %d %d %d %d %d %d %d %d %d %d %d %d", tag, arch, &ncu, &t.nx, &t.ny, &t.nz,
+                        &t.N, &t.B, &t.prec, &t.keep, &t.bk, &t.sync, &t.chain, &t.rhs) != 14)
+            continue;
+        if (std::strcmp(tag, kTuneTag) != 0 || ctx->arch != arch || ncu != ctx->ncu) continue;
+        ctx->tuned.push_back(t);
+        ++n;
+    }
+    std::fclose(f);
+    dlog(1, "tune cache %s: %d schedule(s) for %s with %d CUs", path, n, ctx->arch.c_str(), ctx->ncu);
+}
+
+static void tune_cache_save(const dct_ctx *ctx, const dct_ctx::Tuned &t)
+{
+    const char *path = std::getenv("DCT_TUNE_CACHE");
+    if (!path || !*path) return;
+    char line[512];
+    const int len = std::snprintf(line, sizeof(line), "%s %s %d %d %d %d %d %d %d %d %d %d %d %d\n", kTuneTag,
+                                  ctx->arch.c_str(), ctx->ncu, t.nx, t.ny, t.nz, t.N, t.B, t.prec, t.keep, t.bk,
+                                  t.sync, t.chain, t.rhs);
+    FILE *f = std::fopen(path, "a");
+    if (!f) {
+        dlog(1, "tune cache %s: cannot append", path);
+        return;
+    }
+    std::fwrite(line, 1, (size_t)len, f);   // one write per line, so appending processes do not interleave
+    std::fclose(f);
+}
+
 static void invalidate(dct_ctx *ctx)
 {
     ctx->solved = false;
@@ -222,6 +292,14 @@ int dct_create(dct_ctx **out, int device, void *stream)
             int ncu = 0;
             if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
                 ctx->ncu = ncu;
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+                ctx->arch = prop.gcnArchName;
+                // the name's feature suffix (":sramecc+:xnack-") is not part of the key
+                ctx->arch = ctx->arch.substr(0, ctx->arch.find(':'));
+            }
+            if (ctx->arch.empty()) ctx->arch = "unknown";
+            tune_cache_load(ctx);
         }
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[0]);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_poll[1]);
@@ -1192,6 +1270,8 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                     }
                     float ms = 0.0f;
                     HC(hipEventElapsedTime(&ms, ctx->evpool[0], ctx->evpool[1]));
+                    dlog(3, "tuning candidate: z layers %d, coupling %d, chained directions %d, chained sources %d: "
+                            "%.3f ms per sweep", cand.bk, cand.cpl, cand.K, cand.R, ms / 3.0);
                     tune_ms += ms * 4.0 / 3.0;
                     if (ms < best) {
                         best = ms;
@@ -1203,6 +1283,10 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
                 }
                 if (best == 1e30f) return fail(ctx, DCT_EDEVICE, "solve: no sweep schedule completed during tuning");
                 ctx->tuned.push_back({nx, ny, nz, N, B, o.precision, (int)keep, bk, cpl, chainK, rhsK});
+                tune_cache_save(ctx, ctx->tuned.back());
+                dlog(1, "tuned %dx%dx%d N=%d B=%d precision %d: z layers %d, coupling %d, chained directions %d, "
+                        "chained sources %d (%.2f ms per sweep)", nx, ny, nz, N, B, o.precision, bk, cpl, chainK, rhsK,
+                     best / 3.0);
             }
         }
         apply_blocks(bk);
@@ -1272,6 +1356,9 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         (o.rhs_streams == 2 || (o.rhs_streams == 0 && (long)B * N >= 4L * ctx->ncu)))
         nstreams = 2;
     ctx->last_streams = nstreams;
+    dlog(2, "solve %dx%dx%d N=%d B=%d G=%d precision %d: z layers %d, coupling %d, chained directions %d, "
+            "chained sources %d, fused maps %d, streams %d", nx, ny, nz, N, B, G, o.precision, pl.BK, ctx->last_sync,
+         ctx->last_chain, ctx->last_rhs, (int)fused, nstreams);
     const int hb = nstreams == 2 ? B / 2 : B;   // first half: right-hand sides 0 .. hb - 1
     // chained sources on two streams: a half's launch keeps the chains per
     // direction of a one-stream launch, ceil(B / R), with fewer sources each
@@ -1498,6 +1585,14 @@ extern "C" int dct_solve(dct_ctx *ctx, const dct_opts *opts, dct_stats *stats)
         stats->fused_maps = ctx->last_fused ? 1 : 0;
         stats->warm_start = ctx->last_warm ? 1 : 0;
         stats->tune_ms = tune_ms;
+    }
+    if (log_level() >= 2) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1);
+        long its = 0;
+        for (int v : iters) its += v;
+        dlog(2, "solve done: %ld iteration sets, %ld source iterations, %.2f ms on the device, unfinished %d, "
+                "non-finite %d, not converged %d", sets, its, ms, unfinished, (int)any_nan, (int)any_nc);
     }
     ctx->solved = true;
     ctx->warm = {!any_nan, B, G, Nm, C, o.precision, d_phi};

@@ -213,6 +213,26 @@ def test_status_codes_on_gpu():
         s.close()
 
 
+def test_enumeric_on_overflow():
+    """Group weights near the FP64 maximum overflow the FP32 sources: the
+    FP64 convergence reduction sees a non-finite value, the source stops and
+    the solve reports DCT_ENUMERIC (forced from the host, no kernel faults)."""
+    prob = I.make_problem("tiny")
+    s = dctsn.Solver(prob)
+    try:
+        gw = np.asarray(prob.group_w, dtype=np.float64)
+        dctsn.set_source(s.h, 1, prob.src_pos, prob.src_axis, prob.fan_deg, prob.cone_deg, gw / gw.max() * 1e308)
+        with pytest.raises(dctsn.DctError) as e:
+            s.solve(precision="fp32", tol=1e-6)
+        assert e.value.code == dctsn.DCT_ENUMERIC
+        # the same context solves again once the weights are sane
+        dctsn.set_source(s.h, 1, prob.src_pos, prob.src_axis, prob.fan_deg, prob.cone_deg, gw)
+        st = s.solve(precision="fp32", tol=1e-6)
+        assert st.status == dctsn.DCT_OK and np.all(np.isfinite(s.dose()))
+    finally:
+        s.close()
+
+
 # ------------------------------------------------------------------ full size (config 2)
 @pytest.fixture(scope="module")
 def c2_ref():
